@@ -1,0 +1,84 @@
+/* Plain CPU oracle of the scan-resolved powder-bed-fusion thermal model.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously correct reference that
+ * the GPU library is checked against.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product never does.  It
+ * shares no code, header or table with the GPU library.
+ *
+ * Everything is IEEE double precision, evaluated cell by cell with full
+ * (p+1)^3 x (p+1)^3 shape-function tables (no sum factorization, no fusion).
+ */
+#ifndef PBF_ORACLE_H
+#define PBF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    /* uniform box of nx*ny*nz Lagrange Q_degree hexahedra on [0,Lx]x[0,Ly]x[0,Lz] */
+    int degree, nx, ny, nz;
+    double Lx, Ly, Lz;
+    unsigned dirichlet_mask; /* bit f set: face f (x-,x+,y-,y+,z-,z+) is Dirichlet */
+    double T_D;
+    /* material: piecewise-linear k(T), cp(T) on shared breakpoints */
+    int n_bp;
+    const double *T_bp, *k_bp, *cp_bp;
+    double rho, T_s, T_l, latent, powder_k_factor, powder_depth;
+    /* laser: kind -1 off, 0 Gaussian surface flux on z=Lz, 1 cylindrical volume source */
+    int laser_kind;
+    double radius, absorptivity, h_powder, t_start;
+    int n_tracks;
+    const double *tracks; /* n_tracks x 8: x0 y0 z0 x1 y1 z1 speed power */
+    const double *track_power; /* optional override of the nominal powers (n_tracks) */
+} or_problem;
+
+/* reference element ------------------------------------------------------- */
+int or_gauss_legendre(int n, double *x, double *w);
+double or_lagrange(int p, int a, double x);
+double or_lagrange_deriv(int p, int a, double x);
+
+/* material law -------------------------------------------------------------- */
+double or_liquid_fraction(const or_problem *P, double T);
+double or_piecewise_linear(int n, const double *b, const double *v, double T);
+double or_conductivity(const or_problem *P, double T, double rc);
+double or_capacity(const or_problem *P, double T);
+
+/* laser ----------------------------------------------------------------------- */
+int or_beam(const or_problem *P, double t, double *xb, double *yb, double *W, int *track);
+double or_volume_source(const or_problem *P, double x, double y, double z, double t);
+double or_surface_source(const or_problem *P, double x, double y, double t);
+
+/* mesh bookkeeping ------------------------------------------------------------ */
+int64_t or_n_dofs(const or_problem *P);
+int64_t or_n_qp(const or_problem *P);
+int or_is_dirichlet(const or_problem *P, int64_t node);
+void or_init_history(const or_problem *P, double *rc);
+
+/* explicit scheme -------------------------------------------------------------- */
+int or_assemble(const or_problem *P, const double *T, double *rc, double t,
+                double *f, double *C, double *fvol);
+int or_assemble_lagged(const or_problem *P, const double *T, const double *rc, double t,
+                       double *f, double *C, double *fvol);
+int or_explicit_steps(const or_problem *P, double *T, double *rc, double t0, double dt, int n);
+int or_explicit_step_sampled(const or_problem *P, const double *T, const double *rc, double t,
+                             double dt, int n_nodes, const int64_t *nodes, double *T_new);
+double or_stability_lambda(const or_problem *P, const double *v0, int iters);
+
+/* implicit scheme ---------------------------------------------------------------- */
+int or_capacity_apply(const or_problem *P, const double *Tn, const double *x, double *y);
+int or_implicit_step(const or_problem *P, const double *Tn, double *rc, double t, double dt,
+                     double cg_rtol, int cg_max_it, double picard_tol, int picard_max_it,
+                     double *T_out, int *cg_iters_total, int *picard_iters, double *final_rel_res);
+
+/* probes and the adjoint -------------------------------------------------------- */
+int or_probe(const or_problem *P, const double *T, int n, const double *pts, double *vals);
+int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, int n_steps,
+                   int n_probes, const double *pts, const double *targets,
+                   double *J, double *dJ_dW, double *T_final);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

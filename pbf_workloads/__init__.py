@@ -1,0 +1,208 @@
+"""Seeded synthetic inputs for the powder-bed-fusion thermal step.
+
+This module only *describes* problems: box meshes, material tables, laser paths,
+probe points and targets, all drawn from fixed seeds.  It contains none of the
+method's arithmetic (no shape functions, no quadrature, no material law, no time
+step rule), so that both the CPU oracle and the GPU library can be driven from
+the same numbers without sharing any computation.
+
+Workload shapes follow the paper's setting: a box of metal with a Dirichlet
+base (heat equation with Dirichlet bottom, insulated elsewhere), a Gaussian beam
+of radius 50 um scanning tracks on the top surface, a powder layer on top
+(phase-dependent conductivity, consolidated fraction history), and
+piecewise-linear temperature-dependent conductivity and heat capacity with an
+apparent-capacity latent-heat bump between solidus and liquidus.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# face bits of the box boundary: x-, x+, y-, y+, z-, z+
+FACE_XM, FACE_XP, FACE_YM, FACE_YP, FACE_ZM, FACE_ZP = 1, 2, 4, 8, 16, 32
+ALL_FACES = 63
+
+LASER_OFF, LASER_SURFACE, LASER_VOLUME = -1, 0, 1
+
+
+@dataclass
+class Problem:
+    name: str
+    degree: int
+    nx: int
+    ny: int
+    nz: int
+    L: tuple
+    dirichlet_mask: int
+    T_D: float
+    T0: float
+    T_bp: np.ndarray
+    k_bp: np.ndarray
+    cp_bp: np.ndarray
+    rho: float
+    T_s: float
+    T_l: float
+    latent: float
+    powder_k_factor: float
+    powder_depth: float
+    laser_kind: int
+    radius: float
+    absorptivity: float
+    h_powder: float
+    t_start: float
+    tracks: np.ndarray  # (n_tracks, 8): x0 y0 z0 x1 y1 z1 speed power
+    steps: int = 0
+    dt_factor: float = 0.5  # fraction of the explicit stability limit
+    seed: int = 0
+    probes: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    targets: np.ndarray = field(default_factory=lambda: np.zeros(0))
+
+    # --- counting helpers (mesh bookkeeping only) ---
+    @property
+    def nodes_per_dim(self):
+        p = self.degree
+        return (p * self.nx + 1, p * self.ny + 1, p * self.nz + 1)
+
+    @property
+    def n_dofs(self) -> int:
+        a, b, c = self.nodes_per_dim
+        return a * b * c
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_qp_per_cell(self) -> int:
+        return (self.degree + 1) ** 3
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+def _material_tables(seed: int):
+    """8 breakpoints: 293 K, 3000 K and 6 sorted interior points; k in [15,35] W/mK,
+    cp in [450,750] J/kgK, all drawn uniformly from one seed."""
+    rng = np.random.default_rng(seed)
+    interior = np.sort(rng.uniform(293.0, 3000.0, size=6))
+    T_bp = np.concatenate([[293.0], interior, [3000.0]])
+    k_bp = rng.uniform(15.0, 35.0, size=8)
+    cp_bp = rng.uniform(450.0, 750.0, size=8)
+    return T_bp, k_bp, cp_bp
+
+
+def zigzag(seed: int, centre, z_top: float, n_tracks=10, length=1.0e-3, hatch=100e-6,
+           speed=0.8, power=200.0) -> np.ndarray:
+    """Serpentine scan: n_tracks tracks along +-x of the given length, hatch spacing
+    in y, centred on `centre`; the start corner comes from the seed; turnarounds are
+    instantaneous (the next track starts where the last one ended, one hatch over)."""
+    rng = np.random.default_rng(seed + 7)
+    sx = 1.0 if rng.integers(0, 2) == 0 else -1.0   # first track direction
+    sy = 1.0 if rng.integers(0, 2) == 0 else -1.0   # hatch direction
+    cx, cy = centre
+    tr = np.zeros((n_tracks, 8))
+    for j in range(n_tracks):
+        y = cy + sy * (j - 0.5 * (n_tracks - 1)) * hatch
+        d = sx if j % 2 == 0 else -sx
+        x0 = cx - d * 0.5 * length
+        x1 = cx + d * 0.5 * length
+        tr[j] = [x0, y, z_top, x1, y, z_top, speed, power]
+    return tr
+
+
+def _base_nonlinear(name, seed, nx, ny, nz, L, steps, track_length=1.0e-3, n_tracks=10,
+                    hatch=100e-6):
+    T_bp, k_bp, cp_bp = _material_tables(seed)
+    tracks = zigzag(seed, (0.5 * L[0], 0.5 * L[1]), L[2], n_tracks=n_tracks,
+                    length=track_length, hatch=hatch)
+    return Problem(
+        name=name, degree=2, nx=nx, ny=ny, nz=nz, L=tuple(L),
+        dirichlet_mask=FACE_ZM, T_D=293.0, T0=293.0,
+        T_bp=T_bp, k_bp=k_bp, cp_bp=cp_bp,
+        rho=7900.0, T_s=1563.0, T_l=1623.0, latent=2.7e5,
+        powder_k_factor=0.01, powder_depth=40e-6,
+        laser_kind=LASER_VOLUME, radius=50e-6, absorptivity=0.35, h_powder=40e-6,
+        t_start=0.0, tracks=tracks, steps=steps, dt_factor=0.5, seed=seed)
+
+
+def cfg1() -> Problem:
+    """Q1 16x16x8 box of 1x1x0.5 mm, constant k=20, rho=7900, cp=500, Dirichlet
+    293 K at the bottom, Gaussian *surface* flux P=200 W, A=0.35, R=50 um, moving
+    +x at 0.8 m/s from (0, 0.5 mm); 200 steps at half the stability limit."""
+    tracks = np.array([[0.0, 0.5e-3, 0.5e-3, 1.0e-3, 0.5e-3, 0.5e-3, 0.8, 200.0]])
+    return Problem(
+        name="cfg1_q1_16x16x8", degree=1, nx=16, ny=16, nz=8, L=(1e-3, 1e-3, 0.5e-3),
+        dirichlet_mask=FACE_ZM, T_D=293.0, T0=293.0,
+        T_bp=np.array([293.0, 3000.0]), k_bp=np.array([20.0, 20.0]),
+        cp_bp=np.array([500.0, 500.0]),
+        rho=7900.0, T_s=1563.0, T_l=1623.0, latent=0.0,
+        powder_k_factor=1.0, powder_depth=0.0,
+        laser_kind=LASER_SURFACE, radius=50e-6, absorptivity=0.35, h_powder=40e-6,
+        t_start=0.0, tracks=tracks, steps=200, dt_factor=0.5, seed=0)
+
+
+def cfg2() -> Problem:
+    """Q2 128x128x64 box of 4x4x2 mm (8,520,321 DoFs), seeded nonlinear law,
+    powder in the top 40 um, zigzag of 10 tracks, 5000 explicit steps."""
+    return _base_nonlinear("cfg2_q2_128x128x64", 2302, 128, 128, 64, (4e-3, 4e-3, 2e-3), 5000)
+
+
+def cfg4() -> Problem:
+    """cfg2's law and scan on the same box at 160x160x80 Q2 (16,589,601 DoFs)."""
+    return _base_nonlinear("cfg4_q2_160x160x80", 2302, 160, 160, 80, (4e-3, 4e-3, 2e-3), 5000)
+
+
+def cfg5() -> Problem:
+    """Q2 48x48x24 box of 1.5x1.5x0.75 mm (461,041 DoFs), cfg2's law, zigzag of 10
+    tracks of 0.6 mm so that the whole path is scanned within 3000 steps; 64 probes
+    seeded on the top face over the scanned area, targets seeded in [T0, 2000 K]."""
+    p = _base_nonlinear("cfg5_q2_48x48x24", 2302, 48, 48, 24, (1.5e-3, 1.5e-3, 0.75e-3), 3000,
+                        track_length=0.6e-3)
+    return with_probes(p, 64, seed=2305)
+
+
+def with_probes(p: Problem, n: int, seed: int, t_lo=None, t_hi=2000.0) -> Problem:
+    rng = np.random.default_rng(seed)
+    tr = p.tracks
+    xlo, xhi = tr[:, [0, 3]].min(), tr[:, [0, 3]].max()
+    ylo, yhi = tr[:, [1, 4]].min(), tr[:, [1, 4]].max()
+    pts = np.zeros((n, 3))
+    pts[:, 0] = rng.uniform(xlo, xhi, n)
+    pts[:, 1] = rng.uniform(ylo, yhi, n)
+    pts[:, 2] = p.L[2]
+    lo = p.T0 if t_lo is None else t_lo
+    targets = rng.uniform(lo, t_hi, n)
+    return p.replace(probes=pts, targets=targets)
+
+
+def small_nonlinear(nx=20, ny=18, nz=10, steps=200, seed=2302, h=31.25e-6, track_length=None,
+                    n_tracks=4, hatch=100e-6) -> Problem:
+    """cfg2's physics at a size the oracle runs in seconds; the cell counts are chosen
+    so that they are not multiples of the GPU tile and leave ragged tails."""
+    L = (nx * h, ny * h, nz * h)
+    if track_length is None:
+        track_length = 0.6 * L[0]
+    return _base_nonlinear(f"small_q2_{nx}x{ny}x{nz}", seed, nx, ny, nz, L, steps,
+                           track_length=track_length, n_tracks=n_tracks, hatch=hatch)
+
+
+def sine_mode(degree: int, n: int, k=20.0, rho=7900.0, cp=500.0) -> Problem:
+    """Unit cube, all faces Dirichlet, constant coefficients, laser off: the setting of
+    the decaying eigenmode T = T_D + A sin(pi x) sin(pi y) sin(pi z)."""
+    return Problem(
+        name=f"sine_q{degree}_{n}", degree=degree, nx=n, ny=n, nz=n, L=(1.0, 1.0, 1.0),
+        dirichlet_mask=ALL_FACES, T_D=293.0, T0=293.0,
+        T_bp=np.array([0.0, 1.0e9]), k_bp=np.array([k, k]), cp_bp=np.array([cp, cp]),
+        rho=rho, T_s=1.0e8, T_l=2.0e8, latent=0.0, powder_k_factor=1.0, powder_depth=0.0,
+        laser_kind=LASER_OFF, radius=50e-6, absorptivity=0.35, h_powder=40e-6,
+        t_start=0.0, tracks=np.zeros((0, 8)), steps=0, dt_factor=0.5, seed=0)
+
+
+def seeded_vector(n: int, seed: int) -> np.ndarray:
+    """Uniform(-1, 1) numbers: start vectors for power iterations and random fields."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)
+
+
+CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg4": cfg4, "cfg5": cfg5}
