@@ -27,8 +27,11 @@
  *  - the consolidated fraction is updated before use: r^n = max(r^{n-1}, g(T^n));
  *  - only k depends on the phase; k_m = k_s = k(T), k_p = powder factor * k(T);
  *  - apparent capacity c = c_p(T) + L/(T_l - T_s) on T_s <= T <= T_l;
- *  - with c = c(T) the lumped capacity is the row sum of the consistent
- *    capacity matrix at T_n, recomputed every step;
+ *  - lumped capacity C~_i = rho c(T_i) M~_i with M~ the row-sum lumped mass
+ *    matrix (M~_ii = sum_j M_ij, M_ij = int N_i N_j): equal to the row sum of
+ *    the consistent capacity matrix when c is constant, and positive also for
+ *    Q2 elements with a temperature-dependent c (the row sum of the consistent
+ *    C(T) is not: Q2 shape functions are negative at some Gauss points);
  *  - the source is evaluated at t_n; track k is active on [t_k, t_{k+1});
  *  - Dirichlet nodes are set to T_D after every step (strong, nodal).
  */
@@ -338,8 +341,8 @@ void or_init_history(const or_problem *P, double *rc)
 enum { HIST_UPDATE = 0, HIST_PEEK = 1, HIST_LAGGED = 2 };
 
 /* Contributions of one cell to f (diffusion + volume source + surface flux), to
- * the lumped capacity C and to the volume-source part fvol.  rc holds the cell's
- * history values.  HIST_UPDATE: r = max(r, g(T_q)) is stored and used (explicit
+ * the row sums of the unit mass matrix (ce) and to the volume-source part fvol.
+ * rc holds the cell's history values.  HIST_UPDATE: r = max(r, g(T_q)) is stored and used (explicit
  * step); HIST_PEEK: the same value is used but not stored; HIST_LAGGED: the
  * stored r is used as it is (implicit step, history lagged at the step start). */
 static void cell_eval(const or_problem *P, const ref_elem *R, int cx, int cy, int cz,
@@ -366,7 +369,6 @@ static void cell_eval(const or_problem *P, const ref_elem *R, int cx, int cy, in
         double rn = (hist == HIST_LAGGED) ? r : ((g > r) ? g : r);
         if (hist == HIST_UPDATE) rc_cell[q] = rn;
         double k = or_conductivity(P, Tq, rn);
-        double c = or_capacity(P, Tq);
         double xq = (cx + R->xi[q][0]) * h[0], yq = (cy + R->xi[q][1]) * h[1],
                zq = (cz + R->xi[q][2]) * h[2];
         double src = or_volume_source(P, xq, yq, zq, t);
@@ -376,7 +378,7 @@ static void cell_eval(const or_problem *P, const ref_elem *R, int cx, int cy, in
             for (int d = 0; d < 3; ++d) gradN_dot_gradT += R->dN[a][q][d] / h[d] * gq[d];
             fe[a] += W * (-k * gradN_dot_gradT + R->N[a][q] * src);
             fv[a] += W * R->N[a][q] * src;
-            ce[a] += W * P->rho * c * R->N[a][q];
+            ce[a] += W * R->N[a][q];
         }
     }
     /* Gaussian surface flux on the top face z = Lz (Neumann input) */
@@ -399,8 +401,9 @@ static void cell_eval(const or_problem *P, const ref_elem *R, int cx, int cy, in
     }
 }
 
-/* eq. vector_evaluation: f = sum_e G_e^T f_e, and the lumped capacity
- * C~_ii = sum_j C_ij assembled the same way.  rc is updated in place. */
+/* eq. vector_evaluation: f = sum_e G_e^T f_e; the lumped capacity is
+ * C~_i = rho c(T_i) M~_i with M~_i = sum_j M_ij assembled the same way.  rc is
+ * updated in place. */
 static int assemble_mode(const or_problem *P, const double *T, double *rc, double t, double *f,
                          double *C, double *fvol, int hist);
 
@@ -439,6 +442,7 @@ static int assemble_mode(const or_problem *P, const double *T, double *rc, doubl
                     if (fvol) fvol[g] += fv[a];
                 }
             }
+    for (int64_t i = 0; i < N; ++i) C[i] *= P->rho * or_capacity(P, T[i]);
     free(R);
     return 0;
 }
@@ -490,7 +494,7 @@ int or_explicit_step_sampled(const or_problem *P, const double *T, const double 
                 }
             }
         }
-        T_new[s] = T[g] + dt * fsum / csum;
+        T_new[s] = T[g] + dt * fsum / (P->rho * or_capacity(P, T[g]) * csum);
     }
     free(R);
     return 0;
@@ -769,7 +773,8 @@ int or_probe(const or_problem *P, const double *T, int n, const double *pts, dou
  * with one-sided derivatives: g' = 1/(T_l-T_s) on the open interval, the
  * breakpoint slope of the segment the forward evaluation picked, no derivative of
  * the latent-heat indicator, and the max passing its adjoint to T when
- * g(T_q) > r^{n-1} (to r^{n-1} otherwise, ties included). */
+ * g(T_q) > r^{n-1} (to r^{n-1} otherwise, ties included).  The lumped capacity
+ * depends on the nodal temperature only: dC~_i/dT_i = rho c'(T_i) M~_i. */
 int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, int n_steps,
                    int n_probes, const double *pts, const double *targets, double *J,
                    double *dJ_dW, double *T_final)
@@ -796,7 +801,7 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
     /* objective and its gradient with respect to T_N */
     double *lam = (double *)calloc(N, sizeof(double)), *lam_new = (double *)calloc(N, sizeof(double));
     double *mu = (double *)calloc(nq, sizeof(double));
-    double *a = (double *)malloc(sizeof(double) * N), *b = (double *)malloc(sizeof(double) * N);
+    double *a = (double *)malloc(sizeof(double) * N);
     int nn = R->nn;
     double Jv = 0.0;
     for (int s = 0; s < n_probes; ++s) {
@@ -825,12 +830,13 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
         for (int64_t i = 0; i < N; ++i) {
             if (or_is_dirichlet(P, i)) {
                 a[i] = 0.0;
-                b[i] = 0.0;
                 lam_new[i] = 0.0;
             } else {
-                a[i] = dt * lam[i] / C[i];               /* adjoint of f_i */
-                b[i] = -dt * lam[i] * f[i] / (C[i] * C[i]); /* adjoint of C~_i */
-                lam_new[i] = lam[i];                     /* identity part */
+                a[i] = dt * lam[i] / C[i]; /* adjoint of f_i */
+                /* identity part, plus the nodal capacity C~_i = rho c(T_i) M~_i:
+                 * d(dt f_i / C~_i)/dC~_i * dC~_i/dT_i */
+                double dC_dT = C[i] / or_capacity(P, Tn[i]) * capacity_dT(P, Tn[i]);
+                lam_new[i] = lam[i] - dt * lam[i] * f[i] / (C[i] * C[i]) * dC_dT;
             }
         }
         double xb, yb, Wb;
@@ -843,12 +849,11 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
                     int64_t gn[MAXNN];
                     for (int aa = 0; aa < nn; ++aa) gn[aa] = cell_node(P, cx, cy, cz, aa);
                     for (int q = 0; q < R->nq; ++q) {
-                        double Tq = 0.0, gT[3] = {0, 0, 0}, aq = 0.0, ga[3] = {0, 0, 0}, bq = 0.0;
+                        double Tq = 0.0, gT[3] = {0, 0, 0}, aq = 0.0, ga[3] = {0, 0, 0};
                         for (int bb = 0; bb < nn; ++bb) {
                             double Nb = R->N[bb][q];
                             Tq += Nb * Tn[gn[bb]];
                             aq += Nb * a[gn[bb]];
-                            bq += Nb * b[gn[bb]];
                             for (int d = 0; d < 3; ++d) {
                                 gT[d] += R->dN[bb][q][d] / h[d] * Tn[gn[bb]];
                                 ga[d] += R->dN[bb][q][d] / h[d] * a[gn[bb]];
@@ -864,9 +869,7 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
                         double ga_gT = ga[0] * gT[0] + ga[1] * gT[1] + ga[2] * gT[2];
                         /* adjoint of k from f_diff = -W k grad N . grad T */
                         double kbar = -W * ga_gT;
-                        /* adjoint of c from C~ = W rho c N */
-                        double cbar = W * P->rho * bq;
-                        double Tbar = kbar * conductivity_dT(P, Tq, rn) + cbar * capacity_dT(P, Tq);
+                        double Tbar = kbar * conductivity_dT(P, Tq, rn);
                         double rbar = kbar * conductivity_drc(P, Tq) + mu[qi];
                         if (took_g) {
                             Tbar += rbar * liquid_fraction_dT(P, Tq);
@@ -908,7 +911,7 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
         lam = lam_new;
         lam_new = tmp;
     }
-    free(Ts); free(Rs); free(f); free(C); free(lam); free(lam_new); free(mu); free(a); free(b);
+    free(Ts); free(Rs); free(f); free(C); free(lam); free(lam_new); free(mu); free(a);
     free(R);
     return 0;
 }
