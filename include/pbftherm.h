@@ -1,0 +1,162 @@
+/* pbftherm: matrix-free thermal model of laser powder-bed fusion on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library evaluates the nonlinear heat-equation operator of a scan-resolved
+ * powder-bed-fusion model with sum factorization on uniform boxes of Lagrange
+ * Q1/Q2 hexahedra, and drives it with lumped-mass forward-Euler steps, a
+ * backward-Euler step solved by matrix-free Jacobi-preconditioned CG, a
+ * stability estimate, probes and a discrete adjoint step.  The mathematics is
+ * that of Proell et al., "A highly efficient computational approach for
+ * part-scale thermal modeling of metal powder bed fusion" (arXiv 2302.05164):
+ * the model of Section 2, the discretization and time stepping of Section 3,
+ * and the element-level operator evaluation of Section 4.2.
+ *
+ * Conventions shared by every call:
+ *  - Status: every call returns PBF_OK (0) or a negative PBF_E* code and then
+ *    leaves a message in pbf_last_error(ctx).  No call aborts the process.
+ *  - Memory: the context owns host-side descriptions only (mesh sizes, material,
+ *    laser path), copied in by the set-up calls.  All device memory is owned by
+ *    the caller: one workspace bound with pbf_bind_device, plus the state arrays
+ *    passed to each call.  The library never allocates or frees device memory
+ *    and keeps no device pointer across calls except the workspace.
+ *  - Streams: device calls take the caller's hipStream_t as `void *stream` and
+ *    enqueue their kernels on it.  Calls documented as "synchronizes" wait for
+ *    the stream before returning because they return host scalars; every other
+ *    device call is asynchronous.
+ *  - Layout: nodal vectors (length n_dofs, double) use lexicographic numbering
+ *    with x fastest, node (i,j,k) at i + NX*(j + NY*k), NX = degree*nx + 1, ...
+ *    The history vector (length n_hist_qp, double) stores the consolidated
+ *    fraction of the quadrature points of the top n_hist_layers cell layers (the
+ *    only cells that hold powder initially); all other points are consolidated
+ *    and carry no storage.  Its order is point-major: index
+ *    q*n_hist_cells + c, q = qx + (p+1)*(qy + (p+1)*qz) the tensor Gauss point,
+ *    c = cx + nx*(cy + ny*(cz - (nz - n_hist_layers))) the cell.
+ *  - Units: SI (m, s, K, W, J).
+ *  - Contexts are not thread-safe; distinct contexts are independent.
+ */
+#ifndef PBFTHERM_H
+#define PBFTHERM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbf_ctx pbf_ctx;
+typedef int pbf_status;
+
+#define PBF_OK 0
+#define PBF_EINVAL (-1)     /* invalid argument: null pointer, size, range, order */
+#define PBF_ENOMEM (-2)     /* host allocation failed or workspace too small */
+#define PBF_EMESH (-3)      /* mesh description not supported */
+#define PBF_EDEVICE (-4)    /* HIP runtime error */
+#define PBF_ENOCONV (-5)    /* iterative solver did not converge */
+#define PBF_ENONFINITE (-6) /* non-finite value detected */
+#define PBF_ESTATE (-7)     /* call out of order (e.g. a step before binding) */
+
+#define PBF_PREC_FP64 64    /* operator evaluated in double precision */
+#define PBF_PREC_FP32 32    /* operator in single precision on T - T_ref; state,
+                               accumulation and update stay double */
+
+/* ---- context ------------------------------------------------------------ */
+pbf_status pbf_create(pbf_ctx **out);
+void pbf_destroy(pbf_ctx *ctx);
+/* Message of the last failing call on ctx (or of pbf_create when ctx is NULL).
+ * The pointer stays valid until the next call on ctx. */
+const char *pbf_last_error(const pbf_ctx *ctx);
+
+/* ---- mesh and DoF map (Section 3.1, eq. bubnov_galerkin) -------------------
+ * Uniform box [0,Lx]x[0,Ly]x[0,Lz] of nx*ny*nz hexahedra with tensor-product
+ * Lagrange elements of the given degree (1 or 2) on equispaced nodes and the
+ * (degree+1)^3-point Gauss rule.  Resets material, laser and binding. */
+pbf_status pbf_mesh_box(pbf_ctx *ctx, int degree, int nx, int ny, int nz, double Lx, double Ly,
+                        double Lz);
+/* Sizes of the current mesh; any output pointer may be NULL.  n_hist_* depend
+ * on the powder depth of the material and are 0 before pbf_set_material. */
+pbf_status pbf_mesh_info(const pbf_ctx *ctx, int64_t *n_dofs, int64_t *n_cells, int64_t *n_qp,
+                         int64_t *n_hist_layers, int64_t *n_hist_cells, int64_t *n_hist_qp);
+
+/* ---- boundary conditions (Section 2, eqs. bc_dirichlet, bc_neumann) ---------
+ * Bit f of face_mask makes face f Dirichlet at T_D (bits 0..5: x-, x+, y-, y+,
+ * z-, z+); every node on such a face is held at T_D.  Other faces are
+ * insulated.  Default: no Dirichlet face. */
+pbf_status pbf_set_dirichlet(pbf_ctx *ctx, unsigned face_mask, double T_D);
+
+/* ---- material law (Section 2, eqs. liquid_fraction .. material_parameter_interp)
+ * k(T) and c_p(T) are piecewise linear on the shared breakpoints T_bp (strictly
+ * increasing, n_bp in [1,16]) and constant outside them.  The liquid fraction is
+ * g(T) = clamp((T - T_s)/(T_l - T_s), 0, 1); the consolidated fraction r_c is
+ * the running maximum of g (update before use); the conductivity is
+ * k = (1 - r_c) k_p + g k_m + (r_c - g) k_s with k_m = k_s = k(T) and
+ * k_p = powder_k_factor * k(T).  The heat capacity is the apparent capacity
+ * c_p(T) + latent/(T_l - T_s) on T_s <= T <= T_l.  Quadrature points at most
+ * powder_depth below the top face start as powder (r_c = 0). */
+typedef struct {
+    int n_bp;
+    const double *T_bp, *k_bp, *cp_bp; /* host arrays of n_bp values, copied */
+    double rho, T_s, T_l, latent, powder_k_factor, powder_depth;
+} pbf_material;
+pbf_status pbf_set_material(pbf_ctx *ctx, const pbf_material *m);
+
+/* ---- laser path (Section 2, eq. heat_soruce_cylindrical) ---------------------
+ * Tracks are scanned in order from t_start, each at its own speed; track k is
+ * active on [t_k, t_{k+1}); the beam is off outside the path.  W_eff =
+ * absorptivity * power.  kind 1 (volume): q = 2 W_eff/(pi R^2 h_powder)
+ * exp(-2 r^2/R^2) for depths 0 <= Lz - z <= h_powder, r the distance from the
+ * beam axis.  kind 0 (surface): Neumann flux 2 W_eff/(pi R^2) exp(-2 r^2/R^2)
+ * on the top face z = Lz.  kind -1: off.  The source of a step from t_n is
+ * evaluated at t_n. */
+typedef struct {
+    double x0[3], x1[3], speed, power;
+} pbf_track;
+typedef struct {
+    int kind;
+    double radius, absorptivity, h_powder, t_start;
+    int n_tracks;              /* 0..4096 */
+    const pbf_track *tracks;   /* host array, copied */
+} pbf_laser;
+pbf_status pbf_set_laser(pbf_ctx *ctx, const pbf_laser *l);
+/* Replace the nominal track powers (host array of n_tracks) and absorptivity. */
+pbf_status pbf_set_track_powers(pbf_ctx *ctx, const double *power, double absorptivity);
+
+/* ---- device binding -------------------------------------------------------------
+ * Workspace size for the current mesh; the caller allocates it on the device
+ * (256-byte aligned) and binds it together with the stream used for the
+ * table uploads (synchronizes).  Binding again replaces the previous one. */
+pbf_status pbf_workspace_bytes(const pbf_ctx *ctx, size_t *bytes);
+pbf_status pbf_bind_device(pbf_ctx *ctx, void *workspace, size_t bytes, void *stream);
+
+/* T[n_dofs] <- T0 (T_D on Dirichlet nodes); rc[n_hist_qp] <- initial
+ * consolidated fraction (0 powder, 1 consolidated).  rc may be NULL when
+ * n_hist_qp is 0.  Asynchronous. */
+pbf_status pbf_init_state(pbf_ctx *ctx, double T0, double *T, double *rc, void *stream);
+
+/* ---- explicit scheme (Section 3.2, eq. forward_euler) -------------------------
+ * n_steps forward-Euler steps T_{n+1} = T_n + dt C~(T_n)^{-1} f(T_n) from time
+ * t0 (t_n = t0 + n dt), with C~ the row-sum lumped capacity at T_n and f the
+ * diffusion, source and surface-flux terms; Dirichlet nodes are reset to T_D.
+ * T (in/out) and T_tmp are device arrays of n_dofs doubles that must not
+ * overlap; rc (in/out) is the history.  precision is PBF_PREC_FP64 or
+ * PBF_PREC_FP32.  The result is in T.  Asynchronous. */
+pbf_status pbf_explicit_steps(pbf_ctx *ctx, double *T, double *T_tmp, double *rc, double t0,
+                              double dt, int n_steps, int precision, void *stream);
+
+/* f(T) and C~(T) at time t into device arrays f, C (n_dofs doubles each) with the
+ * history updated in rc as in a step (eq. vector_evaluation).  Asynchronous. */
+pbf_status pbf_assemble(pbf_ctx *ctx, const double *T, double *rc, double t, double *f, double *C,
+                        int precision, void *stream);
+
+/* Largest eigenvalue of C~^{-1} K_diff (eq. explicit_time_step) by `iters`
+ * power iterations from the device vector v0 (n_dofs), with k and c_p frozen at
+ * the breakpoint where k/(rho c_p) is largest; the estimate is the Rayleigh
+ * quotient v^T K v / v^T C~ v over free nodes.  dt_crit = 2/lambda.  Uses
+ * scratch arrays from the workspace.  Synchronizes. */
+pbf_status pbf_stability_lambda(pbf_ctx *ctx, const double *v0, int iters, double *lambda_max,
+                                void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

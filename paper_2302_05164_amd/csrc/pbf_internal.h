@@ -1,0 +1,156 @@
+// Internal definitions shared by the host driver and the HIP kernels of the
+// pbftherm library (uniform Lagrange boxes on gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <type_traits>
+
+#include "pbftherm.h"
+
+namespace pbf {
+
+constexpr int kMaxBp = 16;
+
+// ---------------------------------------------------------------------------
+// Compile-time 1D tables of the tensor-product element: Gauss points and
+// weights on [0,1], Lagrange values on equispaced nodes at the Gauss points,
+// and the collocation derivative on the Gauss points (derivative at Gauss point
+// q of the Lagrange polynomial through the Gauss points that is one at point
+// r).  On a line of a Q_p cell the interpolant is a degree-p polynomial, so its
+// derivative at the Gauss points follows exactly from its Gauss-point values.
+// ---------------------------------------------------------------------------
+constexpr double csqrt(double x)
+{
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 200; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+
+template <int P>
+struct Tables {
+    static_assert(P == 1 || P == 2, "degree 1 or 2");
+    static constexpr int N = P + 1;
+    static constexpr double gp(int i)
+    {
+        if (P == 1) return i == 0 ? 0.5 - 0.5 / csqrt(3.0) : 0.5 + 0.5 / csqrt(3.0);
+        return i == 0 ? 0.5 - csqrt(15.0) / 10.0 : (i == 1 ? 0.5 : 0.5 + csqrt(15.0) / 10.0);
+    }
+    static constexpr double gw(int i)
+    {
+        if (P == 1) return 0.5;
+        return i == 1 ? 8.0 / 18.0 : 5.0 / 18.0;
+    }
+    // Lagrange polynomial a on the nodes b/P
+    static constexpr double lag(int a, double x)
+    {
+        double v = 1.0;
+        for (int b = 0; b <= P; ++b)
+            if (b != a) v *= (x - double(b) / P) / (double(a) / P - double(b) / P);
+        return v;
+    }
+    // derivative at x of the Lagrange polynomial through the Gauss points, 1 at point r
+    static constexpr double lag_gauss_d(int r, double x)
+    {
+        double s = 0.0;
+        for (int c = 0; c < N; ++c) {
+            if (c == r) continue;
+            double t = 1.0 / (gp(r) - gp(c));
+            for (int b = 0; b < N; ++b)
+                if (b != r && b != c) t *= (x - gp(b)) / (gp(r) - gp(b));
+            s += t;
+        }
+        return s;
+    }
+    // S(q,a) = l_a(x_q): nodes -> Gauss points.  The Q2 midpoint basis function
+    // is exactly 1 and the vertex ones exactly 0 at the middle Gauss point.
+    static constexpr double S(int q, int a) { return lag(a, gp(q)); }
+    static constexpr double D(int q, int r) { return lag_gauss_d(r, gp(q)); }
+};
+
+// coefficient "matrices" as types, so that rows can be unrolled at compile time
+template <int P> struct TagS  { static constexpr double c(int o, int i) { return Tables<P>::S(o, i); } };
+template <int P> struct TagSt { static constexpr double c(int o, int i) { return Tables<P>::S(i, o); } };
+template <int P> struct TagD  { static constexpr double c(int o, int i) { return Tables<P>::D(o, i); } };
+template <int P> struct TagDt { static constexpr double c(int o, int i) { return Tables<P>::D(i, o); } };
+
+// ---------------------------------------------------------------------------
+// material law in hinge form:  v(T) = v0 + sum_i dv_i max(T - b_i, 0), which
+// equals the piecewise-linear table with constant extrapolation (the slope
+// changes by dv_i at breakpoint b_i).  FP32 variants hold breakpoints and
+// thresholds shifted by T_ref.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Law {
+    int n_hinge;
+    R b[kMaxBp], dk[kMaxBp], dc[kMaxBp];
+    R k0, c0;
+    R Ts, Tl, inv_dT, lat;  // lat = latent/(T_l - T_s)
+    R phi, rho;
+};
+
+// Parameters of one cell-kernel launch (passed by value).
+template <typename R>
+struct CellParams {
+    const double *Tin;  // nodal temperatures (state, double)
+    double *Tout;       // next state (explicit mode)
+    double *fout, *Cout;  // assembled vectors (assemble mode)
+    double *hist;       // consolidated fraction of the history layers
+    double *slots;      // 8 parity slots of partial sums of f at tile faces
+    int nx, ny, nz, NX, NY, NZ;
+    int MX, MY, MZ, ntiles, tiles_per_xcd;
+    int hist_cz0, n_hist_cells;
+    double hx, hy, hz, Lz;
+    R detJ, ih2x, ih2y, ih2z;  // h^-2 per direction
+    double dt, T_D, Tref;
+    unsigned dmask;
+    int laser_on, laser_kind, src_cz0;
+    double xb, yb, src_amp, two_over_R2, h_powder;
+    const Law<R> *law;          // quadrature-point law (device copy, uniform indices)
+    const Law<double> *nlaw;    // nodal capacity law (always double)
+};
+
+// Parameters of the tile-face completion kernel.
+struct HaloParams {
+    const double *Tin;
+    double *Tout, *fout, *Cout;
+    const double *slots;
+    const Law<double> *nlaw;
+    int P, NX, NY, NZ, SX, SY, SZ, MX, MY, MZ;
+    long long GX, GY, GZ;  // sizes of the x-, y- and z-face groups
+    double hx, hy, hz, dt, T_D;
+    unsigned dmask;
+};
+
+// Row sum of the 1D mass matrix at node i of n_nodes (degree P, cell size h):
+// the 1D element row sums are (1/2, 1/2) h for Q1 and (1/6, 2/3, 1/6) h for Q2.
+__host__ __device__ inline double lumped_mass_1d(int i, int n_nodes, int P, double h)
+{
+    if (P == 1) return (i == 0 || i == n_nodes - 1) ? 0.5 * h : h;
+    if (i & 1) return (2.0 / 3.0) * h;
+    return (i == 0 || i == n_nodes - 1) ? h / 6.0 : h / 3.0;
+}
+
+// tile shape (cells) of the cell kernels: 8 x 8 x 4 cells, one cell per thread
+constexpr int kTX = 8, kTY = 8, kTZ = 4, kTPB = kTX * kTY * kTZ;
+
+// launchers (explicit.hip)
+hipError_t launch_cells(int degree, int precision, int mode, const CellParams<double> &pd,
+                        const CellParams<float> &pf, hipStream_t s);
+hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s);
+// vector kernels (vec.hip)
+hipError_t launch_fill(double *x, double v, long long n, hipStream_t s);
+hipError_t launch_init_dirichlet(double *T, const HaloParams &geom, double T_D, hipStream_t s);
+hipError_t launch_init_history(double *rc, int n_hist_cells, int nq1, const int *qz_powder_mask,
+                               int hist_layers, int nx, int ny, hipStream_t s);
+hipError_t launch_power_dots(const double *f, const double *C, const double *v, double *partials,
+                             double *scal, const HaloParams &geom, long long n, hipStream_t s);
+hipError_t launch_power_update(const double *f, const double *C, double *v, double *partials,
+                               double *scal, const HaloParams &geom, long long n, hipStream_t s);
+hipError_t launch_power_scale(double *v, const double *scal, long long n, hipStream_t s);
+
+constexpr int kRedBlocks = 1024;  // blocks of the first reduction stage
+
+}  // namespace pbf

@@ -1,0 +1,231 @@
+"""Python binding of the pbftherm C ABI (include/pbftherm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libpbftherm.so.  PyTorch provides device memory (tensors) and the
+stream (torch's current stream).  Importing this module fails loudly when the
+library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbftherm.so")
+
+PREC_FP64 = 64
+PREC_FP32 = 32
+
+_ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "EDEVICE", -5: "ENOCONV",
+           -6: "ENONFINITE", -7: "ESTATE"}
+
+
+class PbfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pbftherm {_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Material(C.Structure):
+    _fields_ = [("n_bp", C.c_int), ("T_bp", C.POINTER(C.c_double)), ("k_bp", C.POINTER(C.c_double)),
+                ("cp_bp", C.POINTER(C.c_double)), ("rho", C.c_double), ("T_s", C.c_double),
+                ("T_l", C.c_double), ("latent", C.c_double), ("powder_k_factor", C.c_double),
+                ("powder_depth", C.c_double)]
+
+
+class _Track(C.Structure):
+    _fields_ = [("x0", C.c_double * 3), ("x1", C.c_double * 3), ("speed", C.c_double),
+                ("power", C.c_double)]
+
+
+class _Laser(C.Structure):
+    _fields_ = [("kind", C.c_int), ("radius", C.c_double), ("absorptivity", C.c_double),
+                ("h_powder", C.c_double), ("t_start", C.c_double), ("n_tracks", C.c_int),
+                ("tracks", C.POINTER(_Track))]
+
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+
+# exported entry points and their argument types (also checked by the tests)
+SIGNATURES = {
+    "pbf_create": [C.POINTER(_vp)],
+    "pbf_destroy": [_vp],
+    "pbf_last_error": [_vp],
+    "pbf_mesh_box": [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double],
+    "pbf_mesh_info": [_vp, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p],
+    "pbf_set_dirichlet": [_vp, C.c_uint, C.c_double],
+    "pbf_set_material": [_vp, C.POINTER(_Material)],
+    "pbf_set_laser": [_vp, C.POINTER(_Laser)],
+    "pbf_set_track_powers": [_vp, _dp, C.c_double],
+    "pbf_workspace_bytes": [_vp, C.POINTER(C.c_size_t)],
+    "pbf_bind_device": [_vp, _vp, C.c_size_t, _vp],
+    "pbf_init_state": [_vp, C.c_double, _vp, _vp, _vp],
+    "pbf_explicit_steps": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp],
+    "pbf_assemble": [_vp, _vp, _vp, C.c_double, _vp, _vp, C.c_int, _vp],
+    "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(hipcc, gfx950); there is no fallback implementation")
+    L = C.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.pbf_last_error.restype = C.c_char_p
+    L.pbf_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(t, n, name):
+    if t.dtype != torch.float64 or t.numel() != n:
+        raise ValueError(f"{name}: expected {n} float64 values, got {t.numel()} {t.dtype}")
+    return _ptr(t)
+
+
+class Simulation:
+    """One uniform-box problem bound to one GPU.  Set-up order: constructor (mesh),
+    set_dirichlet, set_material, set_laser, bind(); then init_state() and the
+    stepping calls.  State tensors (T, rc) belong to the caller."""
+
+    def __init__(self, degree, nx, ny, nz, L, device="cuda:0"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.ctx = _vp()
+        self._check(self.lib.pbf_create(C.byref(self.ctx)), use_ctx=False)
+        self._check(self.lib.pbf_mesh_box(self.ctx, degree, nx, ny, nz, *map(float, L)))
+        self.workspace = None
+
+    def __del__(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self.lib.pbf_destroy(self.ctx)
+            self.ctx = _vp()
+
+    def _check(self, st, use_ctx=True):
+        if st != 0:
+            msg = self.lib.pbf_last_error(self.ctx if use_ctx else None)
+            raise PbfError(st, msg.decode() if msg else "")
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # -- description ---------------------------------------------------------
+    def info(self):
+        v = [C.c_int64() for _ in range(6)]
+        self._check(self.lib.pbf_mesh_info(self.ctx, *[C.byref(x) for x in v]))
+        keys = ("n_dofs", "n_cells", "n_qp", "n_hist_layers", "n_hist_cells", "n_hist_qp")
+        return dict(zip(keys, (x.value for x in v)))
+
+    def set_dirichlet(self, face_mask, T_D):
+        self._check(self.lib.pbf_set_dirichlet(self.ctx, int(face_mask), float(T_D)))
+
+    def set_material(self, T_bp, k_bp, cp_bp, rho, T_s, T_l, latent, powder_k_factor,
+                     powder_depth):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (T_bp, k_bp, cp_bp)]
+        m = _Material(len(arrs[0]), *[a.ctypes.data_as(_dp) for a in arrs], float(rho),
+                      float(T_s), float(T_l), float(latent), float(powder_k_factor),
+                      float(powder_depth))
+        self._check(self.lib.pbf_set_material(self.ctx, C.byref(m)))
+
+    def set_laser(self, kind, radius, absorptivity, h_powder, t_start, tracks):
+        tr = np.asarray(tracks, dtype=np.float64).reshape(-1, 8)
+        arr = (_Track * max(1, len(tr)))()
+        for i, row in enumerate(tr):
+            arr[i].x0[:] = row[0:3]
+            arr[i].x1[:] = row[3:6]
+            arr[i].speed = row[6]
+            arr[i].power = row[7]
+        l = _Laser(int(kind), float(radius), float(absorptivity), float(h_powder), float(t_start),
+                   len(tr), arr)
+        self._check(self.lib.pbf_set_laser(self.ctx, C.byref(l)))
+
+    def set_track_powers(self, powers, absorptivity):
+        p = np.ascontiguousarray(powers, dtype=np.float64)
+        self._check(self.lib.pbf_set_track_powers(self.ctx, p.ctypes.data_as(_dp), float(absorptivity)))
+
+    # -- device ------------------------------------------------------------------
+    def bind(self):
+        nb = C.c_size_t()
+        self._check(self.lib.pbf_workspace_bytes(self.ctx, C.byref(nb)))
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.pbf_bind_device(self.ctx, C.c_void_p(base + off), nb.value,
+                                             self._stream()))
+
+    def new_state(self):
+        i = self.info()
+        T = torch.empty(i["n_dofs"], dtype=torch.float64, device=self.device)
+        rc = torch.empty(max(1, i["n_hist_qp"]), dtype=torch.float64, device=self.device)
+        return T, rc
+
+    def init_state(self, T0, T=None, rc=None):
+        if T is None:
+            T, rc = self.new_state()
+        i = self.info()
+        self._check(self.lib.pbf_init_state(self.ctx, float(T0), _f64(T, i["n_dofs"], "T"),
+                                            _ptr(rc) if i["n_hist_qp"] else None, self._stream()))
+        return T, rc
+
+    def explicit_steps(self, T, rc, t0, dt, n_steps, precision=PREC_FP64, T_tmp=None):
+        i = self.info()
+        if T_tmp is None:
+            T_tmp = torch.empty_like(T)
+        self._check(self.lib.pbf_explicit_steps(
+            self.ctx, _f64(T, i["n_dofs"], "T"), _f64(T_tmp, i["n_dofs"], "T_tmp"),
+            _ptr(rc) if i["n_hist_qp"] else None, float(t0), float(dt), int(n_steps),
+            int(precision), self._stream()))
+        return T
+
+    def assemble(self, T, rc, t, precision=PREC_FP64):
+        i = self.info()
+        f = torch.empty_like(T)
+        Cl = torch.empty_like(T)
+        self._check(self.lib.pbf_assemble(self.ctx, _f64(T, i["n_dofs"], "T"),
+                                          _ptr(rc) if i["n_hist_qp"] else None, float(t),
+                                          _ptr(f), _ptr(Cl), int(precision), self._stream()))
+        return f, Cl
+
+    def stability_lambda(self, v0, iters):
+        i = self.info()
+        lam = C.c_double()
+        self._check(self.lib.pbf_stability_lambda(self.ctx, _f64(v0, i["n_dofs"], "v0"), int(iters),
+                                                  C.byref(lam), self._stream()))
+        return lam.value
+
+
+def from_problem(prob, device="cuda:0"):
+    """Simulation set up from a problem description object with the attributes
+    of pbf_workloads.Problem (argument marshalling only)."""
+    s = Simulation(prob.degree, prob.nx, prob.ny, prob.nz, prob.L, device=device)
+    s.set_dirichlet(prob.dirichlet_mask, prob.T_D)
+    s.set_material(prob.T_bp, prob.k_bp, prob.cp_bp, prob.rho, prob.T_s, prob.T_l, prob.latent,
+                   prob.powder_k_factor, prob.powder_depth)
+    s.set_laser(prob.laser_kind, prob.radius, prob.absorptivity, prob.h_powder, prob.t_start,
+                prob.tracks)
+    s.bind()
+    return s
