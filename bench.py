@@ -1,0 +1,193 @@
+"""Benchmark: explicit-step throughput of the matrix-free PBF thermal operator.
+
+One "step" is one forward-Euler step of the whole hot path (sum-factorized
+operator, material law, laser source, lumped-mass update, tile-face completion)
+over the full mesh.  The default workload is the 128x128x64 Q2 box (8,520,321
+DoFs) with the seeded nonlinear law and the 10-track zigzag scan; the value is
+whole-job DoF-updates/s in FP64, inputs resident in HBM.  The FP32-operator
+variant is timed on the same workload and reported beside it.
+
+Prints one JSON line.  --gpus N with N > 1 exits: the build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# peaks of one MI355X (public figures)
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def algorithmic_counts(prob, info):
+    """Per-step algorithmic bytes and flops of the explicit step:
+    bytes: read T_n and write T_{n+1} (8 B each per DoF) plus one read of the
+    powder history (8 B per stored quadrature point);
+    flops: the sum-factorized Q2 cell operator, 1755 flop per cell (interpolation
+    270, collocation gradients 405, flux and one law hinge 324, collocation
+    transpose 486, integration 270), plus 12 flop per node for the lumped
+    capacity and the update.  Q1: 8 x the 1D work of 2-point lines."""
+    n = info["n_dofs"]
+    bytes_step = 16.0 * n + 8.0 * info["n_hist_qp"]
+    if prob.degree == 2:
+        per_cell = 1755.0
+    else:
+        # Q1: 3 sweeps x 4 lines x 2 outputs x 3 flop, gradients 3 x 4 x 2 x 3,
+        # flux 8 x 12, transpose 3 x 8 x 2 x 2, integration 3 x 4 x 2 x 3
+        per_cell = 72 + 72 + 96 + 96 + 72
+    flops_step = per_cell * info["n_cells"] + 12.0 * n
+    return bytes_step, flops_step
+
+
+def cpu_baseline(prob, seconds_cap=60.0):
+    """The oracle (plain serial C) timed on a bounded sample: one explicit step
+    of the full workload mesh from its initial state."""
+    import numpy as np
+    import oracle
+
+    o = oracle.Oracle(prob)
+    T = o.init_T()
+    rc = o.init_history()
+    dt = 2.5e-6
+    t = time.perf_counter()
+    o.explicit_steps(T, rc, 0.0, dt, 1)
+    el = time.perf_counter() - t
+    del np
+    return {"value": o.N / el, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 explicit step of {prob.name} ({o.N} DoFs) from the initial state, "
+                      f"serial C, {el:.2f} s"}
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """Plain device copy of known size, for scaling HBM counters (FETCH_SIZE,
+    WRITE_SIZE) of a profiled run."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg4", "cfg5", "cfg1"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-operator timing")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device copy first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import pbf_workloads as W
+    from paper_2302_05164_amd import pbftherm
+
+    if args.calib_copy:
+        copy_calibration()
+
+    prob = W.CONFIGS[args.workload]()
+    sim = pbftherm.from_problem(prob, device="cuda:0")
+    info = sim.info()
+    # time step: half the explicit stability limit (power iteration on the GPU)
+    v0 = torch.tensor(W.seeded_vector(info["n_dofs"], 1), device="cuda")
+    lam = sim.stability_lambda(v0, 100)
+    dt = prob.dt_factor * 2.0 / lam
+    del v0
+
+    results = {}
+    for prec in ([64] if args.no_fp32 else [64, 32]):
+        T, rc = sim.init_state(prob.T0)
+        T_tmp = torch.empty_like(T)
+        sim.explicit_steps(T, rc, 0.0, dt, args.warmup, precision=prec, T_tmp=T_tmp)
+        torch.cuda.synchronize()
+        # timed region: K steps, kernel durations recorded with HIP events on the
+        # same stream
+        sim.timing_begin(args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        sim.explicit_steps(T, rc, args.warmup * dt, dt, args.steps, precision=prec, T_tmp=T_tmp)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        cell_ms, face_ms, nt = sim.timing_end()
+        finite = bool(torch.isfinite(T).all().item())
+        results[prec] = dict(ms=ms, cell_ms=cell_ms, face_ms=face_ms, n=nt, finite=finite,
+                             Tmax=float(T.max().item()))
+        del T, rc, T_tmp
+
+    n = info["n_dofs"]
+    r64 = results[64]
+    ms_step = r64["ms"] / args.steps
+    value = n * args.steps / (r64["ms"] / 1e3)
+    bytes_step, flops_step = algorithmic_counts(prob, info)
+    cell_s = r64["cell_ms"] / 1e3
+    hbm_gbs = bytes_step / cell_s / 1e9
+    tflops = flops_step / cell_s / 1e12
+    frac_hbm = hbm_gbs / HBM_PEAK_GBS
+    frac_alu = tflops / FP64_PEAK_TFLOPS
+    if frac_alu >= frac_hbm:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(frac_alu, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(frac_hbm, 4)}
+    roof["traffic"] = None
+    roof["kernel"] = "k_cells<2,double,0>" if prob.degree == 2 else "k_cells<1,double,0>"
+    roof["kernel_ms"] = round(r64["cell_ms"], 5)
+    roof["face_kernel_ms"] = round(r64["face_ms"], 5)
+    roof["algorithmic_bytes_per_launch"] = bytes_step
+    roof["algorithmic_flops_per_launch"] = flops_step
+    roof["hbm_frac_algorithmic"] = round(frac_hbm, 4)
+    roof["fp64_frac_algorithmic"] = round(frac_alu, 4)
+
+    out = {
+        "metric": "DoF-updates/s per explicit step (Q2, FP64 vs FP32-op); adjoint/forward time ratio",
+        "value": value,
+        "unit": "DoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "degree": prob.degree,
+                   "cells": [prob.nx, prob.ny, prob.nz], "n_dofs": n, "dt": dt,
+                   "operator_precision": "fp64", "finite": r64["finite"],
+                   "T_max": r64["Tmax"]},
+        "roofline": roof,
+    }
+    if 32 in results:
+        r32 = results[32]
+        v32 = n * args.steps / (r32["ms"] / 1e3)
+        out["fp32_operator"] = {"value": v32, "unit": "DoF-updates/s",
+                                "ms_per_step": r32["ms"] / args.steps,
+                                "speedup_vs_fp64": v32 / value,
+                                "kernel_ms": r32["cell_ms"], "finite": r32["finite"]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

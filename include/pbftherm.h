@@ -156,6 +156,16 @@ pbf_status pbf_assemble(pbf_ctx *ctx, const double *T, double *rc, double t, dou
 pbf_status pbf_stability_lambda(pbf_ctx *ctx, const double *v0, int iters, double *lambda_max,
                                 void *stream);
 
+/* ---- kernel timing (instrumentation) ------------------------------------------
+ * pbf_timing_begin: from now on pbf_explicit_steps records HIP events on the
+ * caller's stream before and after each cell-kernel and tile-face-kernel launch,
+ * for at most max_steps steps (host-side event pool, created here).
+ * pbf_timing_end: waits for the recorded events and returns the average
+ * duration in milliseconds of the cell kernel and of the tile-face kernel and
+ * the number of timed steps; releases the events.  Synchronizes. */
+pbf_status pbf_timing_begin(pbf_ctx *ctx, int max_steps);
+pbf_status pbf_timing_end(pbf_ctx *ctx, double *cell_ms, double *face_ms, int64_t *n_steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,10 @@ struct pbf_ctx {
     bool laws_dirty = true;
     Law<double> h_law64{}, h_lin64{};
     Law<float> h_law32{};
+    // kernel timing: 3 events per timed step (before cells, between, after faces)
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
+    bool timing = false;
 };
 
 namespace {
@@ -331,7 +335,10 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const
         set_beam(c, pf, t);
     }
     if (linear) pd.nlaw = c->d_lin64;
+    const bool timed = c->timing && mode == 0 && c->tev_used + 3 <= c->tev.size();
+    if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used], s));
     PBF_HIP(c, launch_cells(c->degree, precision, mode, pd, pf, s));
+    if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
     HaloParams h = geometry(c);
     if (linear) h.nlaw = c->d_lin64;
     h.Tin = Tin;
@@ -340,6 +347,10 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const
     h.Cout = C;
     h.dt = dt;
     PBF_HIP(c, launch_halo(mode, h, s));
+    if (timed) {
+        PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 2], s));
+        c->tev_used += 3;
+    }
     return PBF_OK;
 }
 
@@ -355,7 +366,12 @@ pbf_status pbf_create(pbf_ctx **out)
     return PBF_OK;
 }
 
-void pbf_destroy(pbf_ctx *ctx) { delete ctx; }
+void pbf_destroy(pbf_ctx *ctx)
+{
+    if (!ctx) return;
+    for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
+    delete ctx;
+}
 
 const char *pbf_last_error(const pbf_ctx *ctx)
 {
@@ -629,6 +645,42 @@ pbf_status pbf_stability_lambda(pbf_ctx *c, const double *v0, int iters, double 
     PBF_HIP(c, hipMemcpyAsync(sc, c->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PBF_HIP(c, hipStreamSynchronize(s));
     *lambda_max = sc[0] / sc[1];
+    return PBF_OK;
+}
+
+pbf_status pbf_timing_begin(pbf_ctx *c, int max_steps)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (max_steps < 1 || max_steps > (1 << 22)) return fail(c, PBF_EINVAL, "max_steps out of range");
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    c->tev.assign((size_t)max_steps * 3, nullptr);
+    for (auto &e : c->tev) PBF_HIP(c, hipEventCreate(&e));
+    c->tev_used = 0;
+    c->timing = true;
+    return PBF_OK;
+}
+
+pbf_status pbf_timing_end(pbf_ctx *c, double *cell_ms, double *face_ms, int64_t *n_steps)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->timing) return fail(c, PBF_ESTATE, "timing was not started");
+    c->timing = false;
+    double a = 0.0, b = 0.0;
+    const size_t n = c->tev_used / 3;
+    if (n > 0) PBF_HIP(c, hipEventSynchronize(c->tev[c->tev_used - 1]));
+    for (size_t k = 0; k < n; ++k) {
+        float t1 = 0.f, t2 = 0.f;
+        PBF_HIP(c, hipEventElapsedTime(&t1, c->tev[3 * k], c->tev[3 * k + 1]));
+        PBF_HIP(c, hipEventElapsedTime(&t2, c->tev[3 * k + 1], c->tev[3 * k + 2]));
+        a += t1;
+        b += t2;
+    }
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    c->tev.clear();
+    c->tev_used = 0;
+    if (cell_ms) *cell_ms = n ? a / n : 0.0;
+    if (face_ms) *face_ms = n ? b / n : 0.0;
+    if (n_steps) *n_steps = (int64_t)n;
     return PBF_OK;
 }
 

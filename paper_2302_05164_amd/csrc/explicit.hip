@@ -44,6 +44,16 @@ template <> __device__ __forceinline__ float ffma<float>(float a, float b, float
 {
     return __builtin_fmaf(a, b, c);
 }
+// The material law is read through the constant address space: the loads are
+// scalar, cached in the scalar cache and known not to alias the history stores.
+template <typename R>
+using ConstLaw = const __attribute__((address_space(4))) Law<R>;
+template <typename R>
+__device__ __forceinline__ ConstLaw<R> &const_law(const Law<R> *p)
+{
+    return *(ConstLaw<R> *)p;
+}
+
 template <typename R> __device__ __forceinline__ R fmax0(R a, R b) { return a > b ? a : b; }
 template <typename R> __device__ __forceinline__ R fmin0(R a, R b) { return a < b ? a : b; }
 
@@ -127,7 +137,7 @@ __device__ __forceinline__ void cell_operator(const CellParams<R> &p, const R *u
     // breakpoint b_i) contributes only where T > b_i, and the latent heat and
     // history only where T >= T_s.  Terms that no Gauss point of the wave
     // reaches are exactly zero and are skipped (called by active lanes only).
-    const Law<R> &law = *p.law;
+    ConstLaw<R> &law = const_law(p.law);
     R tmax = v[0];
 #pragma unroll
     for (int q = 1; q < NN; ++q) tmax = fmax0(tmax, v[q]);
@@ -186,11 +196,12 @@ __device__ __forceinline__ void cell_operator(const CellParams<R> &p, const R *u
             if constexpr (dz != 0.0) w[tidx<N, 2>(r, qx, qy)] = ffma(R(dz), Fz, w[tidx<N, 2>(r, qx, qy)]);
         });
         if (src_cell) {
-            const double zq = (cz + TB::gp(qz)) * p.hz;
+            constexpr double xiq = TB::gp(qx), etq = TB::gp(qy), zeq = TB::gp(qz);
+            const double zq = (cz + zeq) * p.hz;
             const double depth = p.Lz - zq;
             if (depth >= 0.0 && depth <= p.h_powder) {
-                const double dxb = (cx + TB::gp(qx)) * p.hx - p.xb;
-                const double dyb = (cy + TB::gp(qy)) * p.hy - p.yb;
+                const double dxb = (cx + xiq) * p.hx - p.xb;
+                const double dyb = (cy + etq) * p.hy - p.yb;
                 const double s = p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
                 w[q] = ffma(R(wq) * p.detJ, R(s), w[q]);
             }
@@ -206,8 +217,9 @@ __device__ __forceinline__ void cell_operator(const CellParams<R> &p, const R *u
         R qs[N * N];
         sfor<0, N * N>([&](auto ic) {
             constexpr int i = decltype(ic)::value % N, j = decltype(ic)::value / N;
-            const double dxb = (cx + TB::gp(i)) * p.hx - p.xb;
-            const double dyb = (cy + TB::gp(j)) * p.hy - p.yb;
+            constexpr double xi = TB::gp(i), et = TB::gp(j);
+            const double dxb = (cx + xi) * p.hx - p.xb;
+            const double dyb = (cy + et) * p.hy - p.yb;
             constexpr double w2 = TB::gw(i) * TB::gw(j);
             qs[decltype(ic)::value] =
                 R(w2 * p.hx * p.hy * p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2));
@@ -248,7 +260,7 @@ __device__ __forceinline__ bool is_face(int g, int S, int n)  // interior tile f
 
 // lumped capacity C~_i = rho c(T_i) M~_i at node (i,j,k), in double precision;
 // hinges of the law that no active lane of the wave exceeds are skipped
-__device__ __forceinline__ double node_capacity(const Law<double> &L, double T, int i, int j, int k,
+__device__ __forceinline__ double node_capacity(ConstLaw<double> &L, double T, int i, int j, int k,
                                                 int P, int NX, int NY, int NZ, double hx, double hy,
                                                 double hz)
 {
@@ -332,7 +344,8 @@ k_cells(const CellParams<R> p)
             continue;
         }
         const double T = sT[idx];
-        const double C = node_capacity(*p.nlaw, T, gi, gj, gk, P, p.NX, p.NY, p.NZ, p.hx, p.hy, p.hz);
+        const double C = node_capacity(const_law(p.nlaw), T, gi, gj, gk, P, p.NX, p.NY, p.NZ, p.hx,
+                                       p.hy, p.hz);
         if (MODE == 0) {
             p.Tout[g] = on_dirichlet(p.dmask, gi, gj, gk, p.NX, p.NY, p.NZ) ? p.T_D
                                                                            : T + p.dt * sF[idx] / C;
@@ -394,7 +407,8 @@ __global__ void __launch_bounds__(256) k_halo(const HaloParams h)
                 f += h.slots[par * NT + g];
             }
     const double T = h.Tin[g];
-    const double C = node_capacity(*h.nlaw, T, gi, gj, gk, h.P, h.NX, h.NY, h.NZ, h.hx, h.hy, h.hz);
+    const double C = node_capacity(const_law(h.nlaw), T, gi, gj, gk, h.P, h.NX, h.NY, h.NZ, h.hx,
+                                   h.hy, h.hz);
     if (MODE == 0) {
         h.Tout[g] = on_dirichlet(h.dmask, gi, gj, gk, h.NX, h.NY, h.NZ) ? h.T_D : T + h.dt * f / C;
     } else {

@@ -68,6 +68,8 @@ SIGNATURES = {
     "pbf_explicit_steps": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp],
     "pbf_assemble": [_vp, _vp, _vp, C.c_double, _vp, _vp, C.c_int, _vp],
     "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
+    "pbf_timing_begin": [_vp, C.c_int],
+    "pbf_timing_end": [_vp, _dp, _dp, _i64p],
 }
 
 _lib = None
@@ -216,6 +218,15 @@ class Simulation:
         self._check(self.lib.pbf_stability_lambda(self.ctx, _f64(v0, i["n_dofs"], "v0"), int(iters),
                                                   C.byref(lam), self._stream()))
         return lam.value
+
+
+    def timing_begin(self, max_steps):
+        self._check(self.lib.pbf_timing_begin(self.ctx, int(max_steps)))
+
+    def timing_end(self):
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        self._check(self.lib.pbf_timing_end(self.ctx, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
 
 
 def from_problem(prob, device="cuda:0"):
