@@ -205,19 +205,42 @@ Beam beam_at(const pbf_ctx *c, double t)
     return b;
 }
 
+// Cell layers per z-segment of a column workgroup: minimizes the makespan
+// (rounds of resident workgroups x layers per workgroup), two workgroups per CU
+// on 256 CUs, preferring longer segments (fewer segment faces) on ties.
+int segment_length(const pbf_ctx *c)
+{
+    const int ty = column_height();
+    const long long cols = (long long)ceil_div(c->nx, kTX) * ceil_div(c->ny, ty);
+    const long long slots = 256LL * resident_columns_per_cu(ty);
+    int best = c->nz;
+    long long best_cost = -1;
+    for (int S = std::min(c->nz, 32); S >= 1; --S) {
+        const long long blocks = cols * ceil_div(c->nz, S);
+        const long long cost = ((blocks + slots - 1) / slots) * S;
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = S;
+        }
+    }
+    return best;
+}
+
 HaloParams geometry(const pbf_ctx *c)
 {
     HaloParams h{};
     const int P = c->degree;
+    const int S = segment_length(c);
     h.NX = (int)nodes1(c, 0);
     h.NY = (int)nodes1(c, 1);
     h.NZ = (int)nodes1(c, 2);
+    const int ty = column_height();
     h.SX = P * kTX;
-    h.SY = P * kTY;
-    h.SZ = P * kTZ;
+    h.SY = P * ty;
+    h.SZ = P * S;
     h.MX = ceil_div(c->nx, kTX);
-    h.MY = ceil_div(c->ny, kTY);
-    h.MZ = ceil_div(c->nz, kTZ);
+    h.MY = ceil_div(c->ny, ty);
+    h.MZ = ceil_div(c->nz, S);
     h.GX = (long long)(h.MX - 1) * h.NY * h.NZ;
     h.GY = (long long)h.NX * (h.MY - 1) * h.NZ;
     h.GZ = (long long)h.NX * h.NY * (h.MZ - 1);
@@ -248,6 +271,7 @@ CellParams<R> cell_params(const pbf_ctx *c, const Law<R> *law, bool history)
     p.MZ = h.MZ;
     p.ntiles = h.MX * h.MY * h.MZ;
     p.tiles_per_xcd = ceil_div(p.ntiles, 8);
+    p.seg_len = h.SZ / c->degree;
     p.hist_cz0 = history ? c->nz - c->hist_layers : c->nz;
     p.n_hist_cells = (int)n_hist_cells(c);
     p.hx = c->L[0] / c->nx;
@@ -337,7 +361,7 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const
     if (linear) pd.nlaw = c->d_lin64;
     const bool timed = c->timing && mode == 0 && c->tev_used + 3 <= c->tev.size();
     if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used], s));
-    PBF_HIP(c, launch_cells(c->degree, precision, mode, pd, pf, s));
+    PBF_HIP(c, launch_cells(c->degree, precision, mode, column_height(), pd, pf, s));
     if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
     HaloParams h = geometry(c);
     if (linear) h.nlaw = c->d_lin64;

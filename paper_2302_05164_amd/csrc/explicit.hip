@@ -9,26 +9,31 @@
 // the lumped capacity C~_i = rho c(T_i) M~_i (row-sum lumped mass, positive for
 // Q1 and Q2) evaluated at the node when it is updated.
 //
-// Design (one workgroup = a tile of 8x8x4 cells, one cell per lane):
-//  1. the tile's node box is staged in LDS with coalesced row loads;
-//  2. each lane gathers its cell, interpolates to the Gauss points with three
-//     1D sweeps in registers (compile-time 1D tables, structural zeros and ones
-//     removed), differentiates by Gauss-point collocation, evaluates the
-//     material law and the laser source branch-free, and integrates back with
-//     the transposed sweeps;
-//  3. cell results are summed into LDS node accumulators in 8 parity phases
-//     (cells of equal coordinate parity share no node), so the order of every
-//     sum is fixed and results are bitwise reproducible;
-//  4. nodes not on an interior tile face are complete: the lumped-mass update
-//     is applied right away and T_{n+1} written once (the GPU counterpart of
+// Design (one workgroup = a column of 16x16 cells, one cell per lane, marching
+// up through a segment of cell layers):
+//  1. per layer, the node planes of the layer are staged in LDS with coalesced
+//     row loads and each lane gathers its cell;
+//  2. each lane interpolates to the Gauss points with three 1D sweeps in
+//     registers (compile-time 1D tables, structural zeros and ones removed),
+//     differentiates by Gauss-point collocation, evaluates the material law and
+//     the laser source, and integrates back with the transposed sweeps;
+//  3. cell vectors go to a conflict-free LDS staging array; every node then
+//     adds the contributions of its (at most 4) cells of the layer in a fixed
+//     order, so results are bitwise reproducible;
+//  4. the top node plane of a layer is carried in LDS to the next layer, whose
+//     bottom plane it is; nodes that are then complete get the lumped-mass
+//     update right away and T_{n+1} is written once (the GPU counterpart of
 //     interleaving cell loop and vector update, Section 4.2.2);
-//  5. nodes on interior tile faces store their partial sums in one of 8 slot
-//     arrays chosen by the tile's coordinate parity (tiles sharing a node
-//     differ in parity); a second kernel adds the <= 8 partials in a fixed
-//     order and applies the update.
-// Workgroups are mapped to tiles so that each XCD gets a contiguous slab of
-// tiles (neighbouring tiles then share halo nodes in the same L2).
+//  5. nodes on the side faces of a column or on the end planes of a segment
+//     store their partial sums in one of 8 slot arrays chosen by the parity of
+//     the column and segment coordinates (neighbours sharing a node differ in
+//     parity); a second kernel adds the <= 8 partials in a fixed order and
+//     applies the update.
+// Workgroups are mapped so that each XCD gets a contiguous range of columns
+// and segments (neighbours then share face nodes in the same L2).
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
 
 #include "pbf_internal.h"
 
@@ -52,6 +57,19 @@ template <typename R>
 __device__ __forceinline__ ConstLaw<R> &const_law(const Law<R> *p)
 {
     return *(ConstLaw<R> *)p;
+}
+
+// Kernel parameters re-read inside the layer loop through a laundered pointer
+// to the kernel-argument segment (scalar loads near their uses) instead of
+// being held in scalar registers across the whole loop.
+template <typename T>
+using AS4 = const __attribute__((address_space(4))) T;
+template <typename T>
+__device__ __forceinline__ AS4<T> *kernarg_params()
+{
+    AS4<T> *kp = (AS4<T> *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(kp));
+    return kp;
 }
 
 template <typename R> __device__ __forceinline__ R fmax0(R a, R b) { return a > b ? a : b; }
@@ -118,12 +136,87 @@ __device__ __forceinline__ void sweep(const R *in, R *out)
     });
 }
 
+// Flux and source at the Gauss points of one cell, accumulated into the
+// collocation-space integrand w.  FAST: at most one hinge of the law active, no
+// history and no source in the wave (uniform branch-free straight-line code).
+template <int P, typename R, bool FAST, typename PP, typename L>
+__device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int nhinge, bool melt,
+                                            bool has_hist, long long hc, bool src_cell, int cx, int cy,
+                                            int cz)
+{
+    using TB = Tables<P>;
+    constexpr int N = P + 1, NN = N * N * N;
+    const R k0 = law.k0;
+    const R b0 = law.b[0];
+    const R dk0 = nhinge > 0 ? R(law.dk[0]) : R(0);
+    const R detJ = p.detJ, ih2x = p.ih2x, ih2y = p.ih2y, ih2z = p.ih2z;
+    sfor<0, NN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+        // reference gradient by Gauss-point collocation
+        auto gxf = [&](auto rc) { return v[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
+        auto gyf = [&](auto rc) { return v[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
+        auto gzf = [&](auto rc) { return v[tidx<N, 2>(decltype(rc)::value, qx, qy)]; };
+        const R gx = rowdot<TagD<P>, qx, 0, N, false>(gxf, R(0));
+        const R gy = rowdot<TagD<P>, qy, 0, N, false>(gyf, R(0));
+        const R gz = rowdot<TagD<P>, qz, 0, N, false>(gzf, R(0));
+        const R T = v[q];
+        // conductivity (Section 2): hinge sum truncated to the breakpoints
+        // that some lane of the wave exceeds
+        R k;
+        if constexpr (FAST) {
+            k = ffma(dk0, fmax0(T - b0, R(0)), k0);
+        } else {
+            R kpl = k0;
+            for (int i = 0; i < nhinge; ++i) kpl = ffma(law.dk[i], fmax0(T - law.b[i], R(0)), kpl);
+            k = kpl;
+            if (has_hist) {
+                const long long hi = (long long)q * p.n_hist_cells + hc;
+                R r = R(p.hist[hi]);
+                if (melt) {
+                    const R g = fmin0(fmax0((T - law.Ts) * law.inv_dT, R(0)), R(1));
+                    if (g > r) {  // r_c = max(r_c, g): update before use
+                        r = g;
+                        p.hist[hi] = double(g);
+                    }
+                }
+                // k = (1-r) k_p + g k_m + (r-g) k_s with k_m = k_s = k(T), k_p = phi k(T)
+                k = kpl * (r + law.phi * (R(1) - r));
+            }
+        }
+        constexpr double wq = TB::gw(qx) * TB::gw(qy) * TB::gw(qz);
+        const R kW = k * (R(wq) * detJ);
+        // flux -k W J^{-1} J^{-T} grad T, collocation transpose
+        const R Fx = -kW * ih2x * gx, Fy = -kW * ih2y * gy, Fz = -kW * ih2z * gz;
+        sfor<0, N>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            constexpr double dx = TB::D(qx, r), dy = TB::D(qy, r), dz = TB::D(qz, r);
+            if constexpr (dx != 0.0) w[tidx<N, 0>(r, qy, qz)] = ffma(R(dx), Fx, w[tidx<N, 0>(r, qy, qz)]);
+            if constexpr (dy != 0.0) w[tidx<N, 1>(r, qx, qz)] = ffma(R(dy), Fy, w[tidx<N, 1>(r, qx, qz)]);
+            if constexpr (dz != 0.0) w[tidx<N, 2>(r, qx, qy)] = ffma(R(dz), Fz, w[tidx<N, 2>(r, qx, qy)]);
+        });
+        if constexpr (!FAST) {
+            if (src_cell) {
+                constexpr double xiq = TB::gp(qx), etq = TB::gp(qy), zeq = TB::gp(qz);
+                const double zq = (cz + zeq) * p.hz;
+                const double depth = p.Lz - zq;
+                if (depth >= 0.0 && depth <= p.h_powder) {
+                    const double dxb = (cx + xiq) * p.hx - p.xb;
+                    const double dyb = (cy + etq) * p.hy - p.yb;
+                    const double s = p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
+                    w[q] = ffma(R(wq) * detJ, R(s), w[q]);
+                }
+            }
+        }
+    });
+}
+
 // ---------------------------------------------------------------------------
 // one cell: nodal values u -> element vector fe (diffusion, source, surface
 // flux).  Values are relative to Tref (zero in double precision).
 // ---------------------------------------------------------------------------
-template <int P, typename R>
-__device__ __forceinline__ void cell_operator(const CellParams<R> &p, const R *u, int cx, int cy,
+template <int P, typename R, typename PP>
+__device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R *u, int cx, int cy,
                                               int cz, R *fe)
 {
     using TB = Tables<P>;
@@ -137,7 +230,7 @@ __device__ __forceinline__ void cell_operator(const CellParams<R> &p, const R *u
     // breakpoint b_i) contributes only where T > b_i, and the latent heat and
     // history only where T >= T_s.  Terms that no Gauss point of the wave
     // reaches are exactly zero and are skipped (called by active lanes only).
-    ConstLaw<R> &law = const_law(p.law);
+    ConstLaw<R> &law = const_law(lawp);
     R tmax = v[0];
 #pragma unroll
     for (int q = 1; q < NN; ++q) tmax = fmax0(tmax, v[q]);
@@ -153,60 +246,15 @@ __device__ __forceinline__ void cell_operator(const CellParams<R> &p, const R *u
     R w[NN];  // collocation-space integrand of f
 #pragma unroll
     for (int q = 0; q < NN; ++q) w[q] = R(0);
+    // Most cells of a scan are cold, consolidated and away from the beam: for
+    // them the 27 points run as one straight-line block (one hinge at most, no
+    // history, no source), which lets the scheduler interleave independent
+    // points.  Both paths evaluate the same arithmetic.
+    if (nhinge <= 1 && !has_hist && !src_cell)
+        flux_points<P, R, true>(p, law, v, w, nhinge, melt, false, 0, false, cx, cy, cz);
+    else
+        flux_points<P, R, false>(p, law, v, w, nhinge, melt, has_hist, hc, src_cell, cx, cy, cz);
 
-    // flux and source at the Gauss points, collocation transpose into w
-    sfor<0, NN>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
-        // reference gradient by Gauss-point collocation
-        auto gxf = [&](auto rc) { return v[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
-        auto gyf = [&](auto rc) { return v[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
-        auto gzf = [&](auto rc) { return v[tidx<N, 2>(decltype(rc)::value, qx, qy)]; };
-        const R gx = rowdot<TagD<P>, qx, 0, N, false>(gxf, R(0));
-        const R gy = rowdot<TagD<P>, qy, 0, N, false>(gyf, R(0));
-        const R gz = rowdot<TagD<P>, qz, 0, N, false>(gzf, R(0));
-        const R T = v[q];
-        // conductivity (Section 2): hinge sum truncated to the breakpoints
-        // that some lane of the wave exceeds
-        R kpl = law.k0;
-        for (int i = 0; i < nhinge; ++i) kpl = ffma(law.dk[i], fmax0(T - law.b[i], R(0)), kpl);
-        R k = kpl;
-        if (has_hist) {
-            const long long hi = (long long)q * p.n_hist_cells + hc;
-            R r = R(p.hist[hi]);
-            if (melt) {
-                const R g = fmin0(fmax0((T - law.Ts) * law.inv_dT, R(0)), R(1));
-                if (g > r) {  // r_c = max(r_c, g): update before use
-                    r = g;
-                    p.hist[hi] = double(g);
-                }
-            }
-            // k = (1-r) k_p + g k_m + (r-g) k_s with k_m = k_s = k(T), k_p = phi k(T)
-            k = kpl * (r + law.phi * (R(1) - r));
-        }
-        constexpr double wq = TB::gw(qx) * TB::gw(qy) * TB::gw(qz);
-        const R kW = k * (R(wq) * p.detJ);
-        // flux -k W J^{-1} J^{-T} grad T, collocation transpose
-        const R Fx = -kW * p.ih2x * gx, Fy = -kW * p.ih2y * gy, Fz = -kW * p.ih2z * gz;
-        sfor<0, N>([&](auto rc) {
-            constexpr int r = decltype(rc)::value;
-            constexpr double dx = TB::D(qx, r), dy = TB::D(qy, r), dz = TB::D(qz, r);
-            if constexpr (dx != 0.0) w[tidx<N, 0>(r, qy, qz)] = ffma(R(dx), Fx, w[tidx<N, 0>(r, qy, qz)]);
-            if constexpr (dy != 0.0) w[tidx<N, 1>(r, qx, qz)] = ffma(R(dy), Fy, w[tidx<N, 1>(r, qx, qz)]);
-            if constexpr (dz != 0.0) w[tidx<N, 2>(r, qx, qy)] = ffma(R(dz), Fz, w[tidx<N, 2>(r, qx, qy)]);
-        });
-        if (src_cell) {
-            constexpr double xiq = TB::gp(qx), etq = TB::gp(qy), zeq = TB::gp(qz);
-            const double zq = (cz + zeq) * p.hz;
-            const double depth = p.Lz - zq;
-            if (depth >= 0.0 && depth <= p.h_powder) {
-                const double dxb = (cx + xiq) * p.hx - p.xb;
-                const double dyb = (cy + etq) * p.hy - p.yb;
-                const double s = p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
-                w[q] = ffma(R(wq) * p.detJ, R(s), w[q]);
-            }
-        }
-    });
     // integrate f: transposed interpolation sweeps
     sweep<TagSt<P>, N, 0>(w, t1);
     sweep<TagSt<P>, N, 1>(t1, t2);
@@ -241,12 +289,6 @@ __device__ __forceinline__ void cell_operator(const CellParams<R> &p, const R *u
     }
 }
 
-template <int P>
-struct Box {
-    static constexpr int BX = P * kTX + 1, BY = P * kTY + 1, BZ = P * kTZ + 1;
-    static constexpr int N = BX * BY * BZ;
-};
-
 __device__ __forceinline__ bool on_dirichlet(unsigned m, int i, int j, int k, int NX, int NY, int NZ)
 {
     return ((m & 1u) && i == 0) || ((m & 2u) && i == NX - 1) || ((m & 4u) && j == 0) ||
@@ -264,10 +306,16 @@ __device__ __forceinline__ double node_capacity(ConstLaw<double> &L, double T, i
                                                 int P, int NX, int NY, int NZ, double hx, double hy,
                                                 double hz)
 {
-    int nh = 0;
-    while (nh < L.n_hinge && __any(T > L.b[nh])) ++nh;
     double c = L.c0;
-    for (int h = 0; h < nh; ++h) c = __builtin_fma(L.dc[h], fmax0(T - L.b[h], 0.0), c);
+    if (L.n_hinge > 0 && __any(T > L.b[0])) {
+        if (L.n_hinge > 1 && __any(T > L.b[1])) {
+            int nh = 2;
+            while (nh < L.n_hinge && __any(T > L.b[nh])) ++nh;
+            for (int h = 0; h < nh; ++h) c = __builtin_fma(L.dc[h], fmax0(T - L.b[h], 0.0), c);
+        } else {
+            c = __builtin_fma(L.dc[0], fmax0(T - L.b[0], 0.0), c);
+        }
+    }
     if (T >= L.Ts && T <= L.Tl) c += L.lat;
     const double m = lumped_mass_1d(i, NX, P, hx) * lumped_mass_1d(j, NY, P, hy) *
                      lumped_mass_1d(k, NZ, P, hz);
@@ -275,84 +323,129 @@ __device__ __forceinline__ double node_capacity(ConstLaw<double> &L, double T, i
 }
 
 // MODE 0: explicit step (fused update into Tout); MODE 1: assemble f and C~.
-template <int P, typename R, int MODE>
-__global__ void __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(P == 2 && sizeof(R) == 8 ? 2 : (P == 2 ? 3 : 4))))
+//
+// Node ownership inside a column: the lane of cell (lx, ly) owns the nodes of
+// its cell with local x and y indices in 1..P (plus index 0 on the column's
+// low faces).  Own contributions come straight from registers; the shared
+// contributions of the right, upper and diagonal neighbour cells come from a
+// small LDS staging area (each cell stages its x = 0 plane and its y = 0 row);
+// the top node plane is carried per lane to the next layer.  The sum order of
+// every node is fixed: carry, own, right, upper, diagonal.
+template <int P, typename R, int MODE, int kTY>
+__global__ void __launch_bounds__(kTX * kTY) __attribute__((amdgpu_waves_per_eu(P == 2 && sizeof(R) == 8 ? 2 : (P == 2 ? 3 : 4))))
 k_cells(const CellParams<R> p)
 {
+    constexpr int kTPB = kTX * kTY;
     constexpr int N = P + 1, NN = N * N * N;
-    constexpr int BX = Box<P>::BX, BY = Box<P>::BY, BOX = Box<P>::N;
-    __shared__ double sT[BOX];
-    __shared__ double sF[BOX];
+    constexpr int BX = P * kTX + 1, BY = P * kTY + 1, PLANE = BX * BY, NB = N * PLANE;
+    constexpr int NSH = N * N + P * N;  // staged per cell: x = 0 plane, then y = 0 row for x = 1..P
+    __shared__ double sT[NB];
+    __shared__ double sS[NSH * kTPB];
+    __shared__ double sC[N * N * kTPB];  // carry: top-plane partial sums per lane, (y, x) major
 
     const int b = blockIdx.x;
-    const int tile = (b & 7) * p.tiles_per_xcd + (b >> 3);
-    if (tile >= p.ntiles) return;  // uniform over the workgroup
-    const int tx = tile % p.MX, ty = (tile / p.MX) % p.MY, tz = tile / (p.MX * p.MY);
-    const int i0 = P * kTX * tx, j0 = P * kTY * ty, k0 = P * kTZ * tz;
+    const int id = (b & 7) * p.tiles_per_xcd + (b >> 3);
+    if (id >= p.ntiles) return;  // uniform over the workgroup
+    const int seg = id % p.MZ, col = id / p.MZ;
+    const int tx = col % p.MX, ty = col / p.MX;
+    const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
+    const int i0 = P * kTX * tx, j0 = P * kTY * ty;
+    const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
+    const long long NXY = (long long)p.NX * p.NY, NT = NXY * p.NZ;
 
-    for (int idx = threadIdx.x; idx < BOX; idx += kTPB) {
-        const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / (BX * BY);
-        const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
-        double val = 0.0;
-        if (gi < p.NX && gj < p.NY && gk < p.NZ)
-            val = p.Tin[(long long)gi + (long long)p.NX * (gj + (long long)p.NY * gk)];
-        sT[idx] = val;
-        sF[idx] = 0.0;
-    }
-    __syncthreads();
-
-    const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz = threadIdx.x / (kTX * kTY);
-    const int cx = kTX * tx + lx, cy = kTY * ty + ly, cz = kTZ * tz + lz;
-    const bool active = cx < p.nx && cy < p.ny && cz < p.nz;
-
-    R fe[NN];
-    if (active) {
+#pragma clang loop unroll(disable)
+    for (int cz = z0; cz < z1; ++cz) {
+        const int k0 = P * cz;
+        // Everything derived from the lane index is recomputed inside the layer
+        // loop: hoisting it would hold registers across the whole march.
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        AS4<CellParams<R>> &q = *kernarg_params<CellParams<R>>();
+        const Law<R> *lawp = q.law;
+        const Law<double> *nlawp = q.nlaw;
+        const int lx = tid % kTX, ly = tid / kTX;
+        const int cx = kTX * tx + lx, cy = kTY * ty + ly;
+        const bool active = cx < q.nx && cy < q.ny;
+        // 1. stage the node planes of the layer
+        for (int idx = tid; idx < NB; idx += kTPB) {
+            const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
+            const int gi = i0 + li, gj = j0 + lj;
+            double val = 0.0;
+            if (gi < q.NX && gj < q.NY)
+                val = q.Tin[(long long)gi + (long long)q.NX * gj + NXY * (k0 + lk)];
+            sT[idx] = val;
+        }
+        __syncthreads();
+        // 2. cell operator (every lane gathers, so that no value of a previous
+        // layer stays live across the loop)
         R u[NN];
 #pragma unroll
         for (int a = 0; a < NN; ++a) {
             const int ax = a % N, ay = (a / N) % N, az = a / (N * N);
-            const double tv = sT[(P * lz + az) * BX * BY + (P * ly + ay) * BX + P * lx + ax];
+            const double tv = sT[(az * BY + P * ly + ay) * BX + P * lx + ax];
             if constexpr (std::is_same<R, double>::value) u[a] = tv;
-            else u[a] = R(tv - p.Tref);
+            else u[a] = R(tv - q.Tref);
         }
-        cell_operator<P, R>(p, u, cx, cy, cz, fe);
-    }
-
-    const int par = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2);
-    for (int ph = 0; ph < 8; ++ph) {
-        if (active && par == ph) {
+        R fe[NN];
+        if (active) {
+            cell_operator<P, R>(q, lawp, u, cx, cy, cz, fe);
 #pragma unroll
-            for (int a = 0; a < NN; ++a) {
-                const int ax = a % N, ay = (a / N) % N, az = a / (N * N);
-                sF[(P * lz + az) * BX * BY + (P * ly + ay) * BX + P * lx + ax] += double(fe[a]);
+            for (int az = 0; az < N; ++az) {
+#pragma unroll
+                for (int ay = 0; ay < N; ++ay) sS[(az * N + ay) * kTPB + tid] = double(fe[(az * N + ay) * N]);
+#pragma unroll
+                for (int ax = 1; ax <= P; ++ax)
+                    sS[(N * N + az * P + ax - 1) * kTPB + tid] = double(fe[az * N * N + ax]);
             }
         }
         __syncthreads();
-    }
-
-    const int tpar = (tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2);
-    const long long NXY = (long long)p.NX * p.NY, NT = NXY * p.NZ;
-    for (int idx = threadIdx.x; idx < BOX; idx += kTPB) {
-        const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / (BX * BY);
-        const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
-        if (gi >= p.NX || gj >= p.NY || gk >= p.NZ) continue;
-        const long long g = (long long)gi + (long long)p.NX * gj + NXY * gk;
-        const bool face = is_face(gi, P * kTX, p.NX) || is_face(gj, P * kTY, p.NY) ||
-                          is_face(gk, P * kTZ, p.NZ);
-        if (face) {
-            p.slots[tpar * NT + g] = sF[idx];
-            continue;
+        // 3. owned nodes: sum, carry, completion
+        if (active) {
+            const bool hasR = lx < kTX - 1 && cx + 1 < q.nx;
+            const bool hasU = ly < kTY - 1 && cy + 1 < q.ny;
+            const bool first = cz == z0, last = cz == z1 - 1;
+#pragma unroll
+            for (int az = 0; az < N; ++az) {
+#pragma unroll
+                for (int ay = 0; ay < N; ++ay) {
+#pragma unroll
+                    for (int ax = 0; ax < N; ++ax) {
+                        if ((ax == 0 && lx != 0) || (ay == 0 && ly != 0)) continue;
+                        double f = 0.0;
+                        if (az == 0 && !first) f = sC[(ay * N + ax) * kTPB + tid];
+                        f += double(fe[(az * N + ay) * N + ax]);
+                        if (ax == P && hasR) f += sS[(az * N + ay) * kTPB + tid + 1];
+                        if (ay == P && hasU)
+                            f += ax == 0 ? sS[(az * N) * kTPB + tid + kTX]
+                                         : sS[(N * N + az * P + ax - 1) * kTPB + tid + kTX];
+                        if (ax == P && ay == P && hasR && hasU) f += sS[(az * N) * kTPB + tid + kTX + 1];
+                        if (az == P && !last) {  // top plane: completed by the next layer
+                            sC[(ay * N + ax) * kTPB + tid] = f;
+                            continue;
+                        }
+                        const int gi = P * cx + ax, gj = P * cy + ay, gk = k0 + az;
+                        const long long g = (long long)gi + (long long)q.NX * gj + NXY * gk;
+                        const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < q.NZ - 1) ||
+                                          is_face(gi, P * kTX, q.NX) || is_face(gj, P * kTY, q.NY);
+                        if (face) {
+                            q.slots[tpar * NT + g] = f;
+                            continue;
+                        }
+                        const double T = sT[(az * BY + P * ly + ay) * BX + P * lx + ax];
+                        const double C = node_capacity(const_law(nlawp), T, gi, gj, gk, P, q.NX, q.NY,
+                                                       q.NZ, q.hx, q.hy, q.hz);
+                        if (MODE == 0) {
+                            q.Tout[g] = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ) ? q.T_D
+                                                                                            : T + q.dt * f / C;
+                        } else {
+                            q.fout[g] = f;
+                            q.Cout[g] = C;
+                        }
+                    }
+                }
+            }
         }
-        const double T = sT[idx];
-        const double C = node_capacity(const_law(p.nlaw), T, gi, gj, gk, P, p.NX, p.NY, p.NZ, p.hx,
-                                       p.hy, p.hz);
-        if (MODE == 0) {
-            p.Tout[g] = on_dirichlet(p.dmask, gi, gj, gk, p.NX, p.NY, p.NZ) ? p.T_D
-                                                                           : T + p.dt * sF[idx] / C;
-        } else {
-            p.fout[g] = sF[idx];
-            p.Cout[g] = C;
-        }
+        __syncthreads();
     }
 }
 
@@ -419,14 +512,14 @@ __global__ void __launch_bounds__(256) k_halo(const HaloParams h)
 
 }  // namespace
 
-hipError_t launch_cells(int degree, int precision, int mode, const CellParams<double> &pd,
-                        const CellParams<float> &pf, hipStream_t s)
+namespace {
+template <int TY>
+void launch_ty(int degree, int precision, int mode, const CellParams<double> &pd,
+               const CellParams<float> &pf, hipStream_t s)
 {
-    const int ntiles = precision == PBF_PREC_FP32 ? pf.ntiles : pd.ntiles;
     const int tpx = precision == PBF_PREC_FP32 ? pf.tiles_per_xcd : pd.tiles_per_xcd;
-    (void)ntiles;
-    const dim3 grid(8 * tpx), block(kTPB);
-#define PBF_LAUNCH(P_, R_, M_, prm) hipLaunchKernelGGL((k_cells<P_, R_, M_>), grid, block, 0, s, prm)
+    const dim3 grid(8 * tpx), block(kTX * TY);
+#define PBF_LAUNCH(P_, R_, M_, prm) hipLaunchKernelGGL((k_cells<P_, R_, M_, TY>), grid, block, 0, s, prm)
     if (precision == PBF_PREC_FP64) {
         if (degree == 1) { if (mode == 0) PBF_LAUNCH(1, double, 0, pd); else PBF_LAUNCH(1, double, 1, pd); }
         else { if (mode == 0) PBF_LAUNCH(2, double, 0, pd); else PBF_LAUNCH(2, double, 1, pd); }
@@ -435,6 +528,25 @@ hipError_t launch_cells(int degree, int precision, int mode, const CellParams<do
         else { if (mode == 0) PBF_LAUNCH(2, float, 0, pf); else PBF_LAUNCH(2, float, 1, pf); }
     }
 #undef PBF_LAUNCH
+}
+}  // namespace
+
+int column_height()
+{
+    // 16 x 4 cells (one wavefront per workgroup) unless PBF_COLUMN_TY selects 8 or 16
+    const char *e = getenv("PBF_COLUMN_TY");
+    const int v = e ? atoi(e) : 4;
+    return (v == 8 || v == 16) ? v : 4;
+}
+
+int resident_columns_per_cu(int ty) { return ty == 4 ? 8 : (ty == 8 ? 4 : 2); }
+
+hipError_t launch_cells(int degree, int precision, int mode, int ty, const CellParams<double> &pd,
+                        const CellParams<float> &pf, hipStream_t s)
+{
+    if (ty == 4) launch_ty<4>(degree, precision, mode, pd, pf, s);
+    else if (ty == 8) launch_ty<8>(degree, precision, mode, pd, pf, s);
+    else launch_ty<16>(degree, precision, mode, pd, pf, s);
     return hipGetLastError();
 }
 

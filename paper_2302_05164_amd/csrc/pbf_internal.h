@@ -100,7 +100,8 @@ struct CellParams {
     double *hist;       // consolidated fraction of the history layers
     double *slots;      // 8 parity slots of partial sums of f at tile faces
     int nx, ny, nz, NX, NY, NZ;
-    int MX, MY, MZ, ntiles, tiles_per_xcd;
+    int MX, MY, MZ, ntiles, tiles_per_xcd;  // columns in x, y; z-segments; MX*MY*MZ
+    int seg_len;                            // cell layers per z-segment
     int hist_cz0, n_hist_cells;
     double hx, hy, hz, Lz;
     R detJ, ih2x, ih2y, ih2z;  // h^-2 per direction
@@ -133,12 +134,16 @@ __host__ __device__ inline double lumped_mass_1d(int i, int n_nodes, int P, doub
     return (i == 0 || i == n_nodes - 1) ? h / 6.0 : h / 3.0;
 }
 
-// tile shape (cells) of the cell kernels: 8 x 8 x 4 cells, one cell per thread
-constexpr int kTX = 8, kTY = 8, kTZ = 4, kTPB = kTX * kTY * kTZ;
+// Cell kernels: a workgroup owns a column of kTX x TY cells (one cell per
+// thread) and marches up through a segment of seg_len cell layers.
+constexpr int kTX = 16;
 
 // launchers (explicit.hip)
-hipError_t launch_cells(int degree, int precision, int mode, const CellParams<double> &pd,
+hipError_t launch_cells(int degree, int precision, int mode, int ty, const CellParams<double> &pd,
                         const CellParams<float> &pf, hipStream_t s);
+// column height in cells (16 x ty columns) and resident workgroups per CU
+int column_height();
+int resident_columns_per_cu(int ty);
 hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s);
 // vector kernels (vec.hip)
 hipError_t launch_fill(double *x, double v, long long n, hipStream_t s);
