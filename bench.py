@@ -64,6 +64,55 @@ def cpu_baseline(prob, seconds_cap=60.0):
                       f"serial C, {el:.2f} s"}
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_05164_amd", "csrc", "explicit.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def pmc_summary(fetch_dir, write_dir, out_path, workload, kernel="k_cells<2, double, 0"):
+    """Summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+    `bench.py --calib-copy`: per-dispatch KiB of the cell kernel, scaled by the
+    counter/true-bytes ratio of the 1 GiB device copy of the same run."""
+    import csv
+    import glob
+
+    def read(d, name):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == name]
+        return rows
+
+    res = {"workload": workload, "kernel": kernel, "kernel_source_sha256_16": kernel_source_hash()}
+    for d, name in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        rows = read(d, name)
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        calib_kib = max(copy)  # the 1 GiB copy is the largest copy dispatch
+        scale = (1 << 20) / calib_kib  # true KiB per counted KiB
+        kv = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+        res[name] = {"kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv),
+                     "copy_1GiB_counter_kib": calib_kib, "scale": scale,
+                     "bytes_per_dispatch": sum(kv) / len(kv) * scale * 1024.0}
+    res["traffic_bytes_per_dispatch"] = (res["FETCH_SIZE"]["bytes_per_dispatch"] +
+                                         res["WRITE_SIZE"]["bytes_per_dispatch"])
+    json.dump(res, open(out_path, "w"), indent=1)
+    print(json.dumps(res))
+
+
+def measured_traffic(workload):
+    """Counter-based HBM bytes per cell-kernel launch from the committed
+    summary, if it was taken on the current kernel source, else None."""
+    path = os.path.join(ROOT, "profiles", f"k_cells_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d["traffic_bytes_per_dispatch"]
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """Plain device copy of known size, for scaling HBM counters (FETCH_SIZE,
     WRITE_SIZE) of a profiled run."""
@@ -87,7 +136,13 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-operator timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (HBM counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="summarize rocprofv3 FETCH_SIZE/WRITE_SIZE runs and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        prob_name = {"cfg1": "cfg1", "cfg2": "cfg2", "cfg4": "cfg4", "cfg5": "cfg5"}[args.workload]
+        pmc_summary(*args.pmc_summary, workload=prob_name)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -149,7 +204,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(frac_hbm, 4)}
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(args.workload)
     roof["kernel"] = "k_cells<2,double,0>" if prob.degree == 2 else "k_cells<1,double,0>"
     roof["kernel_ms"] = round(r64["cell_ms"], 5)
     roof["face_kernel_ms"] = round(r64["face_ms"], 5)

@@ -33,8 +33,6 @@
 // and segments (neighbours then share face nodes in the same L2).
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
-
 #include "pbf_internal.h"
 
 namespace pbf {
@@ -531,13 +529,9 @@ void launch_ty(int degree, int precision, int mode, const CellParams<double> &pd
 }
 }  // namespace
 
-int column_height()
-{
-    // 16 x 4 cells (one wavefront per workgroup) unless PBF_COLUMN_TY selects 8 or 16
-    const char *e = getenv("PBF_COLUMN_TY");
-    const int v = e ? atoi(e) : 4;
-    return (v == 8 || v == 16) ? v : 4;
-}
+// 16 x 16 cells per column workgroup: measured fastest of 16x4, 16x8 and 16x16
+// on cfg2-size boxes (fewer column-face nodes, same per-lane work)
+int column_height() { return 16; }
 
 int resident_columns_per_cu(int ty) { return ty == 4 ? 8 : (ty == 8 ? 4 : 2); }
 
