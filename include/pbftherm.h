@@ -156,6 +156,26 @@ pbf_status pbf_assemble(pbf_ctx *ctx, const double *T, double *rc, double t, dou
 pbf_status pbf_stability_lambda(pbf_ctx *ctx, const double *v0, int iters, double *lambda_max,
                                 void *stream);
 
+/* ---- implicit scheme (Section 3.2, eqs. backward_euler_nonlinear, Newton_1, Newton_2)
+ * One backward-Euler step from T_n (time t) to T_out (time t + dt), solving
+ *   R(T) = C(T_n)(T - T_n)/dt - f_diff(T) - f_vol(t + dt) = 0
+ * at free nodes (Dirichlet nodes held at T_D) by Picard iterations
+ * (C(T_n)/dt + K(T^i)) dT = -R(T^i): the symmetric part of the Jacobian of
+ * eq. Newton_1, applied matrix-free (Section 4.2, eq. matrix_free_eval without
+ * the L_e term).  C is the consistent apparent-capacity matrix at T_n; the
+ * consolidated fraction is held at its value in rc during the step and then
+ * committed as max(rc, g(T_out)).  Each linear system is solved from zero by
+ * Jacobi-preconditioned CG to ||r|| <= cg_rtol ||b|| (at most cg_max_it
+ * iterations); Picard stops when max|dT| <= picard_tol (at most picard_max_it).
+ * T_n and T_out: device arrays of n_dofs doubles (distinct); rc in/out.
+ * Outputs: total CG iterations, Picard iterations, relative residual of the last
+ * CG solve.  Returns PBF_ENOCONV (with T_out holding the last iterate) when a
+ * limit is reached.  Synchronizes (one scalar read per CG iteration). */
+pbf_status pbf_implicit_step(pbf_ctx *ctx, const double *T_n, double *T_out, double *rc, double t,
+                             double dt, double cg_rtol, int cg_max_it, double picard_tol,
+                             int picard_max_it, int *cg_iters_total, int *picard_iters,
+                             double *final_rel_res, void *stream);
+
 /* ---- kernel timing (instrumentation) ------------------------------------------
  * pbf_timing_begin: from now on pbf_explicit_steps records HIP events on the
  * caller's stream before and after each cell-kernel and tile-face-kernel launch,

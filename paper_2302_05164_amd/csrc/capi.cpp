@@ -46,6 +46,7 @@ struct pbf_ctx {
     Law<float> *d_law32 = nullptr;
     double *d_slots = nullptr;
     double *d_f = nullptr, *d_C = nullptr, *d_v = nullptr, *d_partials = nullptr, *d_scal = nullptr;
+    double *d_cg[8] = {};  // implicit step: y, diag, r, z, p, Ap, x, d
     bool laws_dirty = true;
     Law<double> h_law64{}, h_lin64{};
     Law<float> h_law32{};
@@ -208,11 +209,10 @@ Beam beam_at(const pbf_ctx *c, double t)
 // Cell layers per z-segment of a column workgroup: minimizes the makespan
 // (rounds of resident workgroups x layers per workgroup), two workgroups per CU
 // on 256 CUs, preferring longer segments (fewer segment faces) on ties.
-int segment_length(const pbf_ctx *c)
+int segment_length(const pbf_ctx *c, int ty, int resident_per_cu)
 {
-    const int ty = column_height();
     const long long cols = (long long)ceil_div(c->nx, kTX) * ceil_div(c->ny, ty);
-    const long long slots = 256LL * resident_columns_per_cu(ty);
+    const long long slots = 256LL * resident_per_cu;
     int best = c->nz;
     long long best_cost = -1;
     for (int S = std::min(c->nz, 32); S >= 1; --S) {
@@ -226,15 +226,20 @@ int segment_length(const pbf_ctx *c)
     return best;
 }
 
-HaloParams geometry(const pbf_ctx *c)
+// Column geometry of a cell kernel with columns of 16 x ty cells and the given
+// number of resident workgroups per CU (explicit kernels by default).
+HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
 {
+    if (ty < 0) {
+        ty = column_height();
+        resident = resident_columns_per_cu(ty);
+    }
     HaloParams h{};
     const int P = c->degree;
-    const int S = segment_length(c);
+    const int S = segment_length(c, ty, resident);
     h.NX = (int)nodes1(c, 0);
     h.NY = (int)nodes1(c, 1);
     h.NZ = (int)nodes1(c, 2);
-    const int ty = column_height();
     h.SX = P * kTX;
     h.SY = P * ty;
     h.SZ = P * S;
@@ -376,6 +381,60 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const
         c->tev_used += 3;
     }
     return PBF_OK;
+}
+
+// Picard-operator parameters (apply or diagonal) for C(Tc)/dt + K(Tk)
+PicardParams picard_params(const pbf_ctx *c, const HaloParams &h, const double *Tc, const double *Tk,
+                           const double *x1, const double *x2, double *y, const double *rc,
+                           double dt, const Beam *src)
+{
+    PicardParams q{};
+    q.Tc = Tc;
+    q.Tk = Tk;
+    q.x1 = x1;
+    q.x2 = x2;
+    q.yout = y;
+    q.hist = rc;
+    q.slots = c->d_slots;
+    q.nx = c->nx;
+    q.ny = c->ny;
+    q.nz = c->nz;
+    q.NX = h.NX;
+    q.NY = h.NY;
+    q.NZ = h.NZ;
+    q.MX = h.MX;
+    q.MY = h.MY;
+    q.MZ = h.MZ;
+    q.ntiles = h.MX * h.MY * h.MZ;
+    q.tiles_per_xcd = ceil_div(q.ntiles, 8);
+    q.seg_len = h.SZ / c->degree;
+    q.hist_cz0 = c->nz - c->hist_layers;
+    q.n_hist_cells = (int)n_hist_cells(c);
+    q.hx = c->L[0] / c->nx;
+    q.hy = c->L[1] / c->ny;
+    q.hz = c->L[2] / c->nz;
+    q.Lz = c->L[2];
+    q.detJ = q.hx * q.hy * q.hz;
+    q.ih2x = 1.0 / (q.hx * q.hx);
+    q.ih2y = 1.0 / (q.hy * q.hy);
+    q.ih2z = 1.0 / (q.hz * q.hz);
+    q.inv_dt = 1.0 / dt;
+    q.dmask = c->dmask;
+    q.laser_kind = c->laser_kind;
+    const double depth_cells = (c->L[2] - c->h_powder) / q.hz;
+    q.src_cz0 = std::max(0, (int)std::floor(depth_cells) - 1);
+    q.h_powder = c->h_powder;
+    q.two_over_R2 = c->radius > 0 ? 2.0 / (c->radius * c->radius) : 0.0;
+    q.src_on = 0;
+    if (src && src->on) {
+        const double PI = 3.14159265358979323846, R2 = c->radius * c->radius;
+        q.src_on = 1;
+        q.xb = src->xb;
+        q.yb = src->yb;
+        q.src_amp = c->laser_kind == 1 ? 2.0 * src->W / (PI * R2 * c->h_powder) : 2.0 * src->W / (PI * R2);
+    }
+    q.law = c->d_law64;
+    return q;
 }
 
 }  // namespace
@@ -538,7 +597,7 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     size_t b = 0;
     b += align256(sizeof(Law<double>)) * 2 + align256(sizeof(Law<float>));
     b += align256(8 * N * sizeof(double));        // parity slots
-    b += 3 * align256(N * sizeof(double));        // f, C, v scratch
+    b += 11 * align256(N * sizeof(double));       // f, C, v; implicit: y, diag, r, z, p, Ap, x, d
     b += align256(kRedBlocks * 4 * sizeof(double)); // reduction partials
     b += align256(64 * sizeof(double));           // device scalars
     *bytes = b;
@@ -570,6 +629,10 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     p += align256(N * sizeof(double));
     c->d_v = (double *)p;
     p += align256(N * sizeof(double));
+    for (int k = 0; k < 8; ++k) {
+        c->d_cg[k] = (double *)p;
+        p += align256(N * sizeof(double));
+    }
     c->d_partials = (double *)p;
     p += align256(kRedBlocks * 4 * sizeof(double));
     c->d_scal = (double *)p;
@@ -669,6 +732,85 @@ pbf_status pbf_stability_lambda(pbf_ctx *c, const double *v0, int iters, double 
     PBF_HIP(c, hipMemcpyAsync(sc, c->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PBF_HIP(c, hipStreamSynchronize(s));
     *lambda_max = sc[0] / sc[1];
+    return PBF_OK;
+}
+
+pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, double *rc, double t,
+                             double dt, double cg_rtol, int cg_max_it, double picard_tol,
+                             int picard_max_it, int *cg_iters_total, int *picard_iters,
+                             double *final_rel_res, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!T_n || !T_out || T_n == T_out) return fail(c, PBF_EINVAL, "T_n and T_out must be distinct device arrays");
+    if (n_hist_qp(c) > 0 && !rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
+    if (!(dt > 0) || !std::isfinite(t)) return fail(c, PBF_EINVAL, "need dt > 0 and finite t");
+    if (!(cg_rtol > 0) || cg_max_it < 1 || !(picard_tol > 0) || picard_max_it < 1)
+        return fail(c, PBF_EINVAL, "tolerances must be > 0 and iteration limits >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    const long long N = n_dofs(c);
+    const HaloParams ge = geometry(c);  // explicit-kernel geometry (history commit)
+    const HaloParams hp = geometry(c, picard_column_height(), 3);
+    double *y = c->d_cg[0], *diag = c->d_cg[1], *r = c->d_cg[2], *z = c->d_cg[3], *p = c->d_cg[4],
+           *Ap = c->d_cg[5], *x = c->d_cg[6], *d = c->d_cg[7];
+    double *Ti = T_out;
+    PBF_HIP(c, hipMemcpyAsync(Ti, T_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PBF_HIP(c, launch_init_dirichlet(Ti, ge, c->T_D, s));
+    const Beam bm = beam_at(c, t + dt);
+    int total = 0, it = 0;
+    bool cg_fail = false, converged = false;
+    double last_rel = 0.0;
+    double hs[8];
+    for (it = 0; it < picard_max_it;) {
+        // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_vol, and diag(A(T^i))
+        PBF_HIP(c, launch_sub(d, Ti, T_n, N, s));
+        PicardParams qa = picard_params(c, hp, T_n, Ti, d, Ti, y, rc, dt, &bm);
+        PBF_HIP(c, launch_picard(c->degree, 0, qa, hp, s));
+        PicardParams qd = picard_params(c, hp, T_n, Ti, nullptr, nullptr, diag, rc, dt, nullptr);
+        PBF_HIP(c, launch_picard(c->degree, 1, qd, hp, s));
+        PBF_HIP(c, launch_cg_start(y, diag, r, z, p, x, c->d_partials, c->d_scal, ge, N, s));
+        PBF_HIP(c, hipMemcpyAsync(hs, c->d_scal + CG_RZ0, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+        PBF_HIP(c, hipStreamSynchronize(s));
+        const double bn = std::sqrt(hs[CG_BN2 - CG_RZ0]);
+        double rr = hs[CG_RR - CG_RZ0];
+        int k = 0, rz_old = CG_RZ0;
+        last_rel = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+        PicardParams qp = picard_params(c, hp, T_n, Ti, p, p, Ap, rc, dt, nullptr);
+        while (bn > 0 && std::sqrt(rr) > cg_rtol * bn && k < cg_max_it) {
+            PBF_HIP(c, launch_picard(c->degree, 0, qp, hp, s));
+            PBF_HIP(c, launch_cg_pap(p, Ap, c->d_partials, c->d_scal, N, s));
+            PBF_HIP(c, launch_cg_update(x, r, z, p, Ap, diag, c->d_partials, c->d_scal, rz_old, N, s));
+            PBF_HIP(c, hipMemcpyAsync(&rr, c->d_scal + CG_RR, sizeof(double), hipMemcpyDeviceToHost, s));
+            PBF_HIP(c, hipStreamSynchronize(s));
+            const int rz_new = rz_old == CG_RZ0 ? CG_RZ1 : CG_RZ0;
+            PBF_HIP(c, launch_cg_direction(p, z, c->d_scal, rz_old, rz_new, N, s));
+            rz_old = rz_new;
+            ++k;
+            last_rel = std::sqrt(rr) / bn;
+        }
+        total += k;
+        if (bn > 0 && std::sqrt(rr) > cg_rtol * bn) cg_fail = true;
+        PBF_HIP(c, launch_picard_update(Ti, x, c->d_partials, c->d_scal, ge, N, s));
+        double dmax = 0.0;
+        PBF_HIP(c, hipMemcpyAsync(&dmax, c->d_scal + CG_DMAX, sizeof(double), hipMemcpyDeviceToHost, s));
+        PBF_HIP(c, hipStreamSynchronize(s));
+        ++it;
+        if (!std::isfinite(dmax)) return fail(c, PBF_ENONFINITE, "non-finite Picard update");
+        if (dmax <= picard_tol) {
+            converged = true;
+            break;
+        }
+    }
+    // commit the consolidated fraction: r = max(r, g(T_{n+1}))
+    st = operator_pass(c, 1, PBF_PREC_FP64, false, Ti, nullptr, c->d_f, c->d_C, rc, t + dt, 0.0, s);
+    if (st) return st;
+    if (cg_iters_total) *cg_iters_total = total;
+    if (picard_iters) *picard_iters = it;
+    if (final_rel_res) *final_rel_res = last_rel;
+    if (cg_fail) return fail(c, PBF_ENOCONV, "CG did not reach the relative tolerance %g", cg_rtol);
+    if (!converged) return fail(c, PBF_ENOCONV, "Picard did not converge in %d iterations", picard_max_it);
     return PBF_OK;
 }
 

@@ -1,0 +1,264 @@
+// Device building blocks shared by the cell kernels of the pbftherm library:
+// compile-time 1D contractions, scalar access to the material law and to the
+// kernel arguments, the lumped nodal capacity, and the owner-computes node
+// completion of the column-march kernels.  Internal header (device code).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pbf_internal.h"
+
+namespace pbf {
+namespace {
+
+
+template <typename R> __device__ __forceinline__ R ffma(R a, R b, R c);
+template <> __device__ __forceinline__ double ffma<double>(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
+}
+template <> __device__ __forceinline__ float ffma<float>(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
+// The material law is read through the constant address space: the loads are
+// scalar, cached in the scalar cache and known not to alias the history stores.
+template <typename R>
+using ConstLaw = const __attribute__((address_space(4))) Law<R>;
+template <typename R>
+__device__ __forceinline__ ConstLaw<R> &const_law(const Law<R> *p)
+{
+    return *(ConstLaw<R> *)p;
+}
+
+// Kernel parameters re-read inside the layer loop through a laundered pointer
+// to the kernel-argument segment (scalar loads near their uses) instead of
+// being held in scalar registers across the whole loop.
+template <typename T>
+using AS4 = const __attribute__((address_space(4))) T;
+template <typename T>
+__device__ __forceinline__ AS4<T> *kernarg_params()
+{
+    AS4<T> *kp = (AS4<T> *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(kp));
+    return kp;
+}
+
+template <typename R> __device__ __forceinline__ R fmax0(R a, R b) { return a > b ? a : b; }
+template <typename R> __device__ __forceinline__ R fmin0(R a, R b) { return a < b ? a : b; }
+
+// compile-time loop
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// acc + sum_i M(row, i) x(i), terms with an exactly zero coefficient dropped and
+// unit coefficients added without a multiply.
+template <class M, int row, int i, int N, bool started, typename R, typename X>
+__device__ __forceinline__ R rowdot(const X &x, R acc)
+{
+    if constexpr (i == N) {
+        if constexpr (started) return acc;
+        else return R(0);
+    } else {
+        constexpr double c = M::c(row, i);
+        if constexpr (c == 0.0) {
+            return rowdot<M, row, i + 1, N, started>(x, acc);
+        } else {
+            R xi = x(std::integral_constant<int, i>{});
+            R nacc;
+            if constexpr (!started) nacc = (c == 1.0) ? xi : R(c) * xi;
+            else nacc = (c == 1.0) ? acc + xi : ffma(R(c), xi, acc);
+            return rowdot<M, row, i + 1, N, true>(x, nacc);
+        }
+    }
+}
+
+// flat index of a (z,y,x) register tensor with extent N per direction; `a` runs
+// along direction DIM, (i, j) along the other two in increasing order
+template <int N, int DIM>
+__device__ constexpr int tidx(int a, int i, int j)
+{
+    if constexpr (DIM == 0) return (j * N + i) * N + a;
+    else if constexpr (DIM == 1) return (j * N + a) * N + i;
+    else return (a * N + j) * N + i;
+}
+
+// out = M applied along DIM (every line of the tensor)
+template <class M, int N, int DIM, typename R>
+__device__ __forceinline__ void sweep(const R *in, R *out)
+{
+    sfor<0, N>([&](auto ic) {
+        sfor<0, N>([&](auto jc) {
+            constexpr int I = decltype(ic)::value, J = decltype(jc)::value;
+            auto get = [&](auto ac) {
+                constexpr int A = decltype(ac)::value;
+                return in[tidx<N, DIM>(A, I, J)];
+            };
+            sfor<0, N>([&](auto oc) {
+                constexpr int O = decltype(oc)::value;
+                out[tidx<N, DIM>(O, I, J)] = rowdot<M, O, 0, N, false>(get, R(0));
+            });
+        });
+    });
+}
+
+__device__ __forceinline__ bool on_dirichlet(unsigned m, int i, int j, int k, int NX, int NY, int NZ)
+{
+    return ((m & 1u) && i == 0) || ((m & 2u) && i == NX - 1) || ((m & 4u) && j == 0) ||
+           ((m & 8u) && j == NY - 1) || ((m & 16u) && k == 0) || ((m & 32u) && k == NZ - 1);
+}
+
+__device__ __forceinline__ bool is_face(int g, int S, int n)  // interior tile face
+{
+    return g > 0 && g < n - 1 && (g % S) == 0;
+}
+
+// lumped capacity C~_i = rho c(T_i) M~_i at node (i,j,k), in double precision;
+// hinges of the law that no active lane of the wave exceeds are skipped
+__device__ __forceinline__ double node_capacity(ConstLaw<double> &L, double T, int i, int j, int k,
+                                                int P, int NX, int NY, int NZ, double hx, double hy,
+                                                double hz)
+{
+    double c = L.c0;
+    if (L.n_hinge > 0 && __any(T > L.b[0])) {
+        if (L.n_hinge > 1 && __any(T > L.b[1])) {
+            int nh = 2;
+            while (nh < L.n_hinge && __any(T > L.b[nh])) ++nh;
+            for (int h = 0; h < nh; ++h) c = __builtin_fma(L.dc[h], fmax0(T - L.b[h], 0.0), c);
+        } else {
+            c = __builtin_fma(L.dc[0], fmax0(T - L.b[0], 0.0), c);
+        }
+    }
+    if (T >= L.Ts && T <= L.Tl) c += L.lat;
+    const double m = lumped_mass_1d(i, NX, P, hx) * lumped_mass_1d(j, NY, P, hy) *
+                     lumped_mass_1d(k, NZ, P, hz);
+    return L.rho * c * m;
+}
+
+
+// Stage the contributions of a cell that neighbours need: its x = 0 node plane
+// and its y = 0 node row (x = 1..P), NSH = (P+1)^2 + P (P+1) values per lane.
+template <int P, int kTPB, typename R>
+__device__ __forceinline__ void stage_shared(double *sS, const R *fe, int tid)
+{
+    constexpr int N = P + 1;
+#pragma unroll
+    for (int az = 0; az < N; ++az) {
+#pragma unroll
+        for (int ay = 0; ay < N; ++ay) sS[(az * N + ay) * kTPB + tid] = double(fe[(az * N + ay) * N]);
+#pragma unroll
+        for (int ax = 1; ax <= P; ++ax) sS[(N * N + az * P + ax - 1) * kTPB + tid] = double(fe[az * N * N + ax]);
+    }
+}
+
+// Owner-computes completion of the nodes of one cell layer in a column.  The
+// lane of cell (lx, ly) owns the nodes of its cell with local x and y in 1..P
+// (plus 0 on the column's low faces).  The sum order of every node is fixed:
+// carry (cells below), own, right, upper, diagonal neighbour.  Top-plane sums
+// are carried in sC to the next layer; nodes on column faces and segment ends
+// go to the slot array `slots` (already offset by the column parity); complete
+// nodes are handed to done(g, gi, gj, gk, ax, ay, az, f).
+template <int P, int kTY, typename R, typename Done>
+__device__ __forceinline__ void owner_nodes(const R *fe, const double *sS, double *sC, int tid, int lx,
+                                            int ly, int cx, int cy, int nx, int ny, int k0, bool first,
+                                            bool last, int NX, int NY, int NZ, double *slots,
+                                            long long NXY, Done &&done)
+{
+    constexpr int N = P + 1, kTPB = kTX * kTY;
+    const bool hasR = lx < kTX - 1 && cx + 1 < nx;
+    const bool hasU = ly < kTY - 1 && cy + 1 < ny;
+#pragma unroll
+    for (int az = 0; az < N; ++az) {
+#pragma unroll
+        for (int ay = 0; ay < N; ++ay) {
+#pragma unroll
+            for (int ax = 0; ax < N; ++ax) {
+                if ((ax == 0 && lx != 0) || (ay == 0 && ly != 0)) continue;
+                double f = 0.0;
+                if (az == 0 && !first) f = sC[(ay * N + ax) * kTPB + tid];
+                f += double(fe[(az * N + ay) * N + ax]);
+                if (ax == P && hasR) f += sS[(az * N + ay) * kTPB + tid + 1];
+                if (ay == P && hasU)
+                    f += ax == 0 ? sS[(az * N) * kTPB + tid + kTX]
+                                 : sS[(N * N + az * P + ax - 1) * kTPB + tid + kTX];
+                if (ax == P && ay == P && hasR && hasU) f += sS[(az * N) * kTPB + tid + kTX + 1];
+                if (az == P && !last) {  // top plane: completed by the next layer
+                    sC[(ay * N + ax) * kTPB + tid] = f;
+                    continue;
+                }
+                const int gi = P * cx + ax, gj = P * cy + ay, gk = k0 + az;
+                const long long g = (long long)gi + (long long)NX * gj + NXY * gk;
+                const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1) ||
+                                  is_face(gi, P * kTX, NX) || is_face(gj, P * kTY, NY);
+                if (face) {
+                    slots[g] = f;
+                    continue;
+                }
+                done(g, gi, gj, gk, ax, ay, az, f);
+            }
+        }
+    }
+}
+
+// Decode the index t of a column-face node (x-faces, then y-faces without
+// x-face nodes, then z segment ends without either) and list the columns and
+// segments that contain it.  Returns false for threads without a node.
+struct FaceNode {
+    int gi, gj, gk, n;  // node and number of containing columns/segments
+    int par[8];         // their parity slots, in a fixed order
+};
+__device__ __forceinline__ bool face_node(long long t, const HaloParams &h, FaceNode &fn)
+{
+    long long r = t;
+    int gi, gj, gk, grp;
+    if (r < h.GX) {
+        grp = 0;
+        gj = int(r % h.NY);
+        r /= h.NY;
+        gk = int(r % h.NZ);
+        gi = int(r / h.NZ + 1) * h.SX;
+    } else if ((r -= h.GX) < h.GY) {
+        grp = 1;
+        gi = int(r % h.NX);
+        r /= h.NX;
+        gk = int(r % h.NZ);
+        gj = int(r / h.NZ + 1) * h.SY;
+    } else if ((r -= h.GY) < h.GZ) {
+        grp = 2;
+        gi = int(r % h.NX);
+        r /= h.NX;
+        gj = int(r % h.NY);
+        gk = int(r / h.NY + 1) * h.SZ;
+    } else {
+        return false;
+    }
+    const bool fx = is_face(gi, h.SX, h.NX), fy = is_face(gj, h.SY, h.NY), fz = is_face(gk, h.SZ, h.NZ);
+    if (grp == 0 && !fx) return false;
+    if (grp >= 1 && fx) return false;
+    if (grp == 1 && !fy) return false;
+    if (grp == 2 && (fy || !fz)) return false;
+    int xs[2], ys[2], zs[2];
+    int nxs, nys, nzs;
+    if (fx) { xs[0] = gi / h.SX - 1; xs[1] = gi / h.SX; nxs = 2; } else { xs[0] = min(gi / h.SX, h.MX - 1); nxs = 1; }
+    if (fy) { ys[0] = gj / h.SY - 1; ys[1] = gj / h.SY; nys = 2; } else { ys[0] = min(gj / h.SY, h.MY - 1); nys = 1; }
+    if (fz) { zs[0] = gk / h.SZ - 1; zs[1] = gk / h.SZ; nzs = 2; } else { zs[0] = min(gk / h.SZ, h.MZ - 1); nzs = 1; }
+    int n = 0;
+    for (int a = 0; a < nzs; ++a)
+        for (int bb = 0; bb < nys; ++bb)
+            for (int e = 0; e < nxs; ++e)
+                fn.par[n++] = (xs[e] & 1) | ((ys[bb] & 1) << 1) | ((zs[a] & 1) << 2);
+    fn.gi = gi;
+    fn.gj = gj;
+    fn.gk = gk;
+    fn.n = n;
+    return true;
+}
+
+}  // namespace
+}  // namespace pbf

@@ -33,106 +33,10 @@
 // and segments (neighbours then share face nodes in the same L2).
 #include <hip/hip_runtime.h>
 
-#include "pbf_internal.h"
+#include "cellkit.h"
 
 namespace pbf {
 namespace {
-
-template <typename R> __device__ __forceinline__ R ffma(R a, R b, R c);
-template <> __device__ __forceinline__ double ffma<double>(double a, double b, double c)
-{
-    return __builtin_fma(a, b, c);
-}
-template <> __device__ __forceinline__ float ffma<float>(float a, float b, float c)
-{
-    return __builtin_fmaf(a, b, c);
-}
-// The material law is read through the constant address space: the loads are
-// scalar, cached in the scalar cache and known not to alias the history stores.
-template <typename R>
-using ConstLaw = const __attribute__((address_space(4))) Law<R>;
-template <typename R>
-__device__ __forceinline__ ConstLaw<R> &const_law(const Law<R> *p)
-{
-    return *(ConstLaw<R> *)p;
-}
-
-// Kernel parameters re-read inside the layer loop through a laundered pointer
-// to the kernel-argument segment (scalar loads near their uses) instead of
-// being held in scalar registers across the whole loop.
-template <typename T>
-using AS4 = const __attribute__((address_space(4))) T;
-template <typename T>
-__device__ __forceinline__ AS4<T> *kernarg_params()
-{
-    AS4<T> *kp = (AS4<T> *)__builtin_amdgcn_kernarg_segment_ptr();
-    asm volatile("" : "+s"(kp));
-    return kp;
-}
-
-template <typename R> __device__ __forceinline__ R fmax0(R a, R b) { return a > b ? a : b; }
-template <typename R> __device__ __forceinline__ R fmin0(R a, R b) { return a < b ? a : b; }
-
-// compile-time loop
-template <int B, int E, typename F>
-__device__ __forceinline__ void sfor(F &&f)
-{
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        sfor<B + 1, E>(f);
-    }
-}
-
-// acc + sum_i M(row, i) x(i), terms with an exactly zero coefficient dropped and
-// unit coefficients added without a multiply.
-template <class M, int row, int i, int N, bool started, typename R, typename X>
-__device__ __forceinline__ R rowdot(const X &x, R acc)
-{
-    if constexpr (i == N) {
-        if constexpr (started) return acc;
-        else return R(0);
-    } else {
-        constexpr double c = M::c(row, i);
-        if constexpr (c == 0.0) {
-            return rowdot<M, row, i + 1, N, started>(x, acc);
-        } else {
-            R xi = x(std::integral_constant<int, i>{});
-            R nacc;
-            if constexpr (!started) nacc = (c == 1.0) ? xi : R(c) * xi;
-            else nacc = (c == 1.0) ? acc + xi : ffma(R(c), xi, acc);
-            return rowdot<M, row, i + 1, N, true>(x, nacc);
-        }
-    }
-}
-
-// flat index of a (z,y,x) register tensor with extent N per direction; `a` runs
-// along direction DIM, (i, j) along the other two in increasing order
-template <int N, int DIM>
-__device__ constexpr int tidx(int a, int i, int j)
-{
-    if constexpr (DIM == 0) return (j * N + i) * N + a;
-    else if constexpr (DIM == 1) return (j * N + a) * N + i;
-    else return (a * N + j) * N + i;
-}
-
-// out = M applied along DIM (every line of the tensor)
-template <class M, int N, int DIM, typename R>
-__device__ __forceinline__ void sweep(const R *in, R *out)
-{
-    sfor<0, N>([&](auto ic) {
-        sfor<0, N>([&](auto jc) {
-            constexpr int I = decltype(ic)::value, J = decltype(jc)::value;
-            auto get = [&](auto ac) {
-                constexpr int A = decltype(ac)::value;
-                return in[tidx<N, DIM>(A, I, J)];
-            };
-            sfor<0, N>([&](auto oc) {
-                constexpr int O = decltype(oc)::value;
-                out[tidx<N, DIM>(O, I, J)] = rowdot<M, O, 0, N, false>(get, R(0));
-            });
-        });
-    });
-}
 
 // Flux and source at the Gauss points of one cell, accumulated into the
 // collocation-space integrand w.  FAST: at most one hinge of the law active, no
@@ -287,39 +191,6 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
     }
 }
 
-__device__ __forceinline__ bool on_dirichlet(unsigned m, int i, int j, int k, int NX, int NY, int NZ)
-{
-    return ((m & 1u) && i == 0) || ((m & 2u) && i == NX - 1) || ((m & 4u) && j == 0) ||
-           ((m & 8u) && j == NY - 1) || ((m & 16u) && k == 0) || ((m & 32u) && k == NZ - 1);
-}
-
-__device__ __forceinline__ bool is_face(int g, int S, int n)  // interior tile face
-{
-    return g > 0 && g < n - 1 && (g % S) == 0;
-}
-
-// lumped capacity C~_i = rho c(T_i) M~_i at node (i,j,k), in double precision;
-// hinges of the law that no active lane of the wave exceeds are skipped
-__device__ __forceinline__ double node_capacity(ConstLaw<double> &L, double T, int i, int j, int k,
-                                                int P, int NX, int NY, int NZ, double hx, double hy,
-                                                double hz)
-{
-    double c = L.c0;
-    if (L.n_hinge > 0 && __any(T > L.b[0])) {
-        if (L.n_hinge > 1 && __any(T > L.b[1])) {
-            int nh = 2;
-            while (nh < L.n_hinge && __any(T > L.b[nh])) ++nh;
-            for (int h = 0; h < nh; ++h) c = __builtin_fma(L.dc[h], fmax0(T - L.b[h], 0.0), c);
-        } else {
-            c = __builtin_fma(L.dc[0], fmax0(T - L.b[0], 0.0), c);
-        }
-    }
-    if (T >= L.Ts && T <= L.Tl) c += L.lat;
-    const double m = lumped_mass_1d(i, NX, P, hx) * lumped_mass_1d(j, NY, P, hy) *
-                     lumped_mass_1d(k, NZ, P, hz);
-    return L.rho * c * m;
-}
-
 // MODE 0: explicit step (fused update into Tout); MODE 1: assemble f and C~.
 //
 // Node ownership inside a column: the lane of cell (lx, ly) owns the nodes of
@@ -387,121 +258,47 @@ k_cells(const CellParams<R> p)
         R fe[NN];
         if (active) {
             cell_operator<P, R>(q, lawp, u, cx, cy, cz, fe);
-#pragma unroll
-            for (int az = 0; az < N; ++az) {
-#pragma unroll
-                for (int ay = 0; ay < N; ++ay) sS[(az * N + ay) * kTPB + tid] = double(fe[(az * N + ay) * N]);
-#pragma unroll
-                for (int ax = 1; ax <= P; ++ax)
-                    sS[(N * N + az * P + ax - 1) * kTPB + tid] = double(fe[az * N * N + ax]);
-            }
+            stage_shared<P, kTPB>(sS, fe, tid);
         }
         __syncthreads();
         // 3. owned nodes: sum, carry, completion
         if (active) {
-            const bool hasR = lx < kTX - 1 && cx + 1 < q.nx;
-            const bool hasU = ly < kTY - 1 && cy + 1 < q.ny;
-            const bool first = cz == z0, last = cz == z1 - 1;
-#pragma unroll
-            for (int az = 0; az < N; ++az) {
-#pragma unroll
-                for (int ay = 0; ay < N; ++ay) {
-#pragma unroll
-                    for (int ax = 0; ax < N; ++ax) {
-                        if ((ax == 0 && lx != 0) || (ay == 0 && ly != 0)) continue;
-                        double f = 0.0;
-                        if (az == 0 && !first) f = sC[(ay * N + ax) * kTPB + tid];
-                        f += double(fe[(az * N + ay) * N + ax]);
-                        if (ax == P && hasR) f += sS[(az * N + ay) * kTPB + tid + 1];
-                        if (ay == P && hasU)
-                            f += ax == 0 ? sS[(az * N) * kTPB + tid + kTX]
-                                         : sS[(N * N + az * P + ax - 1) * kTPB + tid + kTX];
-                        if (ax == P && ay == P && hasR && hasU) f += sS[(az * N) * kTPB + tid + kTX + 1];
-                        if (az == P && !last) {  // top plane: completed by the next layer
-                            sC[(ay * N + ax) * kTPB + tid] = f;
-                            continue;
-                        }
-                        const int gi = P * cx + ax, gj = P * cy + ay, gk = k0 + az;
-                        const long long g = (long long)gi + (long long)q.NX * gj + NXY * gk;
-                        const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < q.NZ - 1) ||
-                                          is_face(gi, P * kTX, q.NX) || is_face(gj, P * kTY, q.NY);
-                        if (face) {
-                            q.slots[tpar * NT + g] = f;
-                            continue;
-                        }
-                        const double T = sT[(az * BY + P * ly + ay) * BX + P * lx + ax];
-                        const double C = node_capacity(const_law(nlawp), T, gi, gj, gk, P, q.NX, q.NY,
-                                                       q.NZ, q.hx, q.hy, q.hz);
-                        if (MODE == 0) {
-                            q.Tout[g] = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ) ? q.T_D
-                                                                                            : T + q.dt * f / C;
-                        } else {
-                            q.fout[g] = f;
-                            q.Cout[g] = C;
-                        }
-                    }
+            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
+                                q.NX, q.NY, q.NZ, q.slots + tpar * NT, NXY,
+                                [&](long long g, int gi, int gj, int gk, int ax, int ay, int az, double f) {
+                const double T = sT[(az * BY + P * ly + ay) * BX + P * lx + ax];
+                const double C = node_capacity(const_law(nlawp), T, gi, gj, gk, P, q.NX, q.NY, q.NZ,
+                                               q.hx, q.hy, q.hz);
+                if (MODE == 0) {
+                    q.Tout[g] = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ) ? q.T_D
+                                                                                    : T + q.dt * f / C;
+                } else {
+                    q.fout[g] = f;
+                    q.Cout[g] = C;
                 }
-            }
+            });
         }
         __syncthreads();
     }
 }
 
-// Completion of the nodes on interior tile faces: fixed-order sum of the
-// parity-slot partials of the (up to 8) tiles that contain the node.
+// Completion of the nodes on column faces and segment ends: fixed-order sum of
+// the parity-slot partials of the (up to 8) columns/segments that contain them.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_halo(const HaloParams h)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long r = t;
-    int gi, gj, gk, grp;
-    if (r < h.GX) {  // x-faces: i = m*SX, m = 1..MX-1
-        grp = 0;
-        gj = int(r % h.NY);
-        r /= h.NY;
-        gk = int(r % h.NZ);
-        gi = int(r / h.NZ + 1) * h.SX;
-    } else if ((r -= h.GX) < h.GY) {  // y-faces without x-face nodes
-        grp = 1;
-        gi = int(r % h.NX);
-        r /= h.NX;
-        gk = int(r % h.NZ);
-        gj = int(r / h.NZ + 1) * h.SY;
-    } else if ((r -= h.GY) < h.GZ) {  // z-faces without x- or y-face nodes
-        grp = 2;
-        gi = int(r % h.NX);
-        r /= h.NX;
-        gj = int(r % h.NY);
-        gk = int(r / h.NY + 1) * h.SZ;
-    } else {
-        return;
-    }
-    const bool fx = is_face(gi, h.SX, h.NX), fy = is_face(gj, h.SY, h.NY);
-    if (grp == 0 && !fx) return;
-    if (grp >= 1 && fx) return;
-    if (grp == 1 && !fy) return;
-    if (grp == 2 && (fy || !is_face(gk, h.SZ, h.NZ))) return;
-    const bool fz = is_face(gk, h.SZ, h.NZ);
-    // tiles containing the node along each direction
-    int xs[2], ys[2], zs[2];
-    int nxs, nys, nzs;
-    if (fx) { xs[0] = gi / h.SX - 1; xs[1] = gi / h.SX; nxs = 2; } else { xs[0] = min(gi / h.SX, h.MX - 1); nxs = 1; }
-    if (fy) { ys[0] = gj / h.SY - 1; ys[1] = gj / h.SY; nys = 2; } else { ys[0] = min(gj / h.SY, h.MY - 1); nys = 1; }
-    if (fz) { zs[0] = gk / h.SZ - 1; zs[1] = gk / h.SZ; nzs = 2; } else { zs[0] = min(gk / h.SZ, h.MZ - 1); nzs = 1; }
-    const long long NXY = (long long)h.NX * h.NY, NT = NXY * h.NZ;
-    const long long g = (long long)gi + (long long)h.NX * gj + NXY * gk;
+    FaceNode fn;
+    if (!face_node((long long)blockIdx.x * blockDim.x + threadIdx.x, h, fn)) return;
+    const long long NT = (long long)h.NX * h.NY * h.NZ;
+    const long long g = (long long)fn.gi + (long long)h.NX * fn.gj + (long long)h.NX * h.NY * fn.gk;
     double f = 0.0;
-    for (int a = 0; a < nzs; ++a)
-        for (int bb = 0; bb < nys; ++bb)
-            for (int e = 0; e < nxs; ++e) {
-                const int par = (xs[e] & 1) | ((ys[bb] & 1) << 1) | ((zs[a] & 1) << 2);
-                f += h.slots[par * NT + g];
-            }
+    for (int a = 0; a < fn.n; ++a) f += h.slots[fn.par[a] * NT + g];
     const double T = h.Tin[g];
-    const double C = node_capacity(const_law(h.nlaw), T, gi, gj, gk, h.P, h.NX, h.NY, h.NZ, h.hx,
-                                   h.hy, h.hz);
+    const double C = node_capacity(const_law(h.nlaw), T, fn.gi, fn.gj, fn.gk, h.P, h.NX, h.NY, h.NZ,
+                                   h.hx, h.hy, h.hz);
     if (MODE == 0) {
-        h.Tout[g] = on_dirichlet(h.dmask, gi, gj, gk, h.NX, h.NY, h.NZ) ? h.T_D : T + h.dt * f / C;
+        h.Tout[g] = on_dirichlet(h.dmask, fn.gi, fn.gj, fn.gk, h.NX, h.NY, h.NZ) ? h.T_D
+                                                                                : T + h.dt * f / C;
     } else {
         h.fout[g] = f;
         h.Cout[g] = C;

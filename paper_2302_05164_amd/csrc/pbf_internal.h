@@ -113,6 +113,23 @@ struct CellParams {
     const Law<double> *nlaw;    // nodal capacity law (always double)
 };
 
+// Parameters of the Picard-operator kernels of the implicit step.
+struct PicardParams {
+    const double *Tc, *Tk, *x1, *x2;  // capacity temperature, conductivity temperature, inputs
+    double *yout;
+    const double *hist;  // consolidated fraction, lagged (read only)
+    double *slots;
+    int nx, ny, nz, NX, NY, NZ;
+    int MX, MY, MZ, ntiles, tiles_per_xcd, seg_len;
+    int hist_cz0, n_hist_cells;
+    double hx, hy, hz, Lz;
+    double detJ, ih2x, ih2y, ih2z, inv_dt;
+    unsigned dmask;
+    int src_on, laser_kind, src_cz0;
+    double xb, yb, src_amp, two_over_R2, h_powder;
+    const Law<double> *law;
+};
+
 // Parameters of the tile-face completion kernel.
 struct HaloParams {
     const double *Tin;
@@ -145,6 +162,10 @@ hipError_t launch_cells(int degree, int precision, int mode, int ty, const CellP
 int column_height();
 int resident_columns_per_cu(int ty);
 hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s);
+// implicit step (implicit.hip): mode 0 apply, 1 Jacobi diagonal
+int picard_column_height();
+hipError_t launch_picard(int degree, int mode, const PicardParams &pp, const HaloParams &hp,
+                         hipStream_t s);
 // vector kernels (vec.hip)
 hipError_t launch_fill(double *x, double v, long long n, hipStream_t s);
 hipError_t launch_init_dirichlet(double *T, const HaloParams &geom, double T_D, hipStream_t s);
@@ -157,5 +178,21 @@ hipError_t launch_power_update(const double *f, const double *C, double *v, doub
 hipError_t launch_power_scale(double *v, const double *scal, long long n, hipStream_t s);
 
 constexpr int kRedBlocks = 1024;  // blocks of the first reduction stage
+
+// device scalars of the CG iteration (offsets into the scalar array)
+enum { CG_RZ0 = 8, CG_RZ1 = 9, CG_RR = 10, CG_PAP = 11, CG_BN2 = 12, CG_DMAX = 13 };
+hipError_t launch_cg_start(const double *y, const double *diag, double *r, double *z, double *p,
+                           double *x, double *partials, double *scal, const HaloParams &geom,
+                           long long n, hipStream_t s);
+hipError_t launch_cg_pap(const double *p, const double *Ap, double *partials, double *scal,
+                         long long n, hipStream_t s);
+hipError_t launch_cg_update(double *x, double *r, double *z, const double *p, const double *Ap,
+                            const double *diag, double *partials, double *scal, int rz_old,
+                            long long n, hipStream_t s);
+hipError_t launch_cg_direction(double *p, const double *z, const double *scal, int rz_old, int rz_new,
+                               long long n, hipStream_t s);
+hipError_t launch_picard_update(double *Ti, const double *x, double *partials, double *scal,
+                                const HaloParams &geom, long long n, hipStream_t s);
+hipError_t launch_sub(double *d, const double *a, const double *b, long long n, hipStream_t s);
 
 }  // namespace pbf

@@ -100,14 +100,128 @@ __global__ void __launch_bounds__(kRedThreads) k_power_update(const double *f, c
     if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
 }
 
-// out[c] = sum over blocks of partials[b*nv + c], in block order
-__global__ void k_finish(const double *partials, int nblocks, int nv, double *out)
+// out[c] = sum over blocks of partials[b*stride + c], c < ncomp: each thread
+// adds a fixed strided subset in order, then a fixed tree (deterministic);
+// MAXR: maximum instead of sum
+template <bool MAXR>
+__global__ void __launch_bounds__(kRedThreads) k_finish(const double *partials, int nblocks, int stride,
+                                                        int ncomp, double *out)
 {
-    const int c = threadIdx.x;
-    if (c >= nv) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[b * nv + c];
-    out[c] = s;
+    __shared__ double sh[kRedThreads];
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
+            const double v = partials[b * stride + c];
+            s = MAXR ? fmax(s, v) : s + v;
+        }
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                sh[threadIdx.x] = MAXR ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = sh[0];
+        __syncthreads();
+    }
+}
+
+// CG: r = -y (free) or 0, x = 0, z = r/diag, p = z; partials of r.z, r.r
+__global__ void __launch_bounds__(kRedThreads) k_cg_start(const double *y, const double *diag, double *r,
+                                                           double *z, double *p, double *x,
+                                                           double *partials, const HaloParams h,
+                                                           long long n)
+{
+    double s[2] = {0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        const double ri = node_dirichlet(i, h) ? 0.0 : -y[i];
+        const double zi = ri / diag[i];
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+        x[i] = 0.0;
+        s[0] += ri * zi;
+        s[1] += ri * ri;
+    }
+    block_sum<2>(s);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s[0];
+        partials[2 * blockIdx.x + 1] = s[1];
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_dot(const double *a, const double *b, double *partials,
+                                                      long long n)
+{
+    double s[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads)
+        s[0] += a[i] * b[i];
+    block_sum<1>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// alpha = rz/pAp; x += alpha p; r -= alpha Ap; z = r/diag; partials of r.z, r.r
+__global__ void __launch_bounds__(kRedThreads) k_cg_update(double *x, double *r, double *z, const double *p,
+                                                            const double *Ap, const double *diag,
+                                                            double *partials, const double *scal,
+                                                            int rz_old, long long n)
+{
+    const double alpha = scal[rz_old] / scal[CG_PAP];
+    double s[2] = {0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * Ap[i];
+        const double zi = ri / diag[i];
+        r[i] = ri;
+        z[i] = zi;
+        s[0] += ri * zi;
+        s[1] += ri * ri;
+    }
+    block_sum<2>(s);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s[0];
+        partials[2 * blockIdx.x + 1] = s[1];
+    }
+}
+
+// beta = rz_new/rz_old; p = z + beta p
+__global__ void k_cg_direction(double *p, const double *z, const double *scal, int rz_old, int rz_new,
+                               long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double beta = scal[rz_new] / scal[rz_old];
+    p[i] = z[i] + beta * p[i];
+}
+
+// T^{i+1} = T^i + x on free nodes; partial maxima of |x| there
+__global__ void __launch_bounds__(kRedThreads) k_picard_update(double *Ti, const double *x, double *partials,
+                                                                const HaloParams h, long long n)
+{
+    double m = 0.0;
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        if (node_dirichlet(i, h)) continue;
+        Ti[i] += x[i];
+        m = fmax(m, fabs(x[i]));
+    }
+    __shared__ double sh[kRedThreads];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sub(double *d, const double *a, const double *b, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = a[i] - b[i];
 }
 
 __global__ void k_power_scale(double *v, const double *scal, long long n)
@@ -155,7 +269,7 @@ hipError_t launch_power_dots(const double *f, const double *C, const double *v, 
 {
     hipLaunchKernelGGL(k_power_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, f, C, v, partials,
                        geom, n);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partials, kRedBlocks, 2, scal);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 2, 2, scal);
     return hipGetLastError();
 }
 
@@ -164,13 +278,76 @@ hipError_t launch_power_update(const double *f, const double *C, double *v, doub
 {
     hipLaunchKernelGGL(k_power_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, f, C, v, partials,
                        geom, n);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partials, kRedBlocks, 1, scal + 2);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 1, 1, scal + 2);
     return hipGetLastError();
 }
 
 hipError_t launch_power_scale(double *v, const double *scal, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_power_scale, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, scal, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const double *y, const double *diag, double *r, double *z, double *p,
+                           double *x, double *partials, double *scal, const HaloParams &geom,
+                           long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(kRedThreads), 0, s, y, diag, r, z, p, x,
+                       partials, geom, n);
+    // rz -> CG_RZ0, rr -> CG_RR; the initial rr is also kept as ||b||^2
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 2, 1,
+                       scal + CG_RZ0);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials + 1, kRedBlocks, 2, 1,
+                       scal + CG_RR);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials + 1, kRedBlocks, 2, 1,
+                       scal + CG_BN2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_pap(const double *p, const double *Ap, double *partials, double *scal,
+                         long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, p, Ap, partials, n);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 1, 1,
+                       scal + CG_PAP);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double *x, double *r, double *z, const double *p, const double *Ap,
+                            const double *diag, double *partials, double *scal, int rz_old,
+                            long long n, hipStream_t s)
+{
+    const int rz_new = rz_old == CG_RZ0 ? CG_RZ1 : CG_RZ0;
+    hipLaunchKernelGGL(k_cg_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, r, z, p, Ap, diag,
+                       partials, scal, rz_old, n);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 2, 1,
+                       scal + rz_new);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials + 1, kRedBlocks, 2, 1,
+                       scal + CG_RR);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(double *p, const double *z, const double *scal, int rz_old, int rz_new,
+                               long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_direction, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, z, scal, rz_old,
+                       rz_new, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_picard_update(double *Ti, const double *x, double *partials, double *scal,
+                                const HaloParams &geom, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_picard_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, Ti, x, partials,
+                       geom, n);
+    hipLaunchKernelGGL(k_finish<true>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 1, 1,
+                       scal + CG_DMAX);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(double *d, const double *a, const double *b, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, a, b, n);
     return hipGetLastError();
 }
 

@@ -68,6 +68,8 @@ SIGNATURES = {
     "pbf_explicit_steps": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp],
     "pbf_assemble": [_vp, _vp, _vp, C.c_double, _vp, _vp, C.c_int, _vp],
     "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
+    "pbf_implicit_step": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int,
+                          C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _vp],
     "pbf_timing_begin": [_vp, C.c_int],
     "pbf_timing_end": [_vp, _dp, _dp, _i64p],
 }
@@ -219,6 +221,22 @@ class Simulation:
                                                   C.byref(lam), self._stream()))
         return lam.value
 
+
+    def implicit_step(self, T_n, rc, t, dt, cg_rtol=1e-10, cg_max_it=10000, picard_tol=1e-8,
+                      picard_max_it=30, T_out=None, check=True):
+        i = self.info()
+        if T_out is None:
+            T_out = torch.empty_like(T_n)
+        it, pit, res = C.c_int(0), C.c_int(0), C.c_double(0)
+        st = self.lib.pbf_implicit_step(
+            self.ctx, _f64(T_n, i["n_dofs"], "T_n"), _f64(T_out, i["n_dofs"], "T_out"),
+            _ptr(rc) if i["n_hist_qp"] else None, float(t), float(dt), float(cg_rtol), int(cg_max_it),
+            float(picard_tol), int(picard_max_it), C.byref(it), C.byref(pit), C.byref(res),
+            self._stream())
+        info = dict(status=st, cg_iters=it.value, picard_iters=pit.value, rel_res=res.value)
+        if check and st != 0:
+            self._check(st)
+        return T_out, info
 
     def timing_begin(self, max_steps):
         self._check(self.lib.pbf_timing_begin(self.ctx, int(max_steps)))
