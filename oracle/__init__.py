@@ -83,7 +83,7 @@ def lib():
                                        C.POINTER(C.c_int), _dp]
         L.or_probe.argtypes = [P, _dp, C.c_int, _dp, _dp]
         L.or_adjoint_run.argtypes = [P, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp,
-                                     _dp, _dp, _dp]
+                                     _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -207,14 +207,20 @@ class Oracle:
         self.L.or_probe(C.byref(self.s), _ptr(np.ascontiguousarray(T)), len(pts), _ptr(pts), _ptr(vals))
         return vals
 
-    def adjoint(self, T0, t0, dt, n_steps, pts, targets):
+    def adjoint(self, T0, t0, dt, n_steps, pts, targets, with_lam0=False):
+        """J, dJ/dW_eff per track and T_N (and dJ/dT_0 if with_lam0) of n_steps
+        explicit steps from T0 and the initial history."""
         pts = np.ascontiguousarray(pts, dtype=np.float64)
         tg = np.ascontiguousarray(targets, dtype=np.float64)
         J = C.c_double(0)
         dW = np.zeros(max(1, self.s.n_tracks))
         TN = np.zeros(self.N)
+        lam0 = np.zeros(self.N) if with_lam0 else None
         self.L.or_adjoint_run(C.byref(self.s), _ptr(np.ascontiguousarray(T0)), t0, dt, n_steps,
-                              len(pts), _ptr(pts), _ptr(tg), C.byref(J), _ptr(dW), _ptr(TN))
+                              len(pts), _ptr(pts), _ptr(tg), C.byref(J), _ptr(dW), _ptr(TN),
+                              _ptr(lam0) if with_lam0 else None)
+        if with_lam0:
+            return J.value, dW[: self.s.n_tracks], TN, lam0
         return J.value, dW[: self.s.n_tracks], TN
 
     # -- scalar material law and laser (for pins) ------------------------------------

@@ -777,7 +777,7 @@ int or_probe(const or_problem *P, const double *T, int n, const double *pts, dou
  * depends on the nodal temperature only: dC~_i/dT_i = rho c'(T_i) M~_i. */
 int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, int n_steps,
                    int n_probes, const double *pts, const double *targets, double *J,
-                   double *dJ_dW, double *T_final)
+                   double *dJ_dW, double *T_final, double *lam0)
 {
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
     if (!R || make_ref(P->degree, R)) { free(R); return -1; }
@@ -911,6 +911,7 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
         lam = lam_new;
         lam_new = tmp;
     }
+    if (lam0) memcpy(lam0, lam, sizeof(double) * N); /* dJ/dT_0 */
     free(Ts); free(Rs); free(f); free(C); free(lam); free(lam_new); free(mu); free(a);
     free(R);
     return 0;

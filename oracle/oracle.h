@@ -76,7 +76,7 @@ int or_implicit_step(const or_problem *P, const double *Tn, double *rc, double t
 int or_probe(const or_problem *P, const double *T, int n, const double *pts, double *vals);
 int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, int n_steps,
                    int n_probes, const double *pts, const double *targets,
-                   double *J, double *dJ_dW, double *T_final);
+                   double *J, double *dJ_dW, double *T_final, double *lam0);
 
 #ifdef __cplusplus
 }

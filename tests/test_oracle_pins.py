@@ -534,6 +534,28 @@ def test_adjoint_matches_central_differences(kind, rel, tol):
         assert abs(A * dW[k] - fd) <= tol * abs(fd)
 
 
+# (case, FD step in K, tolerance): J is quadratic in T_0 for constant
+# coefficients, so central differences are exact up to round-off there.
+@pytest.mark.parametrize("kind,eps,tol", [("linear", 1.0, 1e-8), ("full", 1e-5, 1e-5)])
+def test_adjoint_initial_state_gradient_matches_central_differences(kind, eps, tol):
+    """<dJ/dT_0, v> from the adjoint against central differences of J along
+    seeded directions v over all nodes (Dirichlet nodes included: the first
+    step reads them before they are reset)."""
+    prob = _adjoint_case(kind)
+    o = Oracle(prob)
+    T0 = o.init_T() + 50.0 * W.seeded_vector(o.N, 11)
+    dt, n = 2.5e-6, 60
+    J, dW, TN, lam0 = o.adjoint(T0, 0.0, dt, n, prob.probes, prob.targets, with_lam0=True)
+    if kind != "linear":
+        assert TN.max() > prob.T_l
+    for seed in (21, 22):
+        v = W.seeded_vector(o.N, seed)
+        Jp = o.adjoint(T0 + eps * v, 0.0, dt, n, prob.probes, prob.targets)[0]
+        Jm = o.adjoint(T0 - eps * v, 0.0, dt, n, prob.probes, prob.targets)[0]
+        fd = (Jp - Jm) / (2 * eps)
+        assert abs(np.dot(lam0, v) - fd) <= tol * abs(fd)
+
+
 def test_adjoint_linear_case_exact_response():
     """Constant coefficients: T_N is affine in the track powers, so
     dJ/dW_k = 2 sum_p (T_p - T*_p) R_pk with R_pk the probe response to a unit
