@@ -5,7 +5,8 @@
  * powder-bed-fusion model with sum factorization on uniform boxes of Lagrange
  * Q1/Q2 hexahedra, and drives it with lumped-mass forward-Euler steps, a
  * backward-Euler step solved by matrix-free Jacobi-preconditioned CG, a
- * stability estimate, probes and a discrete adjoint step.  The mathematics is
+ * stability estimate, probes, and the discrete adjoint of the explicit scheme
+ * with binomial checkpointing.  The mathematics is
  * that of Proell et al., "A highly efficient computational approach for
  * part-scale thermal modeling of metal powder bed fusion" (arXiv 2302.05164):
  * the model of Section 2, the discretization and time stepping of Section 3,
@@ -175,6 +176,79 @@ pbf_status pbf_implicit_step(pbf_ctx *ctx, const double *T_n, double *T_out, dou
                              double dt, double cg_rtol, int cg_max_it, double picard_tol,
                              int picard_max_it, int *cg_iters_total, int *picard_iters,
                              double *final_rel_res, void *stream);
+
+/* ---- probes and objective (Section 3.1, eq. bubnov_galerkin) -----------------
+ * pbf_set_probes: n points (host array pts[3n], inside the box) and targets
+ * (host array of n, may be NULL for zeros), n in [0, 4096], copied and uploaded
+ * into the workspace; needs a bound device.  A point on a face shared by two
+ * cells is taken in the cell of lower index.  Synchronizes.
+ * pbf_probe: vals[p] = T_h(x_p) = sum_a N_a(x_p) T_a, device array of n.
+ * pbf_objective: J[0] = sum_p (T_h(x_p) - target_p)^2 (device scalar) and
+ * lam = dJ/dT (device array of n_dofs, overwritten).  Asynchronous. */
+pbf_status pbf_set_probes(pbf_ctx *ctx, int n, const double *pts, const double *targets, void *stream);
+pbf_status pbf_probe(pbf_ctx *ctx, const double *T, double *vals, void *stream);
+pbf_status pbf_objective(pbf_ctx *ctx, const double *T, double *J, double *lam, void *stream);
+
+/* ---- discrete adjoint of the explicit scheme -------------------------------------
+ * Reverse of one step of eq. forward_euler (Section 3.2) with the law of
+ * Section 2: the step maps (T_n, r^{n-1}) to r^n = max(r^{n-1}, g(T_n)) and
+ * T_{n+1} = T_n + dt f(T_n, r^n)/C~(T_n).  Given lambda_{n+1} = dJ/dT_{n+1} and
+ * mu_n = dJ/dr^n from later steps, pbf_adjoint_step writes lambda_n = dJ/dT_n
+ * into lam (n_dofs, must not overlap lam_next), replaces mu (n_hist_qp) by
+ * mu_{n-1}, and adds the sensitivity of J to the effective power W_eff of the
+ * track active at t_n to dJdW[track] (device array of n_tracks).  T_n and
+ * rc_prev = r^{n-1} are the step's input state (read only).  Derivative
+ * conventions at non-smooth points: the slope of the table segment that the
+ * forward evaluation used (zero outside the table), g' = 1/(T_l - T_s) on the
+ * open melting interval, no derivative of the latent-heat box, and the max
+ * passes the adjoint to T where g(T) > r^{n-1} (to r^{n-1} otherwise, ties
+ * included).  FP64.  Uses the workspace f/C scratch.  Asynchronous. */
+pbf_status pbf_adjoint_step(pbf_ctx *ctx, const double *T_n, const double *rc_prev,
+                            const double *lam_next, double *lam, double *mu, double t_n, double dt,
+                            double *dJdW, void *stream);
+
+/* ---- binomial checkpointing (reverse of n_steps explicit steps) ----------------
+ * Schedule of a reversal with n_snaps state slots (slot 0 holds the initial
+ * state): the repetition number r is the smallest with C(n_snaps + r, r) >=
+ * n_steps and the number of forward steps is r n_steps - C(n_snaps + r, r - 1),
+ * the minimum for that memory (Griewank's binomial checkpointing).  Actions:
+ *   ADVANCE(step):  forward steps from the current state up to `step`;
+ *   STORE(step, slot): copy the current state (step) into `slot`;
+ *   RESTORE(step, slot): make the state in `slot` (step) current;
+ *   TURN(step):     adjoint step at the current state `step`.
+ * TURN steps come in the order n_steps-1, ..., 0.  Host only: pbf_revolve_schedule
+ * counts (actions may be NULL) or lists at most max_actions actions. */
+#define PBF_ACT_ADVANCE 1
+#define PBF_ACT_STORE 2
+#define PBF_ACT_RESTORE 3
+#define PBF_ACT_TURN 4
+typedef struct {
+    int kind, step, slot;
+} pbf_revolve_action;
+pbf_status pbf_revolve_schedule(int n_steps, int n_snaps, pbf_revolve_action *actions,
+                                int max_actions, int *n_actions, int64_t *n_advances);
+
+/* Gradient of J(T_N) (pbf_objective with the current probes) after n_steps
+ * explicit FP64 steps from (T0, rc0) at time t0, with respect to the track
+ * powers and the absorptivity, by the adjoint steps above under the binomial
+ * schedule with n_snaps slots held in the caller's device buffer `work`
+ * (pbf_adjoint_work_bytes; 256-byte aligned).
+ * pbf_gradient_forward: runs the forward sweep (taking the snapshots), the
+ * last step and the objective: T_N (n_dofs, may be NULL) and J (device scalar,
+ * may be NULL).  T0/rc0 are read only.
+ * pbf_gradient_backward: with the same work buffer and arguments, runs the
+ * reversal: dJdW[k] (device, n_tracks) = dJ/dW_eff,k, dJdP[k] = A dJdW[k]
+ * (track powers P), dJdA[0] = sum_k P_k dJdW[k] (absorptivity A),
+ * lam0 = dJ/dT0 (n_dofs); any output may be NULL.  n_advances (host, may be
+ * NULL) receives the forward steps of both sweeps.  Asynchronous, except that
+ * the forward sweep synchronizes once to upload the powers. */
+pbf_status pbf_adjoint_work_bytes(const pbf_ctx *ctx, int n_snaps, size_t *bytes);
+pbf_status pbf_gradient_forward(pbf_ctx *ctx, const double *T0, const double *rc0, double t0,
+                                double dt, int n_steps, int n_snaps, void *work, size_t work_bytes,
+                                double *T_N, double *J, void *stream);
+pbf_status pbf_gradient_backward(pbf_ctx *ctx, double t0, double dt, int n_steps, int n_snaps,
+                                 void *work, size_t work_bytes, double *dJdW, double *dJdP,
+                                 double *dJdA, double *lam0, int64_t *n_advances, void *stream);
 
 /* ---- kernel timing (instrumentation) ------------------------------------------
  * pbf_timing_begin: from now on pbf_explicit_steps records HIP events on the

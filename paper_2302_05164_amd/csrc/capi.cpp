@@ -47,7 +47,22 @@ struct pbf_ctx {
     double *d_slots = nullptr;
     double *d_f = nullptr, *d_C = nullptr, *d_v = nullptr, *d_partials = nullptr, *d_scal = nullptr;
     double *d_cg[8] = {};  // implicit step: y, diag, r, z, p, Ap, x, d
+    double *d_tiles = nullptr;  // adjoint: per-tile source sensitivities
+    int *d_probe_cell = nullptr;
+    double *d_probe_xi = nullptr, *d_probe_target = nullptr;
     bool laws_dirty = true;
+    // probes: containing cell, reference coordinates and target of each point
+    std::vector<int> probe_cell;
+    std::vector<double> probe_xi, probe_target;
+    bool probes_dirty = false;
+    // last gradient forward sweep (checked by the backward sweep)
+    struct {
+        const void *work = nullptr;
+        int n_steps = 0, n_snaps = 0;
+        double t0 = 0, dt = 0;
+        long long forward_advances = 0;
+        bool valid = false;
+    } grad;
     Law<double> h_law64{}, h_lin64{};
     Law<float> h_law32{};
     // kernel timing: 3 events per timed step (before cells, between, after faces)
@@ -95,6 +110,8 @@ long long n_hist_qp(const pbf_ctx *c)
 }
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kMaxProbes = 4096;
 
 double gauss_point(int degree, int i)
 {
@@ -260,6 +277,17 @@ HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
     return h;
 }
 
+HaloParams adjoint_geometry(const pbf_ctx *c)
+{
+    return geometry(c, adjoint_column_height(), adjoint_resident_columns_per_cu());
+}
+
+long long adjoint_tiles(const pbf_ctx *c)
+{
+    const HaloParams h = adjoint_geometry(c);
+    return (long long)h.MX * h.MY * h.MZ;
+}
+
 template <typename R>
 CellParams<R> cell_params(const pbf_ctx *c, const Law<R> *law, bool history)
 {
@@ -278,6 +306,7 @@ CellParams<R> cell_params(const pbf_ctx *c, const Law<R> *law, bool history)
     p.tiles_per_xcd = ceil_div(p.ntiles, 8);
     p.seg_len = h.SZ / c->degree;
     p.hist_cz0 = history ? c->nz - c->hist_layers : c->nz;
+    p.hist_write = 1;
     p.n_hist_cells = (int)n_hist_cells(c);
     p.hx = c->L[0] / c->nx;
     p.hy = c->L[1] / c->ny;
@@ -340,7 +369,7 @@ pbf_status upload_laws(pbf_ctx *c, hipStream_t s)
 // one operator pass: MODE 0 explicit step Tin -> Tout, MODE 1 assemble into f, C
 pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const double *Tin,
                          double *Tout, double *f, double *C, double *rc, double t, double dt,
-                         hipStream_t s)
+                         hipStream_t s, bool hist_write = true)
 {
     CellParams<double> pd{};
     CellParams<float> pf{};
@@ -352,6 +381,7 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const
         pd.Cout = C;
         pd.hist = rc;
         pd.dt = dt;
+        pd.hist_write = hist_write ? 1 : 0;
         if (!linear) set_beam(c, pd, t);
     } else {
         pf = cell_params<float>(c, c->d_law32, true);
@@ -361,6 +391,7 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const
         pf.Cout = C;
         pf.hist = rc;
         pf.dt = dt;
+        pf.hist_write = hist_write ? 1 : 0;
         set_beam(c, pf, t);
     }
     if (linear) pd.nlaw = c->d_lin64;
@@ -435,6 +466,183 @@ PicardParams picard_params(const pbf_ctx *c, const HaloParams &h, const double *
     }
     q.law = c->d_law64;
     return q;
+}
+
+// ---- probes and adjoint ------------------------------------------------------
+
+ProbeSet probe_set(const pbf_ctx *c)
+{
+    ProbeSet ps{};
+    ps.cell = c->d_probe_cell;
+    ps.xi = c->d_probe_xi;
+    ps.target = c->d_probe_target;
+    ps.n = (int)c->probe_target.size();
+    ps.P = c->degree;
+    ps.NX = (int)nodes1(c, 0);
+    ps.NY = (int)nodes1(c, 1);
+    ps.NXY = (long long)ps.NX * ps.NY;
+    return ps;
+}
+
+pbf_status upload_probes(pbf_ctx *c, hipStream_t s)
+{
+    if (!c->probes_dirty) return PBF_OK;
+    const size_t n = c->probe_target.size();
+    if (n > 0) {
+        PBF_HIP(c, hipMemcpyAsync(c->d_probe_cell, c->probe_cell.data(), 3 * n * sizeof(int),
+                                  hipMemcpyHostToDevice, s));
+        PBF_HIP(c, hipMemcpyAsync(c->d_probe_xi, c->probe_xi.data(), 3 * n * sizeof(double),
+                                  hipMemcpyHostToDevice, s));
+        PBF_HIP(c, hipMemcpyAsync(c->d_probe_target, c->probe_target.data(), n * sizeof(double),
+                                  hipMemcpyHostToDevice, s));
+        PBF_HIP(c, hipStreamSynchronize(s));
+    }
+    c->probes_dirty = false;
+    return PBF_OK;
+}
+
+AdjointParams adjoint_params(const pbf_ctx *c, const HaloParams &h, const double *T, const double *rc,
+                             const double *lam_next, double *lam, double *mu, double dt, const Beam &bm)
+{
+    AdjointParams a{};
+    a.T = T;
+    a.lam = lam_next;
+    a.C = c->d_C;
+    a.f = c->d_f;
+    a.lam_out = lam;
+    a.hist = rc;
+    a.mu = mu;
+    a.slots = c->d_slots;
+    a.partials = c->d_tiles;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.NX = h.NX;
+    a.NY = h.NY;
+    a.NZ = h.NZ;
+    a.MX = h.MX;
+    a.MY = h.MY;
+    a.MZ = h.MZ;
+    a.ntiles = h.MX * h.MY * h.MZ;
+    a.tiles_per_xcd = ceil_div(a.ntiles, 8);
+    a.seg_len = h.SZ / c->degree;
+    a.hist_cz0 = c->nz - c->hist_layers;
+    a.n_hist_cells = (int)n_hist_cells(c);
+    a.hx = c->L[0] / c->nx;
+    a.hy = c->L[1] / c->ny;
+    a.hz = c->L[2] / c->nz;
+    a.Lz = c->L[2];
+    a.detJ = a.hx * a.hy * a.hz;
+    a.ih2x = 1.0 / (a.hx * a.hx);
+    a.ih2y = 1.0 / (a.hy * a.hy);
+    a.ih2z = 1.0 / (a.hz * a.hz);
+    a.dt = dt;
+    a.dmask = c->dmask;
+    a.laser_kind = c->laser_kind;
+    const double depth_cells = (c->L[2] - c->h_powder) / a.hz;
+    a.src_cz0 = std::max(0, (int)std::floor(depth_cells) - 1);
+    a.h_powder = c->h_powder;
+    a.two_over_R2 = c->radius > 0 ? 2.0 / (c->radius * c->radius) : 0.0;
+    a.src_on = bm.on ? 1 : 0;
+    if (bm.on) {
+        const double PI = 3.14159265358979323846, R2 = c->radius * c->radius;
+        a.xb = bm.xb;
+        a.yb = bm.yb;
+        a.src_unit = c->laser_kind == 1 ? 2.0 / (PI * R2 * c->h_powder) : 2.0 / (PI * R2);
+    }
+    a.law = c->d_law64;
+    return a;
+}
+
+// one reverse step at state (T, rc = r^{n-1}), time t
+pbf_status adjoint_step(pbf_ctx *c, const double *T, const double *rc, const double *lam_next, double *lam,
+                        double *mu, double t, double dt, double *dJdW, hipStream_t s)
+{
+    // f and C~ of the forward step, history read but not written
+    pbf_status st = operator_pass(c, 1, PBF_PREC_FP64, false, T, nullptr, c->d_f, c->d_C,
+                                  const_cast<double *>(rc), t, 0.0, s, false);
+    if (st) return st;
+    const Beam bm = beam_at(c, t);
+    HaloParams h = adjoint_geometry(c);
+    h.Tin = T;
+    h.dt = dt;
+    const AdjointParams ap = adjoint_params(c, h, T, rc, lam_next, lam, mu, dt, bm);
+    PBF_HIP(c, launch_adjoint(c->degree, ap, h, s));
+    if (bm.on) PBF_HIP(c, launch_adjoint_finish(c->d_tiles, ap.ntiles, dJdW, bm.track, s));
+    return PBF_OK;
+}
+
+// device buffer of the checkpointed gradient
+struct GradWork {
+    double *snapT, *snapR, *Tcur, *Ttmp, *rcur, *rtmp, *lam, *lam2, *mu, *dJdW, *powers, *J;
+    size_t bytes;
+};
+
+GradWork grad_layout(const pbf_ctx *c, int n_snaps, char *base)
+{
+    const size_t N = (size_t)n_dofs(c), H = (size_t)std::max(n_hist_qp(c), 1LL),
+                 K = std::max<size_t>(c->tracks.size(), 1);
+    GradWork w{};
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        double *p = base ? (double *)(base + off) : nullptr;
+        off += align256(n * sizeof(double));
+        return p;
+    };
+    w.snapT = take((size_t)n_snaps * N);
+    w.snapR = take((size_t)n_snaps * H);
+    w.Tcur = take(N);
+    w.Ttmp = take(N);
+    w.rcur = take(H);
+    w.rtmp = take(H);
+    w.lam = take(N);
+    w.lam2 = take(N);
+    w.mu = take(H);
+    w.dJdW = take(K);
+    w.powers = take(K);
+    w.J = take(1);
+    w.bytes = off;
+    return w;
+}
+
+// execute schedule actions [i0, i1) from state `cur`; TURN actions run adjoint steps
+pbf_status run_actions(pbf_ctx *c, const std::vector<pbf_revolve_action> &acts, size_t i0, size_t i1,
+                       const GradWork &w, int &cur, double *&lam, double *&lam2, double t0, double dt,
+                       hipStream_t s)
+{
+    const size_t N = (size_t)n_dofs(c), H = (size_t)n_hist_qp(c);
+    for (size_t i = i0; i < i1; ++i) {
+        const pbf_revolve_action &a = acts[i];
+        if (a.kind == PBF_ACT_ADVANCE) {
+            double *x = w.Tcur, *y = w.Ttmp;
+            for (int n = cur; n < a.step; ++n) {
+                pbf_status st = operator_pass(c, 0, PBF_PREC_FP64, false, x, y, nullptr, nullptr,
+                                              H ? w.rcur : nullptr, t0 + n * dt, dt, s);
+                if (st) return st;
+                std::swap(x, y);
+            }
+            if (x != w.Tcur) PBF_HIP(c, hipMemcpyAsync(w.Tcur, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            cur = a.step;
+        } else if (a.kind == PBF_ACT_STORE) {
+            PBF_HIP(c, hipMemcpyAsync(w.snapT + (size_t)a.slot * N, w.Tcur, N * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+            if (H) PBF_HIP(c, hipMemcpyAsync(w.snapR + (size_t)a.slot * H, w.rcur, H * sizeof(double),
+                                             hipMemcpyDeviceToDevice, s));
+        } else if (a.kind == PBF_ACT_RESTORE) {
+            PBF_HIP(c, hipMemcpyAsync(w.Tcur, w.snapT + (size_t)a.slot * N, N * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+            if (H) PBF_HIP(c, hipMemcpyAsync(w.rcur, w.snapR + (size_t)a.slot * H, H * sizeof(double),
+                                             hipMemcpyDeviceToDevice, s));
+            cur = a.step;
+        } else if (a.kind == PBF_ACT_TURN) {
+            if (cur != a.step) return fail(c, PBF_ESTATE, "checkpoint schedule out of step (%d vs %d)", cur, a.step);
+            pbf_status st = adjoint_step(c, w.Tcur, H ? w.rcur : nullptr, lam, lam2, H ? w.mu : nullptr,
+                                         t0 + a.step * dt, dt, w.dJdW, s);
+            if (st) return st;
+            std::swap(lam, lam2);
+        }
+    }
+    return PBF_OK;
 }
 
 }  // namespace
@@ -600,6 +808,8 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     b += 11 * align256(N * sizeof(double));       // f, C, v; implicit: y, diag, r, z, p, Ap, x, d
     b += align256(kRedBlocks * 4 * sizeof(double)); // reduction partials
     b += align256(64 * sizeof(double));           // device scalars
+    b += align256(adjoint_tiles(c) * sizeof(double));  // adjoint tile partials
+    b += align256(3 * kMaxProbes * sizeof(int)) + align256(4 * kMaxProbes * sizeof(double));
     *bytes = b;
     return PBF_OK;
 }
@@ -636,6 +846,14 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     c->d_partials = (double *)p;
     p += align256(kRedBlocks * 4 * sizeof(double));
     c->d_scal = (double *)p;
+    p += align256(64 * sizeof(double));
+    c->d_tiles = (double *)p;
+    p += align256(adjoint_tiles(c) * sizeof(double));
+    c->d_probe_cell = (int *)p;
+    p += align256(3 * kMaxProbes * sizeof(int));
+    c->d_probe_xi = (double *)p;
+    c->d_probe_target = c->d_probe_xi + 3 * kMaxProbes;
+    c->probes_dirty = !c->probe_target.empty();
     c->ws = (char *)workspace;
     c->ws_bytes = bytes;
     c->bound = true;
@@ -811,6 +1029,208 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
     if (final_rel_res) *final_rel_res = last_rel;
     if (cg_fail) return fail(c, PBF_ENOCONV, "CG did not reach the relative tolerance %g", cg_rtol);
     if (!converged) return fail(c, PBF_ENOCONV, "Picard did not converge in %d iterations", picard_max_it);
+    return PBF_OK;
+}
+
+pbf_status pbf_set_probes(pbf_ctx *c, int n, const double *pts, const double *targets, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->has_mesh) return fail(c, PBF_ESTATE, "no mesh");
+    if (n < 0 || n > kMaxProbes) return fail(c, PBF_EINVAL, "number of probes must be in [0, %d]", kMaxProbes);
+    if (n > 0 && !pts) return fail(c, PBF_EINVAL, "pts is NULL");
+    std::vector<int> cell(3 * (size_t)n);
+    std::vector<double> xi(3 * (size_t)n), tgt((size_t)n, 0.0);
+    const int nc[3] = {c->nx, c->ny, c->nz};
+    for (int p = 0; p < n; ++p) {
+        for (int d = 0; d < 3; ++d) {
+            const double x = pts[3 * p + d];
+            if (!(x >= 0.0 && x <= c->L[d])) return fail(c, PBF_EINVAL, "probe %d lies outside the box", p);
+            const double h = c->L[d] / nc[d];
+            const double sx = x / h;
+            int ci = (int)std::floor(sx);
+            if (ci > 0 && (double)ci == sx) ci -= 1;  // shared face: lower cell
+            ci = std::min(std::max(ci, 0), nc[d] - 1);
+            cell[3 * p + d] = ci;
+            xi[3 * p + d] = sx - ci;
+        }
+        if (targets) {
+            if (!std::isfinite(targets[p])) return fail(c, PBF_EINVAL, "target %d is not finite", p);
+            tgt[p] = targets[p];
+        }
+    }
+    c->probe_cell = cell;
+    c->probe_xi = xi;
+    c->probe_target = tgt;
+    c->probes_dirty = true;
+    if (c->bound) return upload_probes(c, (hipStream_t)stream);
+    return PBF_OK;
+}
+
+pbf_status pbf_probe(pbf_ctx *c, const double *T, double *vals, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!T || (!vals && !c->probe_target.empty())) return fail(c, PBF_EINVAL, "NULL device array");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_probes(c, s))) return st;
+    PBF_HIP(c, launch_probe_values(probe_set(c), T, vals, s));
+    return PBF_OK;
+}
+
+pbf_status pbf_objective(pbf_ctx *c, const double *T, double *J, double *lam, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!T || !J || !lam) return fail(c, PBF_EINVAL, "NULL device array");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_probes(c, s))) return st;
+    PBF_HIP(c, launch_objective(probe_set(c), T, J, lam, n_dofs(c), s));
+    return PBF_OK;
+}
+
+pbf_status pbf_adjoint_step(pbf_ctx *c, const double *T_n, const double *rc_prev, const double *lam_next,
+                            double *lam, double *mu, double t_n, double dt, double *dJdW, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!T_n || !lam_next || !lam) return fail(c, PBF_EINVAL, "NULL device array");
+    if (lam == lam_next) return fail(c, PBF_EINVAL, "lam and lam_next must be distinct arrays");
+    if (n_hist_qp(c) > 0 && (!rc_prev || !mu))
+        return fail(c, PBF_EINVAL, "rc_prev and mu are required when the mesh has history");
+    if (!c->tracks.empty() && !dJdW) return fail(c, PBF_EINVAL, "dJdW is NULL");
+    if (!(dt > 0) || !std::isfinite(t_n)) return fail(c, PBF_EINVAL, "need dt > 0 and finite t_n");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    return adjoint_step(c, T_n, n_hist_qp(c) > 0 ? rc_prev : nullptr, lam_next, lam,
+                        n_hist_qp(c) > 0 ? mu : nullptr, t_n, dt, dJdW, s);
+}
+
+pbf_status pbf_revolve_schedule(int n_steps, int n_snaps, pbf_revolve_action *actions, int max_actions,
+                                int *n_actions, int64_t *n_advances)
+{
+    if (n_steps < 1 || n_steps > (1 << 24) || n_snaps < 1)
+        return fail(nullptr, PBF_EINVAL, "need 1 <= n_steps <= 2^24 and n_snaps >= 1");
+    std::vector<pbf_revolve_action> acts;
+    long long adv = 0;
+    if (!revolve_schedule(n_steps, n_snaps, acts, &adv)) return fail(nullptr, PBF_EINVAL, "bad schedule request");
+    if (n_actions) *n_actions = (int)acts.size();
+    if (n_advances) *n_advances = adv;
+    if (actions) {
+        if ((size_t)max_actions < acts.size())
+            return fail(nullptr, PBF_EINVAL, "max_actions %d < %zu actions", max_actions, acts.size());
+        std::copy(acts.begin(), acts.end(), actions);
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_adjoint_work_bytes(const pbf_ctx *c, int n_snaps, size_t *bytes)
+{
+    if (!c || !bytes) return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "NULL argument");
+    if (!c->has_mesh) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no mesh");
+    if (n_snaps < 1) return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "n_snaps must be >= 1");
+    *bytes = grad_layout(c, n_snaps, nullptr).bytes;
+    return PBF_OK;
+}
+
+static pbf_status check_grad_args(pbf_ctx *c, double dt, int n_steps, int n_snaps, void *work, size_t work_bytes)
+{
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!(dt > 0)) return fail(c, PBF_EINVAL, "dt must be > 0");
+    if (n_steps < 1 || n_steps > (1 << 24)) return fail(c, PBF_EINVAL, "n_steps must be in [1, 2^24]");
+    if (n_snaps < 1) return fail(c, PBF_EINVAL, "n_snaps must be >= 1");
+    if (!work || ((uintptr_t)work & 255) != 0) return fail(c, PBF_EINVAL, "work must be 256-byte aligned device memory");
+    const size_t need = grad_layout(c, n_snaps, nullptr).bytes;
+    if (work_bytes < need) return fail(c, PBF_ENOMEM, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    return PBF_OK;
+}
+
+pbf_status pbf_gradient_forward(pbf_ctx *c, const double *T0, const double *rc0, double t0, double dt,
+                                int n_steps, int n_snaps, void *work, size_t work_bytes, double *T_N,
+                                double *J, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_grad_args(c, dt, n_steps, n_snaps, work, work_bytes);
+    if (st) return st;
+    if (!T0 || (n_hist_qp(c) > 0 && !rc0)) return fail(c, PBF_EINVAL, "NULL initial state");
+    if (!std::isfinite(t0)) return fail(c, PBF_EINVAL, "t0 must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    if ((st = upload_probes(c, s))) return st;
+    c->grad.valid = false;
+    std::vector<pbf_revolve_action> acts;
+    long long adv = 0;
+    revolve_schedule(n_steps, n_snaps, acts, &adv);
+    size_t first_turn = 0;
+    while (first_turn < acts.size() && acts[first_turn].kind != PBF_ACT_TURN) ++first_turn;
+    const GradWork w = grad_layout(c, n_snaps, (char *)work);
+    const size_t N = (size_t)n_dofs(c), H = (size_t)n_hist_qp(c);
+    PBF_HIP(c, hipMemcpyAsync(w.Tcur, T0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (H) PBF_HIP(c, hipMemcpyAsync(w.rcur, rc0, H * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::vector<double> P(std::max<size_t>(c->tracks.size(), 1), 0.0);
+    for (size_t k = 0; k < c->tracks.size(); ++k) P[k] = c->tracks[k].power;
+    PBF_HIP(c, hipMemcpyAsync(w.powers, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    PBF_HIP(c, hipStreamSynchronize(s));
+    int cur = 0;
+    double *lam = w.lam, *lam2 = w.lam2;
+    long long fwd = 0;
+    for (size_t i = 0; i < first_turn; ++i)
+        if (acts[i].kind == PBF_ACT_ADVANCE) fwd = acts[i].step;  // forward sweep: 0 -> step
+    if ((st = run_actions(c, acts, 0, first_turn, w, cur, lam, lam2, t0, dt, s))) return st;
+    // last step (l-1 -> l) on copies, then the objective at T_N
+    if (H) PBF_HIP(c, hipMemcpyAsync(w.rtmp, w.rcur, H * sizeof(double), hipMemcpyDeviceToDevice, s));
+    st = operator_pass(c, 0, PBF_PREC_FP64, false, w.Tcur, w.Ttmp, nullptr, nullptr, H ? w.rtmp : nullptr,
+                       t0 + (n_steps - 1) * dt, dt, s);
+    if (st) return st;
+    PBF_HIP(c, launch_objective(probe_set(c), w.Ttmp, w.J, w.lam, (long long)N, s));
+    if (T_N) PBF_HIP(c, hipMemcpyAsync(T_N, w.Ttmp, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (J) PBF_HIP(c, hipMemcpyAsync(J, w.J, sizeof(double), hipMemcpyDeviceToDevice, s));
+    c->grad.work = work;
+    c->grad.n_steps = n_steps;
+    c->grad.n_snaps = n_snaps;
+    c->grad.t0 = t0;
+    c->grad.dt = dt;
+    c->grad.forward_advances = fwd;
+    c->grad.valid = true;
+    return PBF_OK;
+}
+
+pbf_status pbf_gradient_backward(pbf_ctx *c, double t0, double dt, int n_steps, int n_snaps, void *work,
+                                 size_t work_bytes, double *dJdW, double *dJdP, double *dJdA, double *lam0,
+                                 int64_t *n_advances, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_grad_args(c, dt, n_steps, n_snaps, work, work_bytes);
+    if (st) return st;
+    if (!c->grad.valid || c->grad.work != work || c->grad.n_steps != n_steps || c->grad.n_snaps != n_snaps ||
+        c->grad.t0 != t0 || c->grad.dt != dt)
+        return fail(c, PBF_ESTATE, "no matching forward sweep: call pbf_gradient_forward with the same arguments");
+    c->grad.valid = false;  // the reversal consumes the forward state
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    std::vector<pbf_revolve_action> acts;
+    long long adv = 0;
+    revolve_schedule(n_steps, n_snaps, acts, &adv);
+    size_t first_turn = 0;
+    while (first_turn < acts.size() && acts[first_turn].kind != PBF_ACT_TURN) ++first_turn;
+    const GradWork w = grad_layout(c, n_snaps, (char *)work);
+    const size_t N = (size_t)n_dofs(c), H = (size_t)n_hist_qp(c), K = c->tracks.size();
+    if (H) PBF_HIP(c, launch_fill(w.mu, 0.0, (long long)H, s));
+    PBF_HIP(c, launch_fill(w.dJdW, 0.0, (long long)std::max<size_t>(K, 1), s));
+    int cur = n_steps - 1;
+    double *lam = w.lam, *lam2 = w.lam2;
+    if ((st = run_actions(c, acts, first_turn, acts.size(), w, cur, lam, lam2, t0, dt, s))) return st;
+    if (K > 0) {
+        if (dJdP || dJdA) PBF_HIP(c, launch_adjoint_params(w.dJdW, w.powers, c->absorptivity, (int)K, dJdP, dJdA, s));
+        if (dJdW) PBF_HIP(c, hipMemcpyAsync(dJdW, w.dJdW, K * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else if (dJdA) {
+        PBF_HIP(c, launch_fill(dJdA, 0.0, 1, s));
+    }
+    if (lam0) PBF_HIP(c, hipMemcpyAsync(lam0, lam, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (n_advances) *n_advances = adv;
     return PBF_OK;
 }
 

@@ -79,7 +79,7 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
                     const R g = fmin0(fmax0((T - law.Ts) * law.inv_dT, R(0)), R(1));
                     if (g > r) {  // r_c = max(r_c, g): update before use
                         r = g;
-                        p.hist[hi] = double(g);
+                        if (p.hist_write) p.hist[hi] = double(g);
                     }
                 }
                 // k = (1-r) k_p + g k_m + (r-g) k_s with k_m = k_s = k(T), k_p = phi k(T)

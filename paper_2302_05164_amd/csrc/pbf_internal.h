@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <type_traits>
+#include <vector>
 
 #include "pbftherm.h"
 
@@ -103,6 +104,7 @@ struct CellParams {
     int MX, MY, MZ, ntiles, tiles_per_xcd;  // columns in x, y; z-segments; MX*MY*MZ
     int seg_len;                            // cell layers per z-segment
     int hist_cz0, n_hist_cells;
+    int hist_write;  // 0: the updated consolidated fraction is used but not stored
     double hx, hy, hz, Lz;
     R detJ, ih2x, ih2y, ih2z;  // h^-2 per direction
     double dt, T_D, Tref;
@@ -128,6 +130,37 @@ struct PicardParams {
     int src_on, laser_kind, src_cz0;
     double xb, yb, src_amp, two_over_R2, h_powder;
     const Law<double> *law;
+};
+
+// Parameters of the adjoint cell kernel (reverse of one explicit step).
+struct AdjointParams {
+    const double *T;     // T_n
+    const double *lam;   // lambda_{n+1}
+    const double *C;     // lumped capacity C~(T_n)
+    const double *f;     // f(T_n, r^n)
+    double *lam_out;     // lambda_n
+    const double *hist;  // r^{n-1} (read only)
+    double *mu;          // history adjoint: mu_n in, mu_{n-1} out
+    double *slots;
+    double *partials;    // per column tile: source sensitivity of the step
+    int nx, ny, nz, NX, NY, NZ;
+    int MX, MY, MZ, ntiles, tiles_per_xcd, seg_len;
+    int hist_cz0, n_hist_cells;
+    double hx, hy, hz, Lz;
+    double detJ, ih2x, ih2y, ih2z, dt;
+    unsigned dmask;
+    int src_on, laser_kind, src_cz0;
+    double xb, yb, src_unit, two_over_R2, h_powder;  // src_unit: amplitude per unit W_eff
+    const Law<double> *law;
+};
+
+// Probe set: containing cell and reference coordinates of each point.
+struct ProbeSet {
+    const int *cell;      // 3 per probe
+    const double *xi;     // 3 per probe
+    const double *target; // 1 per probe
+    int n, P, NX, NY;
+    long long NXY;
 };
 
 // Parameters of the tile-face completion kernel.
@@ -194,5 +227,24 @@ hipError_t launch_cg_direction(double *p, const double *z, const double *scal, i
 hipError_t launch_picard_update(double *Ti, const double *x, double *partials, double *scal,
                                 const HaloParams &geom, long long n, hipStream_t s);
 hipError_t launch_sub(double *d, const double *a, const double *b, long long n, hipStream_t s);
+
+// discrete adjoint (adjoint.hip)
+int adjoint_column_height();
+int adjoint_resident_columns_per_cu();
+hipError_t launch_adjoint(int degree, const AdjointParams &ap, const HaloParams &hp, hipStream_t s);
+// dJdW[track] += sum of the per-tile partials (one workgroup, fixed order)
+hipError_t launch_adjoint_finish(const double *partials, int ntiles, double *dJdW, int track,
+                                 hipStream_t s);
+// dJdP_k = A dJdW_k, dJdA = sum_k P_k dJdW_k
+hipError_t launch_adjoint_params(const double *dJdW, const double *powers, double A, int n_tracks,
+                                 double *dJdP, double *dJdA, hipStream_t s);
+hipError_t launch_probe_values(const ProbeSet &ps, const double *T, double *vals, hipStream_t s);
+// J = sum_p (T_h(x_p) - T*_p)^2 into J[0]; lam = dJ/dT (lam zeroed here)
+hipError_t launch_objective(const ProbeSet &ps, const double *T, double *J, double *lam, long long n,
+                            hipStream_t s);
+
+// binomial checkpoint schedule (revolve.cpp, host only)
+bool revolve_schedule(int l, int c, std::vector<pbf_revolve_action> &acts, long long *advances);
+long long revolve_min_advances(long long l, int c);
 
 }  // namespace pbf

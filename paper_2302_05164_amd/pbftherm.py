@@ -47,6 +47,12 @@ class _Laser(C.Structure):
                 ("tracks", C.POINTER(_Track))]
 
 
+class _Action(C.Structure):
+    _fields_ = [("kind", C.c_int), ("step", C.c_int), ("slot", C.c_int)]
+
+
+ACT_ADVANCE, ACT_STORE, ACT_RESTORE, ACT_TURN = 1, 2, 3, 4
+
 _vp = C.c_void_p
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -70,6 +76,16 @@ SIGNATURES = {
     "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
     "pbf_implicit_step": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int,
                           C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _vp],
+    "pbf_set_probes": [_vp, C.c_int, _dp, _dp, _vp],
+    "pbf_probe": [_vp, _vp, _vp, _vp],
+    "pbf_objective": [_vp, _vp, _vp, _vp, _vp],
+    "pbf_adjoint_step": [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp],
+    "pbf_revolve_schedule": [C.c_int, C.c_int, C.POINTER(_Action), C.c_int, C.POINTER(C.c_int), _i64p],
+    "pbf_adjoint_work_bytes": [_vp, C.c_int, C.POINTER(C.c_size_t)],
+    "pbf_gradient_forward": [_vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, C.c_size_t,
+                             _vp, _vp, _vp],
+    "pbf_gradient_backward": [_vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, C.c_size_t, _vp, _vp,
+                              _vp, _vp, _i64p, _vp],
     "pbf_timing_begin": [_vp, C.c_int],
     "pbf_timing_end": [_vp, _dp, _dp, _i64p],
 }
@@ -105,6 +121,30 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _aligned(nbytes, device):
+    """Device byte buffer with a 256-byte aligned start: (tensor, address)."""
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    base = buf.data_ptr()
+    return buf, base + (-base) % 256
+
+
+def revolve_schedule(n_steps, n_snaps, with_actions=True):
+    """Binomial checkpoint schedule (host only): (list of (kind, step, slot),
+    number of forward steps)."""
+    L = load_library()
+    na, adv = C.c_int(0), C.c_int64(0)
+    st = L.pbf_revolve_schedule(int(n_steps), int(n_snaps), None, 0, C.byref(na), C.byref(adv))
+    if st != 0:
+        raise PbfError(st, L.pbf_last_error(None).decode())
+    if not with_actions:
+        return None, adv.value
+    arr = (_Action * max(1, na.value))()
+    st = L.pbf_revolve_schedule(int(n_steps), int(n_snaps), arr, na.value, C.byref(na), C.byref(adv))
+    if st != 0:
+        raise PbfError(st, L.pbf_last_error(None).decode())
+    return [(a.kind, a.step, a.slot) for a in arr[: na.value]], adv.value
+
+
 def _f64(t, n, name):
     if t.dtype != torch.float64 or t.numel() != n:
         raise ValueError(f"{name}: expected {n} float64 values, got {t.numel()} {t.dtype}")
@@ -123,6 +163,8 @@ class Simulation:
         self._check(self.lib.pbf_create(C.byref(self.ctx)), use_ctx=False)
         self._check(self.lib.pbf_mesh_box(self.ctx, degree, nx, ny, nz, *map(float, L)))
         self.workspace = None
+        self.n_tracks = 0
+        self.n_probes = 0
 
     def __del__(self):
         if getattr(self, "ctx", None) and self.ctx.value:
@@ -166,6 +208,7 @@ class Simulation:
         l = _Laser(int(kind), float(radius), float(absorptivity), float(h_powder), float(t_start),
                    len(tr), arr)
         self._check(self.lib.pbf_set_laser(self.ctx, C.byref(l)))
+        self.n_tracks = len(tr)
 
     def set_track_powers(self, powers, absorptivity):
         p = np.ascontiguousarray(powers, dtype=np.float64)
@@ -221,7 +264,6 @@ class Simulation:
                                                   C.byref(lam), self._stream()))
         return lam.value
 
-
     def implicit_step(self, T_n, rc, t, dt, cg_rtol=1e-10, cg_max_it=10000, picard_tol=1e-8,
                       picard_max_it=30, T_out=None, check=True):
         i = self.info()
@@ -237,6 +279,77 @@ class Simulation:
         if check and st != 0:
             self._check(st)
         return T_out, info
+
+    # -- probes and adjoint -------------------------------------------------------
+    def set_probes(self, pts, targets=None):
+        p = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+        t = None if targets is None else np.ascontiguousarray(targets, dtype=np.float64)
+        if t is not None and t.size != len(p):
+            raise ValueError("one target per probe")
+        self._check(self.lib.pbf_set_probes(self.ctx, len(p), p.ctypes.data_as(_dp),
+                                            None if t is None else t.ctypes.data_as(_dp),
+                                            self._stream()))
+        self.n_probes = len(p)
+
+    def probe(self, T):
+        i = self.info()
+        vals = torch.empty(max(1, self.n_probes), dtype=torch.float64, device=self.device)
+        self._check(self.lib.pbf_probe(self.ctx, _f64(T, i["n_dofs"], "T"), _ptr(vals), self._stream()))
+        return vals[: self.n_probes]
+
+    def objective(self, T):
+        """(J as a one-element device tensor, dJ/dT)."""
+        i = self.info()
+        J = torch.empty(1, dtype=torch.float64, device=self.device)
+        lam = torch.empty_like(T)
+        self._check(self.lib.pbf_objective(self.ctx, _f64(T, i["n_dofs"], "T"), _ptr(J), _ptr(lam),
+                                           self._stream()))
+        return J, lam
+
+    def adjoint_step(self, T_n, rc_prev, lam_next, mu, t_n, dt, dJdW, lam=None):
+        i = self.info()
+        if lam is None:
+            lam = torch.empty_like(lam_next)
+        h = i["n_hist_qp"] > 0
+        self._check(self.lib.pbf_adjoint_step(
+            self.ctx, _f64(T_n, i["n_dofs"], "T_n"), _ptr(rc_prev) if h else None,
+            _f64(lam_next, i["n_dofs"], "lam_next"), _f64(lam, i["n_dofs"], "lam"),
+            _ptr(mu) if h else None, float(t_n), float(dt), _ptr(dJdW) if self.n_tracks else None,
+            self._stream()))
+        return lam
+
+    def gradient_work(self, n_snaps):
+        """Device buffer for gradient_forward/backward with n_snaps slots."""
+        nb = C.c_size_t()
+        self._check(self.lib.pbf_adjoint_work_bytes(self.ctx, int(n_snaps), C.byref(nb)))
+        buf, addr = _aligned(nb.value, self.device)
+        return {"buf": buf, "addr": addr, "bytes": nb.value, "n_snaps": int(n_snaps)}
+
+    def gradient_forward(self, T0, rc0, t0, dt, n_steps, work):
+        i = self.info()
+        T_N = torch.empty(i["n_dofs"], dtype=torch.float64, device=self.device)
+        J = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._check(self.lib.pbf_gradient_forward(
+            self.ctx, _f64(T0, i["n_dofs"], "T0"), _ptr(rc0) if i["n_hist_qp"] else None, float(t0),
+            float(dt), int(n_steps), work["n_snaps"], C.c_void_p(work["addr"]), work["bytes"],
+            _ptr(T_N), _ptr(J), self._stream()))
+        return T_N, J
+
+    def gradient_backward(self, t0, dt, n_steps, work, with_lam0=False):
+        i = self.info()
+        K = max(1, self.n_tracks)
+        out = {k: torch.zeros(K, dtype=torch.float64, device=self.device) for k in ("dJdW", "dJdP")}
+        out["dJdA"] = torch.zeros(1, dtype=torch.float64, device=self.device)
+        out["lam0"] = torch.empty(i["n_dofs"], dtype=torch.float64, device=self.device) if with_lam0 else None
+        adv = C.c_int64(0)
+        self._check(self.lib.pbf_gradient_backward(
+            self.ctx, float(t0), float(dt), int(n_steps), work["n_snaps"], C.c_void_p(work["addr"]),
+            work["bytes"], _ptr(out["dJdW"]), _ptr(out["dJdP"]), _ptr(out["dJdA"]), _ptr(out["lam0"]),
+            C.byref(adv), self._stream()))
+        out["dJdW"] = out["dJdW"][: self.n_tracks]
+        out["dJdP"] = out["dJdP"][: self.n_tracks]
+        out["n_advances"] = adv.value
+        return out
 
     def timing_begin(self, max_steps):
         self._check(self.lib.pbf_timing_begin(self.ctx, int(max_steps)))
