@@ -126,6 +126,55 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     return nbytes
 
 
+def adjoint_timing(reps=1):
+    """Adjoint/forward time ratio on the differentiation workload: the 48x48x24 Q2
+    box with the seeded nonlinear law, 3000 explicit steps, 64 probes, gradients
+    with respect to 10 track powers and the absorptivity, 30 checkpoint slots.
+    Times (HIP events on the library's stream): the forward sweep (steps,
+    snapshots, objective), the backward sweep (replays and adjoint steps), and
+    3000 plain explicit steps."""
+    import torch
+
+    import pbf_workloads as W
+    from paper_2302_05164_amd import pbftherm
+
+    prob = W.cfg5()
+    sim = pbftherm.from_problem(prob, device="cuda:0")
+    info = sim.info()
+    v0 = torch.tensor(W.seeded_vector(info["n_dofs"], 1), device="cuda")
+    dt = prob.dt_factor * 2.0 / sim.stability_lambda(v0, 100)
+    sim.set_probes(prob.probes, prob.targets)
+    n, s = prob.steps, 30
+    work = sim.gradient_work(s)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), out
+
+    res = []
+    for it in range(reps + 1):  # first repetition is warm-up
+        T0, rc0 = sim.init_state(prob.T0)
+        t_fwd, (TN, J) = timed(lambda: sim.gradient_forward(T0, rc0, 0.0, dt, n, work))
+        t_bwd, g = timed(lambda: sim.gradient_backward(0.0, dt, n, work))
+        T, rc = sim.init_state(prob.T0)
+        T_tmp = torch.empty_like(T)
+        t_plain, _ = timed(lambda: sim.explicit_steps(T, rc, 0.0, dt, n, T_tmp=T_tmp))
+        if it > 0:
+            res.append((t_fwd, t_bwd, t_plain, J.item(), g))
+    t_fwd, t_bwd, t_plain, J, g = res[-1]
+    return {"workload": prob.name, "n_dofs": info["n_dofs"], "steps": n, "checkpoint_slots": s,
+            "parameters": len(prob.tracks) + 1, "forward_ms": t_fwd, "backward_ms": t_bwd,
+            "plain_forward_ms": t_plain, "adjoint_forward_ratio": t_bwd / t_fwd,
+            "total_over_plain_forward": (t_fwd + t_bwd) / t_plain,
+            "forward_steps_total": g["n_advances"], "work_bytes": work["bytes"], "J": J,
+            "dJdA": g["dJdA"].item(), "dJdP_norm": float(torch.linalg.norm(g["dJdP"]).item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +183,7 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg4", "cfg5", "cfg1"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-operator timing")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -239,6 +289,8 @@ def main():
                                 "ms_per_step": r32["ms"] / args.steps,
                                 "speedup_vs_fp64": v32 / value,
                                 "kernel_ms": r32["cell_ms"], "finite": r32["finite"]}
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_timing()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

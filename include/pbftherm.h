@@ -189,6 +189,26 @@ pbf_status pbf_set_probes(pbf_ctx *ctx, int n, const double *pts, const double *
 pbf_status pbf_probe(pbf_ctx *ctx, const double *T, double *vals, void *stream);
 pbf_status pbf_objective(pbf_ctx *ctx, const double *T, double *J, double *lam, void *stream);
 
+/* ---- diagnostics -----------------------------------------------------------------
+ * pbf_energy: energy terms of the explicit step from T_prev (time t, step dt) to
+ * T, with rc the history after that step (read only).  With f = f_diff + f_vol
+ * and C~ evaluated at T_prev as in the step (Section 3.2, eq. forward_euler),
+ * over the free nodes:
+ *   out[0] = sum C~_i (T_i - T_prev,i)   change of stored heat,
+ *   out[1] = sum f_vol,i                 absorbed laser power,
+ *   out[2] = -sum f_diff,i               heat flow into the Dirichlet nodes,
+ *   out[3] = out[0] - dt (out[1] - out[2])  (zero up to round-off for a step
+ *            of pbf_explicit_steps).
+ * Since the diffusion rows sum to zero, out[2] equals the sum of f_diff over the
+ * Dirichlet nodes.  Host array out[4].  Uses workspace scratch.  Synchronizes.
+ * pbf_check_finite: *ok = 1 if all n values of the device array x are finite,
+ * *maxabs = max |x_i| over the finite ones; returns PBF_ENONFINITE otherwise.
+ * Synchronizes. */
+pbf_status pbf_energy(pbf_ctx *ctx, const double *T_prev, const double *T, const double *rc, double t,
+                      double dt, double out[4], void *stream);
+pbf_status pbf_check_finite(pbf_ctx *ctx, const double *x, int64_t n, int *ok, double *maxabs,
+                            void *stream);
+
 /* ---- discrete adjoint of the explicit scheme -------------------------------------
  * Reverse of one step of eq. forward_euler (Section 3.2) with the law of
  * Section 2: the step maps (T_n, r^{n-1}) to r^n = max(r^{n-1}, g(T_n)) and

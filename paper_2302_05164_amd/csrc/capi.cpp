@@ -42,7 +42,7 @@ struct pbf_ctx {
     bool bound = false;
     char *ws = nullptr;
     size_t ws_bytes = 0;
-    Law<double> *d_law64 = nullptr, *d_lin64 = nullptr;
+    Law<double> *d_law64 = nullptr, *d_lin64 = nullptr, *d_zero64 = nullptr;
     Law<float> *d_law32 = nullptr;
     double *d_slots = nullptr;
     double *d_f = nullptr, *d_C = nullptr, *d_v = nullptr, *d_partials = nullptr, *d_scal = nullptr;
@@ -63,7 +63,7 @@ struct pbf_ctx {
         long long forward_advances = 0;
         bool valid = false;
     } grad;
-    Law<double> h_law64{}, h_lin64{};
+    Law<double> h_law64{}, h_lin64{}, h_zero64{};
     Law<float> h_law32{};
     // kernel timing: 3 events per timed step (before cells, between, after faces)
     std::vector<hipEvent_t> tev;
@@ -358,23 +358,32 @@ pbf_status upload_laws(pbf_ctx *c, hipStream_t s)
     build_law<double>(c, 0.0, false, 0, c->h_law64);
     build_law<float>(c, c->Tref, false, 0, c->h_law32);
     build_law<double>(c, 0.0, true, critical_breakpoint(c), c->h_lin64);
+    c->h_zero64 = c->h_lin64;  // k = 0: the operator reduces to the source terms
+    c->h_zero64.k0 = 0.0;
     PBF_HIP(c, hipMemcpyAsync(c->d_law64, &c->h_law64, sizeof(Law<double>), hipMemcpyHostToDevice, s));
     PBF_HIP(c, hipMemcpyAsync(c->d_law32, &c->h_law32, sizeof(Law<float>), hipMemcpyHostToDevice, s));
     PBF_HIP(c, hipMemcpyAsync(c->d_lin64, &c->h_lin64, sizeof(Law<double>), hipMemcpyHostToDevice, s));
+    PBF_HIP(c, hipMemcpyAsync(c->d_zero64, &c->h_zero64, sizeof(Law<double>), hipMemcpyHostToDevice, s));
     PBF_HIP(c, hipStreamSynchronize(s));
     c->laws_dirty = false;
     return PBF_OK;
 }
 
+// law of an operator pass: the material law, the linear law at the critical
+// breakpoint (stability estimate), or k = 0 (source terms only)
+enum { LAW_FULL = 0, LAW_CRITICAL = 1, LAW_SOURCE = 2 };
+
 // one operator pass: MODE 0 explicit step Tin -> Tout, MODE 1 assemble into f, C
-pbf_status operator_pass(pbf_ctx *c, int mode, int precision, bool linear, const double *Tin,
+pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const double *Tin,
                          double *Tout, double *f, double *C, double *rc, double t, double dt,
                          hipStream_t s, bool hist_write = true)
 {
+    const bool linear = law == LAW_CRITICAL;
     CellParams<double> pd{};
     CellParams<float> pf{};
     if (precision == PBF_PREC_FP64) {
-        pd = cell_params<double>(c, linear ? c->d_lin64 : c->d_law64, !linear);
+        pd = cell_params<double>(c, law == LAW_FULL ? c->d_law64 : (linear ? c->d_lin64 : c->d_zero64),
+                                 law == LAW_FULL);
         pd.Tin = Tin;
         pd.Tout = Tout;
         pd.fout = f;
@@ -559,7 +568,7 @@ pbf_status adjoint_step(pbf_ctx *c, const double *T, const double *rc, const dou
                         double *mu, double t, double dt, double *dJdW, hipStream_t s)
 {
     // f and C~ of the forward step, history read but not written
-    pbf_status st = operator_pass(c, 1, PBF_PREC_FP64, false, T, nullptr, c->d_f, c->d_C,
+    pbf_status st = operator_pass(c, 1, PBF_PREC_FP64, LAW_FULL, T, nullptr, c->d_f, c->d_C,
                                   const_cast<double *>(rc), t, 0.0, s, false);
     if (st) return st;
     const Beam bm = beam_at(c, t);
@@ -616,7 +625,7 @@ pbf_status run_actions(pbf_ctx *c, const std::vector<pbf_revolve_action> &acts, 
         if (a.kind == PBF_ACT_ADVANCE) {
             double *x = w.Tcur, *y = w.Ttmp;
             for (int n = cur; n < a.step; ++n) {
-                pbf_status st = operator_pass(c, 0, PBF_PREC_FP64, false, x, y, nullptr, nullptr,
+                pbf_status st = operator_pass(c, 0, PBF_PREC_FP64, LAW_FULL, x, y, nullptr, nullptr,
                                               H ? w.rcur : nullptr, t0 + n * dt, dt, s);
                 if (st) return st;
                 std::swap(x, y);
@@ -803,7 +812,7 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     if (!c->has_mesh) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no mesh");
     const size_t N = (size_t)n_dofs(c);
     size_t b = 0;
-    b += align256(sizeof(Law<double>)) * 2 + align256(sizeof(Law<float>));
+    b += align256(sizeof(Law<double>)) * 3 + align256(sizeof(Law<float>));
     b += align256(8 * N * sizeof(double));        // parity slots
     b += 11 * align256(N * sizeof(double));       // f, C, v; implicit: y, diag, r, z, p, Ap, x, d
     b += align256(kRedBlocks * 4 * sizeof(double)); // reduction partials
@@ -828,6 +837,8 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     c->d_law64 = (Law<double> *)p;
     p += align256(sizeof(Law<double>));
     c->d_lin64 = (Law<double> *)p;
+    p += align256(sizeof(Law<double>));
+    c->d_zero64 = (Law<double> *)p;
     p += align256(sizeof(Law<double>));
     c->d_law32 = (Law<float> *)p;
     p += align256(sizeof(Law<float>));
@@ -901,7 +912,7 @@ pbf_status pbf_explicit_steps(pbf_ctx *c, double *T, double *T_tmp, double *rc, 
     double *cur = T, *nxt = T_tmp;
     for (int n = 0; n < n_steps; ++n) {
         const double t = t0 + n * dt;
-        st = operator_pass(c, 0, precision, false, cur, nxt, nullptr, nullptr, rc, t, dt, s);
+        st = operator_pass(c, 0, precision, LAW_FULL, cur, nxt, nullptr, nullptr, rc, t, dt, s);
         if (st) return st;
         std::swap(cur, nxt);
     }
@@ -921,7 +932,7 @@ pbf_status pbf_assemble(pbf_ctx *c, const double *T, double *rc, double t, doubl
         return fail(c, PBF_EINVAL, "precision must be 64 or 32");
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_laws(c, s))) return st;
-    return operator_pass(c, 1, precision, false, T, nullptr, f, C, rc, t, 0.0, s);
+    return operator_pass(c, 1, precision, LAW_FULL, T, nullptr, f, C, rc, t, 0.0, s);
 }
 
 pbf_status pbf_stability_lambda(pbf_ctx *c, const double *v0, int iters, double *lambda_max,
@@ -939,7 +950,7 @@ pbf_status pbf_stability_lambda(pbf_ctx *c, const double *v0, int iters, double 
     PBF_HIP(c, hipMemcpyAsync(c->d_v, v0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     PBF_HIP(c, launch_init_dirichlet(c->d_v, g, 0.0, s));
     for (int it = 0; it < iters; ++it) {
-        st = operator_pass(c, 1, PBF_PREC_FP64, true, c->d_v, nullptr, c->d_f, c->d_C, nullptr, 0.0,
+        st = operator_pass(c, 1, PBF_PREC_FP64, LAW_CRITICAL, c->d_v, nullptr, c->d_f, c->d_C, nullptr, 0.0,
                            0.0, s);
         if (st) return st;
         PBF_HIP(c, launch_power_dots(c->d_f, c->d_C, c->d_v, c->d_partials, c->d_scal, g, N, s));
@@ -1022,7 +1033,7 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
         }
     }
     // commit the consolidated fraction: r = max(r, g(T_{n+1}))
-    st = operator_pass(c, 1, PBF_PREC_FP64, false, Ti, nullptr, c->d_f, c->d_C, rc, t + dt, 0.0, s);
+    st = operator_pass(c, 1, PBF_PREC_FP64, LAW_FULL, Ti, nullptr, c->d_f, c->d_C, rc, t + dt, 0.0, s);
     if (st) return st;
     if (cg_iters_total) *cg_iters_total = total;
     if (picard_iters) *picard_iters = it;
@@ -1182,7 +1193,7 @@ pbf_status pbf_gradient_forward(pbf_ctx *c, const double *T0, const double *rc0,
     if ((st = run_actions(c, acts, 0, first_turn, w, cur, lam, lam2, t0, dt, s))) return st;
     // last step (l-1 -> l) on copies, then the objective at T_N
     if (H) PBF_HIP(c, hipMemcpyAsync(w.rtmp, w.rcur, H * sizeof(double), hipMemcpyDeviceToDevice, s));
-    st = operator_pass(c, 0, PBF_PREC_FP64, false, w.Tcur, w.Ttmp, nullptr, nullptr, H ? w.rtmp : nullptr,
+    st = operator_pass(c, 0, PBF_PREC_FP64, LAW_FULL, w.Tcur, w.Ttmp, nullptr, nullptr, H ? w.rtmp : nullptr,
                        t0 + (n_steps - 1) * dt, dt, s);
     if (st) return st;
     PBF_HIP(c, launch_objective(probe_set(c), w.Ttmp, w.J, w.lam, (long long)N, s));
@@ -1232,6 +1243,52 @@ pbf_status pbf_gradient_backward(pbf_ctx *c, double t0, double dt, int n_steps, 
     if (lam0) PBF_HIP(c, hipMemcpyAsync(lam0, lam, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (n_advances) *n_advances = adv;
     return PBF_OK;
+}
+
+pbf_status pbf_energy(pbf_ctx *c, const double *T_prev, const double *T, const double *rc, double t,
+                      double dt, double out[4], void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!T_prev || !T || !out) return fail(c, PBF_EINVAL, "NULL argument");
+    if (n_hist_qp(c) > 0 && !rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
+    if (!(dt > 0) || !std::isfinite(t)) return fail(c, PBF_EINVAL, "need dt > 0 and finite t");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    const long long N = n_dofs(c);
+    // f and C~ of the step from T_prev (history read only), then the source alone
+    st = operator_pass(c, 1, PBF_PREC_FP64, LAW_FULL, T_prev, nullptr, c->d_f, c->d_C,
+                       const_cast<double *>(rc), t, 0.0, s, false);
+    if (st) return st;
+    st = operator_pass(c, 1, PBF_PREC_FP64, LAW_SOURCE, T_prev, nullptr, c->d_v, c->d_cg[0], nullptr, t,
+                       0.0, s);
+    if (st) return st;
+    PBF_HIP(c, launch_energy(T_prev, T, c->d_f, c->d_v, c->d_C, c->d_partials, c->d_scal, geometry(c), N, s));
+    double e[3];
+    PBF_HIP(c, hipMemcpyAsync(e, c->d_scal + SC_ENERGY, sizeof e, hipMemcpyDeviceToHost, s));
+    PBF_HIP(c, hipStreamSynchronize(s));
+    out[0] = e[0];
+    out[1] = e[1];
+    out[2] = e[2];
+    out[3] = e[0] - dt * (e[1] - e[2]);
+    return PBF_OK;
+}
+
+pbf_status pbf_check_finite(pbf_ctx *c, const double *x, int64_t n, int *ok, double *maxabs, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!x || n < 1) return fail(c, PBF_EINVAL, "need a device array of n >= 1 values");
+    hipStream_t s = (hipStream_t)stream;
+    PBF_HIP(c, launch_finite(x, c->d_partials, c->d_scal, (long long)n, s));
+    double r[2];
+    PBF_HIP(c, hipMemcpyAsync(r, c->d_scal + SC_FINITE, sizeof r, hipMemcpyDeviceToHost, s));
+    PBF_HIP(c, hipStreamSynchronize(s));
+    if (ok) *ok = r[0] == 0.0;
+    if (maxabs) *maxabs = r[1];
+    return r[0] == 0.0 ? PBF_OK : fail(c, PBF_ENONFINITE, "%.0f non-finite values", r[0]);
 }
 
 pbf_status pbf_timing_begin(pbf_ctx *c, int max_steps)

@@ -214,6 +214,12 @@ constexpr int kRedBlocks = 1024;  // blocks of the first reduction stage
 
 // device scalars of the CG iteration (offsets into the scalar array)
 enum { CG_RZ0 = 8, CG_RZ1 = 9, CG_RR = 10, CG_PAP = 11, CG_BN2 = 12, CG_DMAX = 13 };
+// diagnostics: energy terms (3 values), non-finite count and max |x| (2 values)
+enum { SC_ENERGY = 16, SC_FINITE = 20 };
+hipError_t launch_energy(const double *Tp, const double *T, const double *f, const double *fv,
+                         const double *C, double *partials, double *scal, const HaloParams &geom,
+                         long long n, hipStream_t s);
+hipError_t launch_finite(const double *x, double *partials, double *scal, long long n, hipStream_t s);
 hipError_t launch_cg_start(const double *y, const double *diag, double *r, double *z, double *p,
                            double *x, double *partials, double *scal, const HaloParams &geom,
                            long long n, hipStream_t s);

@@ -218,6 +218,49 @@ __global__ void __launch_bounds__(kRedThreads) k_picard_update(double *Ti, const
     if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
 }
 
+// energy terms over free nodes: C~ (T - T_prev), f_vol, -(f - f_vol)
+__global__ void __launch_bounds__(kRedThreads) k_energy(const double *Tp, const double *T, const double *f,
+                                                         const double *fv, const double *C, double *partials,
+                                                         const HaloParams h, long long n)
+{
+    double s[3] = {0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        if (node_dirichlet(i, h)) continue;
+        s[0] += C[i] * (T[i] - Tp[i]);
+        s[1] += fv[i];
+        s[2] -= f[i] - fv[i];
+    }
+    block_sum<3>(s);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) partials[3 * blockIdx.x + c] = s[c];
+}
+
+// number of non-finite entries and max |x| over the finite ones
+__global__ void __launch_bounds__(kRedThreads) k_finite(const double *x, double *partials, long long n)
+{
+    double bad = 0.0, m = 0.0;
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        const double v = x[i];
+        if (isfinite(v)) m = fmax(m, fabs(v));
+        else bad += 1.0;
+    }
+    double s[1] = {bad};
+    block_sum<1>(s);
+    __shared__ double sh[kRedThreads];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s[0];
+        partials[2 * blockIdx.x + 1] = sh[0];
+    }
+}
+
 __global__ void k_sub(double *d, const double *a, const double *b, long long n)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,6 +391,26 @@ hipError_t launch_picard_update(double *Ti, const double *x, double *partials, d
 hipError_t launch_sub(double *d, const double *a, const double *b, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sub, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const double *Tp, const double *T, const double *f, const double *fv,
+                         const double *C, double *partials, double *scal, const HaloParams &geom,
+                         long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy, dim3(kRedBlocks), dim3(kRedThreads), 0, s, Tp, T, f, fv, C, partials, geom, n);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 3, 3,
+                       scal + SC_ENERGY);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite(const double *x, double *partials, double *scal, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finite, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, partials, n);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 2, 1,
+                       scal + SC_FINITE);
+    hipLaunchKernelGGL(k_finish<true>, dim3(1), dim3(kRedThreads), 0, s, partials + 1, kRedBlocks, 2, 1,
+                       scal + SC_FINITE + 1);
     return hipGetLastError();
 }
 

@@ -86,6 +86,8 @@ SIGNATURES = {
                              _vp, _vp, _vp],
     "pbf_gradient_backward": [_vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, C.c_size_t, _vp, _vp,
                               _vp, _vp, _i64p, _vp],
+    "pbf_energy": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, _dp, _vp],
+    "pbf_check_finite": [_vp, _vp, C.c_int64, C.POINTER(C.c_int), _dp, _vp],
     "pbf_timing_begin": [_vp, C.c_int],
     "pbf_timing_end": [_vp, _dp, _dp, _i64p],
 }
@@ -279,6 +281,25 @@ class Simulation:
         if check and st != 0:
             self._check(st)
         return T_out, info
+
+    # -- diagnostics ----------------------------------------------------------------
+    def energy(self, T_prev, T, rc, t, dt):
+        """(stored-heat change, absorbed power, Dirichlet heat flow, identity residual)."""
+        i = self.info()
+        out = (C.c_double * 4)()
+        self._check(self.lib.pbf_energy(self.ctx, _f64(T_prev, i["n_dofs"], "T_prev"),
+                                        _f64(T, i["n_dofs"], "T"), _ptr(rc) if i["n_hist_qp"] else None,
+                                        float(t), float(dt), out, self._stream()))
+        return tuple(out)
+
+    def check_finite(self, x):
+        """(all finite, max |x| over the finite values)."""
+        ok, mx = C.c_int(0), C.c_double(0)
+        st = self.lib.pbf_check_finite(self.ctx, _ptr(x), x.numel(), C.byref(ok), C.byref(mx),
+                                       self._stream())
+        if st not in (0, -6):
+            self._check(st)
+        return bool(ok.value), mx.value
 
     # -- probes and adjoint -------------------------------------------------------
     def set_probes(self, pts, targets=None):

@@ -581,6 +581,20 @@ def test_adjoint_linear_case_exact_response():
 # lumped capacity with a temperature-dependent c
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("deg", [1, 2])
+def test_diffusion_rows_sum_to_zero(deg):
+    """Sum over all nodes of f_diff = -sum_e sum_q W k grad(sum_a N_a) . grad T = 0
+    for any T and history (the basis sums to one), so the heat leaving the free
+    nodes is the reaction at the Dirichlet nodes."""
+    prob = W.small_nonlinear(nx=5, ny=4, nz=3, steps=0).replace(degree=deg)
+    o = Oracle(prob)
+    T = o.init_T() + 900.0 * (1.0 + W.seeded_vector(o.N, 4))
+    rc = o.init_history()
+    f, Cl, fv = o.assemble(T, rc, 1e-5)
+    fd = f - fv
+    assert abs(fd.sum()) <= 1e-12 * np.abs(fd).sum()
+
+
+@pytest.mark.parametrize("deg", [1, 2])
 def test_lumped_capacity_nodal_form(deg):
     """C~_i = rho c(T_i) M~_i with M~ the row sums of the exact mass matrix
     (Kronecker assembly), for a field spanning every segment of the law."""
