@@ -1,4 +1,4 @@
-"""ctypes wrapper of the plain C oracle (oracle.c).
+"""ctypes wrapper of the plain C oracle (oracle.c on boxes, octree.c on octrees).
 
 TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the CPU
 baseline of the benchmark, never by the product path.  See oracle.h for the
@@ -33,11 +33,16 @@ class OrProblem(C.Structure):
     ]
 
 
+_SOURCES = ("oracle.c", "octree.c")
+_HEADERS = ("oracle.h", "oracle_internal.h")
+
+
 def build(force: bool = False) -> str:
-    src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+    srcs = [os.path.join(_HERE, f) for f in _SOURCES]
+    newest = max(os.path.getmtime(os.path.join(_HERE, f)) for f in _SOURCES + _HEADERS)
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < newest:
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-o", _SO,
-                               src, "-lm"])
+                               *srcs, "-lm"])
     return _SO
 
 
@@ -84,6 +89,29 @@ def lib():
         L.or_probe.argtypes = [P, _dp, C.c_int, _dp, _dp]
         L.or_adjoint_run.argtypes = [P, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp,
                                      _dp, _dp, _dp, _dp]
+        O = C.c_void_p
+        L.or_oct_build.argtypes = [P, C.c_int, C.c_int64, _i64p]
+        L.or_oct_build.restype = O
+        L.or_oct_free.argtypes = [O]
+        L.or_oct_free.restype = None
+        for nm in ("or_oct_n_dofs", "or_oct_n_hanging", "or_oct_n_qp"):
+            getattr(L, nm).argtypes = [O]
+            getattr(L, nm).restype = C.c_int64
+        L.or_oct_dof_coords.argtypes = [O, _dp]
+        L.or_oct_dof_coords.restype = None
+        L.or_oct_dirichlet.argtypes = [O, C.POINTER(C.c_int)]
+        L.or_oct_dirichlet.restype = None
+        L.or_oct_init_history.argtypes = [O, _dp]
+        L.or_oct_init_history.restype = None
+        L.or_oct_assemble.argtypes = [O, _dp, _dp, C.c_double, _dp, _dp, _dp, C.c_int]
+        L.or_oct_explicit_steps.argtypes = [O, _dp, _dp, C.c_double, C.c_double, C.c_int]
+        L.or_oct_stability_lambda.argtypes = [O, _dp, C.c_int]
+        L.or_oct_stability_lambda.restype = C.c_double
+        L.or_oct_implicit_step.argtypes = [O, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int,
+                                           C.c_double, C.c_int, _dp, C.POINTER(C.c_int),
+                                           C.POINTER(C.c_int), _dp]
+        L.or_oct_probe.argtypes = [O, _dp, C.c_int, _dp, _dp]
+        L.or_oct_transfer.argtypes = [O, _dp, _dp, O, _dp, _dp]
         _lib = L
     return _lib
 
@@ -237,6 +265,86 @@ class Oracle:
         xb, yb, W, k = C.c_double(), C.c_double(), C.c_double(), C.c_int(-1)
         on = self.L.or_beam(C.byref(self.s), t, C.byref(xb), C.byref(yb), C.byref(W), C.byref(k))
         return bool(on), xb.value, yb.value, W.value, k.value
+
+
+class OctOracle:
+    """The oracle on an octree mesh: prob is a problem description with coarse
+    cells nx, ny, nz, max_level and leaves (n, 4) = (level, ix, iy, iz)."""
+
+    def __init__(self, prob, leaves=None, track_power=None):
+        self.base = Oracle(prob, track_power=track_power)  # holds the problem struct
+        self.L = self.base.L
+        lv = np.ascontiguousarray(prob.leaves if leaves is None else leaves, dtype=np.int64)
+        self._leaves = lv
+        self.h = self.L.or_oct_build(C.byref(self.base.s), int(prob.max_level), len(lv),
+                                     lv.ctypes.data_as(_i64p))
+        if not self.h:
+            raise RuntimeError("or_oct_build failed")
+        self.prob = prob
+        self.N = self.L.or_oct_n_dofs(self.h)
+        self.NQ = self.L.or_oct_n_qp(self.h)
+        self.n_hanging = self.L.or_oct_n_hanging(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.or_oct_free(self.h)
+            self.h = None
+
+    def dof_coords(self):
+        x = np.zeros((self.N, 3))
+        self.L.or_oct_dof_coords(self.h, _ptr(x))
+        return x
+
+    def dirichlet_mask(self):
+        f = np.zeros(self.N, dtype=np.int32)
+        self.L.or_oct_dirichlet(self.h, f.ctypes.data_as(C.POINTER(C.c_int)))
+        return f.astype(bool)
+
+    def init_T(self):
+        T = np.full(self.N, float(self.prob.T0))
+        T[self.dirichlet_mask()] = self.prob.T_D
+        return T
+
+    def init_history(self):
+        rc = np.zeros(self.NQ)
+        self.L.or_oct_init_history(self.h, _ptr(rc))
+        return rc
+
+    def assemble(self, T, rc, t, hist=0):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        f, Cl, fv = np.zeros(self.N), np.zeros(self.N), np.zeros(self.N)
+        self.L.or_oct_assemble(self.h, _ptr(T), _ptr(rc), t, _ptr(f), _ptr(Cl), _ptr(fv), hist)
+        return f, Cl, fv
+
+    def explicit_steps(self, T, rc, t0, dt, n):
+        self.L.or_oct_explicit_steps(self.h, _ptr(T), _ptr(rc), t0, dt, n)
+        return T
+
+    def stability_lambda(self, v0, iters):
+        return self.L.or_oct_stability_lambda(self.h, _ptr(np.ascontiguousarray(v0, dtype=np.float64)), iters)
+
+    def implicit_step(self, Tn, rc, t, dt, cg_rtol=1e-10, cg_max_it=10000, picard_tol=1e-8,
+                      picard_max_it=30):
+        out = np.zeros(self.N)
+        it, pit, res = C.c_int(0), C.c_int(0), C.c_double(0)
+        st = self.L.or_oct_implicit_step(self.h, _ptr(np.ascontiguousarray(Tn)), _ptr(rc), t, dt, cg_rtol,
+                                         cg_max_it, picard_tol, picard_max_it, _ptr(out), C.byref(it),
+                                         C.byref(pit), C.byref(res))
+        return out, dict(status=st, cg_iters=it.value, picard_iters=pit.value, rel_res=res.value)
+
+    def probe(self, T, pts):
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        vals = np.zeros(len(pts))
+        if self.L.or_oct_probe(self.h, _ptr(np.ascontiguousarray(T)), len(pts), _ptr(pts), _ptr(vals)):
+            raise ValueError("probe outside the mesh")
+        return vals
+
+    def transfer(self, T, rc, new):
+        """(T, history) on the octree `new` (an OctOracle) from this one."""
+        Tn, rn = np.zeros(new.N), np.zeros(new.NQ)
+        if self.L.or_oct_transfer(self.h, _ptr(np.ascontiguousarray(T)), _ptr(rc), new.h, _ptr(Tn), _ptr(rn)):
+            raise ValueError("transfer: a new point lies outside the old mesh")
+        return Tn, rn
 
 
 def gauss_legendre(n):

@@ -36,14 +36,13 @@
  *  - Dirichlet nodes are set to T_D after every step (strong, nodal).
  */
 #include "oracle.h"
+#include "oracle_internal.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define OR_PI 3.14159265358979323846
-#define MAXN1 4           /* up to cubic elements */
-#define MAXNN 64          /* (p+1)^3 */
 
 /* ------------------------------------------------------------------------- */
 /* reference element                                                          */
@@ -109,18 +108,9 @@ double or_lagrange_deriv(int p, int a, double x)
     return s;
 }
 
-typedef struct {
-    int p, n1, nn, nq;
-    double xg[MAXN1], wg[MAXN1];
-    double N[MAXNN][MAXNN];        /* N[a][q] */
-    double dN[MAXNN][MAXNN][3];    /* reference gradient of N_a at xi_q */
-    double wq[MAXNN];              /* tensor quadrature weight (reference cell) */
-    double xi[MAXNN][3];           /* reference qp coordinates */
-} ref_elem;
-
 /* Shape functions N_a(xi) = l_ax(xi_x) l_ay(xi_y) l_az(xi_z) (eq. bubnov_galerkin
  * with tensor-product Lagrange polynomials), tabulated at the tensor Gauss rule. */
-static int make_ref(int p, ref_elem *R)
+int or_make_ref(int p, ref_elem *R)
 {
     if (p < 1 || p > MAXN1 - 1) return -1;
     R->p = p;
@@ -320,7 +310,7 @@ static int64_t cell_node(const or_problem *P, int cx, int cy, int cz, int a)
 void or_init_history(const or_problem *P, double *rc)
 {
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
-    make_ref(P->degree, R);
+    or_make_ref(P->degree, R);
     double hz = P->Lz / P->nz;
     int64_t idx = 0;
     for (int cz = 0; cz < P->nz; ++cz)
@@ -424,7 +414,7 @@ static int assemble_mode(const or_problem *P, const double *T, double *rc, doubl
                          double *C, double *fvol, int hist)
 {
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
-    if (!R || make_ref(P->degree, R)) { free(R); return -1; }
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
     int64_t N = or_n_dofs(P);
     memset(f, 0, sizeof(double) * N);
     memset(C, 0, sizeof(double) * N);
@@ -471,7 +461,7 @@ int or_explicit_step_sampled(const or_problem *P, const double *T, const double 
                              double dt, int n_nodes, const int64_t *nodes, double *T_new)
 {
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
-    if (!R || make_ref(P->degree, R)) { free(R); return -1; }
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
     double fe[MAXNN], ce[MAXNN], fv[MAXNN], rtmp[MAXNN];
     int p = P->degree, n1 = p + 1;
     for (int s = 0; s < n_nodes; ++s) {
@@ -559,7 +549,7 @@ double or_stability_lambda(const or_problem *P, const double *v0, int iters)
 int or_capacity_apply(const or_problem *P, const double *Tn, const double *x, double *y)
 {
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
-    if (!R || make_ref(P->degree, R)) { free(R); return -1; }
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
     double h[3] = {P->Lx / P->nx, P->Ly / P->ny, P->Lz / P->nz};
     double detJ = h[0] * h[1] * h[2];
     int64_t N = or_n_dofs(P);
@@ -646,7 +636,7 @@ int or_implicit_step(const or_problem *P, const double *Tn, double *rc, double t
                      double *T_out, int *cg_iters_total, int *picard_iters, double *final_rel_res)
 {
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
-    if (!R || make_ref(P->degree, R)) { free(R); return -1; }
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
     int64_t N = or_n_dofs(P), nq = or_n_qp(P);
     double *Ti = T_out;
     double *res = calloc(N, sizeof(double)), *f = calloc(N, sizeof(double)),
@@ -780,7 +770,7 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
                    double *dJ_dW, double *T_final, double *lam0)
 {
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
-    if (!R || make_ref(P->degree, R)) { free(R); return -1; }
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
     int64_t N = or_n_dofs(P), nq = or_n_qp(P);
     double *Ts = (double *)malloc(sizeof(double) * N * (n_steps + 1));
     double *Rs = (double *)malloc(sizeof(double) * nq * (n_steps + 1)); /* r^{n-1} for n = 0..N */

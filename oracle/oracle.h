@@ -81,4 +81,29 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
 #ifdef __cplusplus
 }
 #endif
+/* ---- octree meshes with hanging nodes (octree.c) ---------------------------
+ * leaves: n_leaves rows (level, ix, iy, iz), origin in units of the finest cell
+ * (coarse cell size / 2^max_level); P->nx.. give the coarse cells.  Dof order:
+ * regular nodes sorted by (z, y, x).  History: leaf-major, nq per leaf.
+ * hist: 0 update (explicit step), 1 peek, 2 lagged. */
+typedef struct or_octree or_octree;
+or_octree *or_oct_build(const or_problem *P, int max_level, int64_t n_leaves, const int64_t *leaves);
+void or_oct_free(or_octree *O);
+int64_t or_oct_n_dofs(const or_octree *O);
+int64_t or_oct_n_hanging(const or_octree *O);
+int64_t or_oct_n_qp(const or_octree *O);
+void or_oct_dof_coords(const or_octree *O, double *xyz);
+void or_oct_dirichlet(const or_octree *O, int *flag);
+void or_oct_init_history(const or_octree *O, double *rc);
+int or_oct_assemble(const or_octree *O, const double *T, double *rc, double t, double *f, double *C,
+                    double *fvol, int hist);
+int or_oct_explicit_steps(const or_octree *O, double *T, double *rc, double t0, double dt, int n);
+double or_oct_stability_lambda(const or_octree *O, const double *v0, int iters);
+int or_oct_implicit_step(const or_octree *O, const double *Tn, double *rc, double t, double dt,
+                         double cg_rtol, int cg_max_it, double picard_tol, int picard_max_it,
+                         double *T_out, int *cg_iters_total, int *picard_iters, double *final_rel_res);
+int or_oct_probe(const or_octree *O, const double *T, int n, const double *pts, double *vals);
+int or_oct_transfer(const or_octree *Oo, const double *To, const double *rco, const or_octree *On,
+                    double *Tn, double *rcn);
+
 #endif

@@ -58,6 +58,15 @@ class Problem:
     seed: int = 0
     probes: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     targets: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    # octree meshes: nx, ny, nz are the coarse (level 0) cells; leaves (n, 4) hold
+    # (level, ix, iy, iz) with the origin in units of the finest cell size
+    max_level: int = 0
+    refine_radius: float = 0.0
+    refine_ahead: float = 0.0   # path length refined ahead of the beam
+    remesh_every: int = 0
+    leaves: np.ndarray = None
+    implicit_steps: int = 0
+    implicit_dt: float = 0.0
 
     # --- counting helpers (mesh bookkeeping only) ---
     @property
@@ -205,4 +214,118 @@ def seeded_vector(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)
 
 
-CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg4": cfg4, "cfg5": cfg5}
+# ---------------------------------------------------------------------------
+# octree meshes
+# ---------------------------------------------------------------------------
+def path_points(p: Problem, s_lo: float, s_hi: float, spacing: float) -> np.ndarray:
+    """Beam centres along the scan path between arc lengths s_lo and s_hi
+    (tracks in order, arc length measured from the first track's start), sampled
+    at most `spacing` apart, shape (m, 3)."""
+    out = []
+    s0 = 0.0
+    for tr in p.tracks:
+        a, b = np.asarray(tr[0:3]), np.asarray(tr[3:6])
+        length = float(np.linalg.norm(b - a))
+        lo, hi = max(s_lo, s0), min(s_hi, s0 + length)
+        if hi >= lo:
+            n = max(2, int(np.ceil((hi - lo) / spacing)) + 1)
+            u = (np.linspace(lo, hi, n) - s0) / length
+            out.append(a[None, :] + u[:, None] * (b - a)[None, :])
+        s0 += length
+    return np.concatenate(out) if out else np.zeros((0, 3))
+
+
+def beam_arc_length(p: Problem, t: float) -> float:
+    """Arc length of the beam position at time t along the scan path."""
+    s, tk = 0.0, p.t_start
+    for tr in p.tracks:
+        length = float(np.linalg.norm(np.asarray(tr[3:6]) - np.asarray(tr[0:3])))
+        dur = length / tr[6]
+        if t < tk + dur:
+            return s + max(0.0, t - tk) * tr[6]
+        s += length
+        tk += dur
+    return s
+
+
+def _morton(ix, iy, iz):
+    key = np.zeros(len(ix), dtype=np.int64)
+    for b in range(21):
+        key |= ((ix >> b) & 1) << (3 * b) | ((iy >> b) & 1) << (3 * b + 1) | ((iz >> b) & 1) << (3 * b + 2)
+    return key
+
+
+def octree_leaves(p: Problem, s_hi: float, s_lo: float = 0.0) -> np.ndarray:
+    """Leaves (level, ix, iy, iz) of an octree over p's coarse box, origins in
+    units of the finest cell: a level-l cell is split when its distance to the
+    sampled beam path between arc lengths s_lo and s_hi is below R_{l+1}, with
+    R_max = p.refine_radius and R_l = R_{l+1} + (diagonal of a level-l cell).
+    The graded radii make the tree 2:1 balanced across faces, edges and
+    vertices (a leaf touching a leaf two levels finer would be closer to the
+    path than its own radius).  Leaves are returned in Morton order."""
+    L = np.asarray(p.L, dtype=np.float64)
+    n0 = np.array([p.nx, p.ny, p.nz])
+    maxl = p.max_level
+    h0 = L / n0
+    unit = h0 / 2 ** maxl
+    R = np.zeros(maxl + 1)
+    R[maxl] = p.refine_radius
+    for l in range(maxl - 1, -1, -1):
+        R[l] = R[l + 1] + float(np.linalg.norm(h0 / 2 ** l))
+    pts = path_points(p, s_lo, s_hi, spacing=0.5 * float(unit.min()))
+    g = np.stack(np.meshgrid(np.arange(p.nx), np.arange(p.ny), np.arange(p.nz), indexing="ij"),
+                 -1).reshape(-1, 3).astype(np.int64) * 2 ** maxl
+    out = []
+    for l in range(maxl + 1):
+        size = 2 ** (maxl - l)
+        split = np.zeros(len(g), dtype=bool)
+        if l < maxl and len(pts) and len(g):
+            lo, hi = g * unit, (g + size) * unit
+            d2 = np.full(len(g), np.inf)
+            for c0 in range(0, len(pts), 256):
+                q = pts[c0:c0 + 256]
+                e = np.maximum(np.maximum(lo[:, None, :] - q[None], 0.0), q[None] - hi[:, None, :])
+                d2 = np.minimum(d2, (e * e).sum(-1).min(1))
+            split = d2 < R[l + 1] ** 2
+        keep = g[~split]
+        out.append(np.concatenate([np.full((len(keep), 1), l, dtype=np.int64), keep], 1))
+        half = size // 2
+        par = g[split]
+        if l < maxl and len(par):
+            off = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1)], dtype=np.int64) * half
+            g = (par[:, None, :] + off[None]).reshape(-1, 3)
+        else:
+            g = np.zeros((0, 3), dtype=np.int64)
+    leaves = np.concatenate(out)
+    order = np.argsort(_morton(leaves[:, 1], leaves[:, 2], leaves[:, 3]), kind="stable")
+    return np.ascontiguousarray(leaves[order])
+
+
+def with_leaves(p: Problem, s_hi: float, s_lo: float = 0.0) -> Problem:
+    return p.replace(leaves=octree_leaves(p, s_hi, s_lo))
+
+
+def cfg3() -> Problem:
+    """Q2 octree over a 10x10x5 mm part: coarse 20x20x10 cells refined to level 6
+    (7.8 um) within 200 um of the scanned path and 50 um ahead of the beam,
+    cfg2's law, a 10-track zigzag of 1 mm tracks at the centre of the top face;
+    2000 explicit steps with a remesh every 100, then 50 backward-Euler steps of
+    1 ms with the laser off."""
+    p = _base_nonlinear("cfg3_q2_octree", 2302, 20, 20, 10, (10e-3, 10e-3, 5e-3), 2000)
+    p = p.replace(max_level=6, refine_radius=200e-6, refine_ahead=50e-6, remesh_every=100,
+                  implicit_steps=50, implicit_dt=1e-3)
+    return with_leaves(p, p.refine_ahead)
+
+
+def small_octree(degree=2, max_level=2, seed=2302, ahead=60e-6, radius=40e-6) -> Problem:
+    """cfg3's physics on a 3x2x2-cell coarse box of 0.375x0.25x0.25 mm refined to
+    level `max_level` around the start of the scan (sizes the oracle runs in
+    seconds)."""
+    h = 125e-6
+    p = _base_nonlinear(f"small_octree_q{degree}", seed, 3, 2, 2, (3 * h, 2 * h, 2 * h), 0,
+                        track_length=0.2e-3, n_tracks=2, hatch=60e-6)
+    p = p.replace(degree=degree, max_level=max_level, refine_radius=radius, refine_ahead=ahead)
+    return with_leaves(p, ahead)
+
+
+CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4, "cfg5": cfg5}
