@@ -74,6 +74,43 @@ const char *pbf_last_error(const pbf_ctx *ctx);
  * (degree+1)^3-point Gauss rule.  Resets material, laser and binding. */
 pbf_status pbf_mesh_box(pbf_ctx *ctx, int degree, int nx, int ny, int nz, double Lx, double Ly,
                         double Lz);
+/* ---- octree meshes with hanging nodes (Section 4.2: the gather includes the
+ * hanging-node constraints) -----------------------------------------------------
+ * Coarse box of nx*ny*nz cells of [0,Lx]x[0,Ly]x[0,Lz], refined into the given
+ * leaves: n_leaves rows (level, ix, iy, iz) of int32, level in [0, max_level]
+ * (max_level <= 15), origin in units of the finest cell (coarse cell /
+ * 2^max_level), aligned to the leaf size.  The leaves must tile the box without
+ * overlap and be 2:1 balanced across faces, edges and vertices (else
+ * PBF_EMESH); Morton order is recommended (memory locality).  Nodes of a leaf
+ * that lie on a face of a coarser leaf without being one of its nodes hang:
+ * their value is the coarse leaf's interpolant there (chains are expanded to
+ * regular nodes, the dofs).  Dofs are numbered in order of first appearance;
+ * pbf_dof_coords gives their coordinates.  The history is stored for the leaves
+ * with a Gauss point at most powder_depth below the top face (point-major over
+ * those leaves, in leaf order).  Explicit, assembly, stability, energy and
+ * implicit calls work on octrees (FP64); probes and the adjoint need a box.
+ * Resets material, laser and binding like pbf_mesh_box. */
+pbf_status pbf_mesh_octree(pbf_ctx *ctx, int degree, int nx, int ny, int nz, double Lx, double Ly,
+                           double Lz, int max_level, int64_t n_leaves, const int32_t *leaves);
+/* leaves, hanging nodes and finest level of the current octree mesh */
+pbf_status pbf_octree_info(const pbf_ctx *ctx, int64_t *n_leaves, int64_t *n_hanging, int *max_level);
+/* Remesh onto new leaves (same coarse box, degree and max_level).
+ * pbf_octree_remesh_bytes builds the new mesh on the host and returns the size
+ * of its workspace and its numbers of dofs and history points (outputs may be
+ * NULL except bytes).  pbf_octree_remesh binds that workspace (256-byte aligned)
+ * and transfers the state: T_new (new n_dofs) is the old finite element field
+ * at the new dofs; each new history point takes the value of the nearest old
+ * Gauss point in the old leaf containing it if that point lies within the
+ * powder depth, else its initial value.  The old workspace and arrays must stay
+ * valid until the call returns; afterwards the context works on the new mesh.
+ * Synchronizes. */
+pbf_status pbf_octree_remesh_bytes(pbf_ctx *ctx, int64_t n_leaves, const int32_t *leaves, size_t *bytes,
+                                   int64_t *new_n_dofs, int64_t *new_n_hist_qp);
+pbf_status pbf_octree_remesh(pbf_ctx *ctx, void *workspace, size_t bytes, const double *T_old,
+                             const double *rc_old, double *T_new, double *rc_new, void *stream);
+/* coordinates of the dofs (host array of 3*n_dofs), boxes and octrees */
+pbf_status pbf_dof_coords(const pbf_ctx *ctx, double *xyz);
+
 /* Sizes of the current mesh; any output pointer may be NULL.  n_hist_* depend
  * on the powder depth of the material and are 0 before pbf_set_material. */
 pbf_status pbf_mesh_info(const pbf_ctx *ctx, int64_t *n_dofs, int64_t *n_cells, int64_t *n_qp,

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpbftherm.so")
-SOURCES = ["explicit.hip", "implicit.hip", "adjoint.hip", "vec.hip", "revolve.cpp", "capi.cpp"]
+SOURCES = ["explicit.hip", "implicit.hip", "adjoint.hip", "octree.hip", "vec.hip", "revolve.cpp",
+           "octree_mesh.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-x", "hip",

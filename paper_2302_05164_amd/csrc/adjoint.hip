@@ -280,15 +280,6 @@ __global__ void __launch_bounds__(256) k_adjoint_params(const double *dJdW, cons
     }
 }
 
-// 1D Lagrange basis on the equispaced nodes of [0,1]
-__device__ __forceinline__ double lagrange1(int P, int a, double x)
-{
-    if (P == 1) return a == 0 ? 1.0 - x : x;
-    if (a == 0) return 2.0 * (x - 0.5) * (x - 1.0);
-    if (a == 1) return 4.0 * x * (1.0 - x);
-    return 2.0 * x * (x - 0.5);
-}
-
 __device__ __forceinline__ long long probe_node(const ProbeSet &ps, int p, int a, double *wgt)
 {
     const int N = ps.P + 1;

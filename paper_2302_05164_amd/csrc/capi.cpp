@@ -55,6 +55,17 @@ struct pbf_ctx {
     std::vector<int> probe_cell;
     std::vector<double> probe_xi, probe_target;
     bool probes_dirty = false;
+    // octree mesh (when octree is set, nx, ny, nz are the coarse cells)
+    bool octree = false;
+    bool oct_flags_dirty = false;  // Dirichlet flags / history leaves changed since the upload
+    OctMesh oct;
+    OctDev od{};
+    struct {                // remesh prepared by pbf_octree_remesh_bytes
+        bool ready = false;
+        OctMesh mesh;
+        std::vector<int32_t> cell, src;  // per new dof: old leaf; per new history point: source
+        std::vector<double> xi;          // per new dof: reference coordinates in the old leaf
+    } pending;
     // last gradient forward sweep (checked by the backward sweep)
     struct {
         const void *work = nullptr;
@@ -99,10 +110,16 @@ long long nodes1(const pbf_ctx *c, int d)
     const int n = d == 0 ? c->nx : (d == 1 ? c->ny : c->nz);
     return (long long)c->degree * n + 1;
 }
-long long n_dofs(const pbf_ctx *c) { return nodes1(c, 0) * nodes1(c, 1) * nodes1(c, 2); }
-long long n_cells(const pbf_ctx *c) { return (long long)c->nx * c->ny * c->nz; }
+long long n_dofs(const pbf_ctx *c)
+{
+    return c->octree ? c->oct.n_dofs : nodes1(c, 0) * nodes1(c, 1) * nodes1(c, 2);
+}
+long long n_cells(const pbf_ctx *c) { return c->octree ? c->oct.n_cells : (long long)c->nx * c->ny * c->nz; }
 int nq1(const pbf_ctx *c) { return c->degree + 1; }
-long long n_hist_cells(const pbf_ctx *c) { return (long long)c->nx * c->ny * c->hist_layers; }
+long long n_hist_cells(const pbf_ctx *c)
+{
+    return c->octree ? c->oct.n_hist_cells : (long long)c->nx * c->ny * c->hist_layers;
+}
 long long n_hist_qp(const pbf_ctx *c)
 {
     const long long q = nq1(c);
@@ -123,6 +140,10 @@ void compute_history_layers(pbf_ctx *c)
 {
     c->hist_layers = 0;
     c->powder_levels.clear();
+    if (c->octree && c->has_mesh) {
+        oct_finish(c->oct, c->dmask, c->has_material ? c->powder_depth : -1.0);
+        return;
+    }
     if (!c->has_mesh || !c->has_material) return;
     const double hz = c->L[2] / c->nz;
     const int n1 = nq1(c);
@@ -247,6 +268,15 @@ int segment_length(const pbf_ctx *c, int ty, int resident_per_cu)
 // number of resident workgroups per CU (explicit kernels by default).
 HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
 {
+    if (c->octree) {  // dof vectors with per-dof Dirichlet flags
+        HaloParams h{};
+        h.NX = (int)c->oct.n_dofs;
+        h.NY = h.NZ = 1;
+        h.T_D = c->T_D;
+        h.dflag = c->od.dflag;
+        h.nlaw = c->d_law64;
+        return h;
+    }
     if (ty < 0) {
         ty = column_height();
         resident = resident_columns_per_cu(ty);
@@ -352,8 +382,14 @@ pbf_status check_bound(pbf_ctx *c)
     return PBF_OK;
 }
 
+pbf_status oct_upload(pbf_ctx *c, hipStream_t s, bool all);
+
 pbf_status upload_laws(pbf_ctx *c, hipStream_t s)
 {
+    if (c->octree && c->oct_flags_dirty) {  // Dirichlet flags and history leaves
+        pbf_status st = oct_upload(c, s, false);
+        if (st) return st;
+    }
     if (!c->laws_dirty) return PBF_OK;
     build_law<double>(c, 0.0, false, 0, c->h_law64);
     build_law<float>(c, c->Tref, false, 0, c->h_law32);
@@ -373,11 +409,62 @@ pbf_status upload_laws(pbf_ctx *c, hipStream_t s)
 // breakpoint (stability estimate), or k = 0 (source terms only)
 enum { LAW_FULL = 0, LAW_CRITICAL = 1, LAW_SOURCE = 2 };
 
+OctParams oct_params(const pbf_ctx *c, const Law<double> *law, const Beam &bm)
+{
+    OctParams p{};
+    p.m = c->od;
+    p.law = law;
+    p.laser_kind = c->laser_kind;
+    p.h_powder = c->h_powder;
+    p.two_over_R2 = c->radius > 0 ? 2.0 / (c->radius * c->radius) : 0.0;
+    if (bm.on) {
+        const double PI = 3.14159265358979323846, R2 = c->radius * c->radius;
+        p.laser_on = 1;
+        p.xb = bm.xb;
+        p.yb = bm.yb;
+        p.src_amp = c->laser_kind == 1 ? 2.0 * bm.W / (PI * R2 * c->h_powder) : 2.0 * bm.W / (PI * R2);
+    }
+    return p;
+}
+
+// operator pass on an octree: cell pass into the element buffer, node pass
+pbf_status oct_pass(pbf_ctx *c, int mode, int law, const double *Tin, double *Tout, double *f, double *C,
+                    double *rc, double t, double dt, hipStream_t s, bool hist_write)
+{
+    const Law<double> *L = law == LAW_FULL ? c->d_law64 : (law == LAW_CRITICAL ? c->d_lin64 : c->d_zero64);
+    const Beam off{false, 0, 0, 0, -1};
+    OctParams p = oct_params(c, L, law == LAW_CRITICAL ? off : beam_at(c, t));
+    p.Tin = Tin;
+    p.hist = rc;
+    p.has_hist = law == LAW_FULL && rc != nullptr;
+    p.hist_write = hist_write ? 1 : 0;
+    const bool timed = c->timing && mode == 0 && c->tev_used + 3 <= c->tev.size();
+    if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used], s));
+    PBF_HIP(c, launch_oct_cells(c->degree, p, s));
+    if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
+    OctNodeParams np{};
+    np.m = c->od;
+    np.Tin = Tin;
+    np.Tout = Tout;
+    np.fout = f;
+    np.Cout = C;
+    np.dt = dt;
+    np.T_D = c->T_D;
+    np.nlaw = law == LAW_CRITICAL ? c->d_lin64 : c->d_law64;
+    PBF_HIP(c, launch_oct_nodes(mode, np, s));
+    if (timed) {
+        PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 2], s));
+        c->tev_used += 3;
+    }
+    return PBF_OK;
+}
+
 // one operator pass: MODE 0 explicit step Tin -> Tout, MODE 1 assemble into f, C
 pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const double *Tin,
                          double *Tout, double *f, double *C, double *rc, double t, double dt,
                          hipStream_t s, bool hist_write = true)
 {
+    if (c->octree) return oct_pass(c, mode, law, Tin, Tout, f, C, rc, t, dt, s, hist_write);
     const bool linear = law == LAW_CRITICAL;
     CellParams<double> pd{};
     CellParams<float> pf{};
@@ -475,6 +562,33 @@ PicardParams picard_params(const pbf_ctx *c, const HaloParams &h, const double *
     }
     q.law = c->d_law64;
     return q;
+}
+
+// Picard operator pass (mode 0 apply into y, 1 diagonal into y) on boxes or octrees
+pbf_status picard_pass(pbf_ctx *c, int mode, const HaloParams &hp, const double *Tc, const double *Tk,
+                       const double *x1, const double *x2, double *y, const double *rc, double dt,
+                       const Beam *src, hipStream_t s)
+{
+    if (!c->octree) {
+        const PicardParams q = picard_params(c, hp, Tc, Tk, x1, x2, y, rc, dt, src);
+        PBF_HIP(c, launch_picard(c->degree, mode, q, hp, s));
+        return PBF_OK;
+    }
+    const Beam off{false, 0, 0, 0, -1};
+    OctParams p = oct_params(c, c->d_law64, (src && mode == 0) ? *src : off);
+    p.Tc = Tc;
+    p.Tk = Tk;
+    p.x1 = x1;
+    p.x2 = x2;
+    p.hist = const_cast<double *>(rc);
+    p.has_hist = rc != nullptr;
+    p.inv_dt = 1.0 / dt;
+    PBF_HIP(c, launch_oct_picard(c->degree, mode, p, s));
+    OctNodeParams np{};
+    np.m = c->od;
+    np.Tout = y;
+    PBF_HIP(c, launch_oct_nodes(mode == 0 ? 2 : 3, np, s));
+    return PBF_OK;
 }
 
 // ---- probes and adjoint ------------------------------------------------------
@@ -654,6 +768,77 @@ pbf_status run_actions(pbf_ctx *c, const std::vector<pbf_revolve_action> &acts, 
     return PBF_OK;
 }
 
+// octree tables in the workspace: the bytes they take and, when base is not
+// NULL, the device view carved from base into c->od (sizing leaves c untouched)
+size_t oct_tables(pbf_ctx *c, char *base)
+{
+    if (!c->octree) return 0;
+    const OctMesh &m = c->oct;
+    const int NN = nq1(c) * nq1(c) * nq1(c);
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        char *p = base ? base + off : nullptr;
+        off += align256(n);
+        return p;
+    };
+    OctDev tmp{};
+    OctDev &d = base ? c->od : tmp;
+    d.cidx = (const int32_t *)take(m.cidx.size() * 4);
+    d.hstart = (const int32_t *)take(m.hstart.size() * 4);
+    d.hdof = (const int32_t *)take(m.hdof.size() * 4);
+    d.hw = (const double *)take(m.hw.size() * 8);
+    d.leaf = (const int32_t *)take(m.leaf.size() * 4);
+    d.cell_hist = (const int32_t *)take((size_t)m.n_cells * 4);
+    d.nstart = (const int32_t *)take(m.nstart.size() * 4);
+    d.nslot = (const int32_t *)take(m.nslot.size() * 4);
+    d.nw = (const double *)take(m.nw.size() * 8);
+    d.mass = (const double *)take(m.mass.size() * 8);
+    d.dflag = (const unsigned char *)take((size_t)m.n_dofs);
+    d.hist_z = (const double *)take(std::max<size_t>(m.hist_z.size(), 2) * 8);
+    d.E = (double *)take((size_t)NN * m.n_cells * 8);
+    d.n_cells = (int)m.n_cells;
+    d.n_dofs = (int)m.n_dofs;
+    d.n_hist_cells = (int)m.n_hist_cells;
+    d.maxl = m.maxl;
+    d.top_iz = m.n0[2] << m.maxl;
+    d.ux = m.unit[0];
+    d.uy = m.unit[1];
+    d.uz = m.unit[2];
+    d.Lz = m.L[2];
+    return off;
+}
+
+pbf_status oct_upload(pbf_ctx *c, hipStream_t s, bool all)
+{
+    const OctMesh &m = c->oct;
+    const OctDev &d = c->od;
+    auto put = [&](const void *dst, const void *src, size_t n) -> hipError_t {
+        return n ? hipMemcpyAsync(const_cast<void *>(dst), src, n, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    c->oct_flags_dirty = false;
+    if (!all) {
+        PBF_HIP(c, put(d.dflag, m.dflag.data(), m.dflag.size()));
+        PBF_HIP(c, put(d.cell_hist, m.cell_hist.data(), m.cell_hist.size() * 4));
+        PBF_HIP(c, put(d.hist_z, m.hist_z.data(), m.hist_z.size() * 8));
+        PBF_HIP(c, hipStreamSynchronize(s));
+        return PBF_OK;
+    }
+    PBF_HIP(c, put(d.cidx, m.cidx.data(), m.cidx.size() * 4));
+    PBF_HIP(c, put(d.hstart, m.hstart.data(), m.hstart.size() * 4));
+    PBF_HIP(c, put(d.hdof, m.hdof.data(), m.hdof.size() * 4));
+    PBF_HIP(c, put(d.hw, m.hw.data(), m.hw.size() * 8));
+    PBF_HIP(c, put(d.leaf, m.leaf.data(), m.leaf.size() * 4));
+    PBF_HIP(c, put(d.cell_hist, m.cell_hist.data(), m.cell_hist.size() * 4));
+    PBF_HIP(c, put(d.nstart, m.nstart.data(), m.nstart.size() * 4));
+    PBF_HIP(c, put(d.nslot, m.nslot.data(), m.nslot.size() * 4));
+    PBF_HIP(c, put(d.nw, m.nw.data(), m.nw.size() * 8));
+    PBF_HIP(c, put(d.mass, m.mass.data(), m.mass.size() * 8));
+    PBF_HIP(c, put(d.dflag, m.dflag.data(), m.dflag.size()));
+    PBF_HIP(c, put(d.hist_z, m.hist_z.data(), m.hist_z.size() * 8));
+    PBF_HIP(c, hipStreamSynchronize(s));
+    return PBF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -690,6 +875,8 @@ pbf_status pbf_mesh_box(pbf_ctx *c, int degree, int nx, int ny, int nz, double L
     if (NX > (1 << 30) || NY > (1 << 30) || NZ > (1 << 30) || NX * NY * NZ > (1LL << 40))
         return fail(c, PBF_EMESH, "mesh too large");
     c->has_mesh = true;
+    c->octree = false;
+    c->oct = OctMesh{};
     c->degree = degree;
     c->nx = nx;
     c->ny = ny;
@@ -700,6 +887,67 @@ pbf_status pbf_mesh_box(pbf_ctx *c, int degree, int nx, int ny, int nz, double L
     c->bound = false;
     c->laws_dirty = true;
     compute_history_layers(c);
+    return PBF_OK;
+}
+
+pbf_status pbf_mesh_octree(pbf_ctx *c, int degree, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                           int max_level, int64_t n_leaves, const int32_t *leaves)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "pbf_mesh_octree: ctx is NULL");
+    if (degree != 1 && degree != 2) return fail(c, PBF_EMESH, "degree %d not supported (1 or 2)", degree);
+    if (nx < 1 || ny < 1 || nz < 1) return fail(c, PBF_EINVAL, "coarse cell counts must be >= 1");
+    if (!(Lx > 0 && Ly > 0 && Lz > 0)) return fail(c, PBF_EINVAL, "box lengths must be > 0");
+    if (!leaves) return fail(c, PBF_EINVAL, "leaves is NULL");
+    const int n0[3] = {nx, ny, nz};
+    const double L[3] = {Lx, Ly, Lz};
+    OctMesh m;
+    std::string err;
+    if (!oct_build(m, degree, max_level, n0, L, n_leaves, leaves, err)) return fail(c, PBF_EMESH, "%s", err.c_str());
+    c->has_mesh = true;
+    c->octree = true;
+    c->oct = std::move(m);
+    c->degree = degree;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->L[0] = Lx;
+    c->L[1] = Ly;
+    c->L[2] = Lz;
+    c->bound = false;
+    c->laws_dirty = true;
+    c->pending.ready = false;
+    compute_history_layers(c);
+    return PBF_OK;
+}
+
+pbf_status pbf_octree_info(const pbf_ctx *c, int64_t *n_leaves, int64_t *n_hanging, int *max_level)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->has_mesh || !c->octree) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no octree mesh");
+    if (n_leaves) *n_leaves = c->oct.n_cells;
+    if (n_hanging) *n_hanging = c->oct.n_hanging;
+    if (max_level) *max_level = c->oct.maxl;
+    return PBF_OK;
+}
+
+pbf_status pbf_dof_coords(const pbf_ctx *c, double *xyz)
+{
+    if (!c || !xyz) return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "NULL argument");
+    if (!c->has_mesh) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no mesh");
+    if (c->octree) {
+        std::copy(c->oct.coords.begin(), c->oct.coords.end(), xyz);
+        return PBF_OK;
+    }
+    const long long NX = nodes1(c, 0), NY = nodes1(c, 1), NZ = nodes1(c, 2);
+    const double h[3] = {c->L[0] / c->nx / c->degree, c->L[1] / c->ny / c->degree, c->L[2] / c->nz / c->degree};
+    for (long long k = 0; k < NZ; ++k)
+        for (long long j = 0; j < NY; ++j)
+            for (long long i = 0; i < NX; ++i) {
+                double *x = xyz + 3 * (i + NX * (j + NY * k));
+                x[0] = i * h[0];
+                x[1] = j * h[1];
+                x[2] = k * h[2];
+            }
     return PBF_OK;
 }
 
@@ -725,6 +973,10 @@ pbf_status pbf_set_dirichlet(pbf_ctx *c, unsigned face_mask, double T_D)
     if (!std::isfinite(T_D)) return fail(c, PBF_EINVAL, "T_D must be finite");
     c->dmask = face_mask;
     c->T_D = T_D;
+    if (c->octree) {
+        compute_history_layers(c);
+        c->oct_flags_dirty = true;
+    }
     return PBF_OK;
 }
 
@@ -760,8 +1012,11 @@ pbf_status pbf_set_material(pbf_ctx *c, const pbf_material *m)
     c->has_material = true;
     c->laws_dirty = true;
     const int old_layers = c->hist_layers;
+    const long long old_hist_cells = n_hist_cells(c);
     compute_history_layers(c);
-    if (c->bound && c->hist_layers != old_layers) c->bound = false;  // sizes changed
+    if (c->bound && (c->hist_layers != old_layers || n_hist_cells(c) != old_hist_cells))
+        c->bound = false;  // sizes changed
+    if (c->octree) c->oct_flags_dirty = true;
     return PBF_OK;
 }
 
@@ -813,12 +1068,13 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     const size_t N = (size_t)n_dofs(c);
     size_t b = 0;
     b += align256(sizeof(Law<double>)) * 3 + align256(sizeof(Law<float>));
-    b += align256(8 * N * sizeof(double));        // parity slots
+    b += align256((c->octree ? 0 : 8 * N) * sizeof(double));  // parity slots (boxes)
     b += 11 * align256(N * sizeof(double));       // f, C, v; implicit: y, diag, r, z, p, Ap, x, d
     b += align256(kRedBlocks * 4 * sizeof(double)); // reduction partials
     b += align256(64 * sizeof(double));           // device scalars
     b += align256(adjoint_tiles(c) * sizeof(double));  // adjoint tile partials
     b += align256(3 * kMaxProbes * sizeof(int)) + align256(4 * kMaxProbes * sizeof(double));
+    b += oct_tables(const_cast<pbf_ctx *>(c), nullptr);  // octree tables and element buffer
     *bytes = b;
     return PBF_OK;
 }
@@ -843,7 +1099,7 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     c->d_law32 = (Law<float> *)p;
     p += align256(sizeof(Law<float>));
     c->d_slots = (double *)p;
-    p += align256(8 * N * sizeof(double));
+    p += align256((c->octree ? 0 : 8 * N) * sizeof(double));
     c->d_f = (double *)p;
     p += align256(N * sizeof(double));
     c->d_C = (double *)p;
@@ -864,7 +1120,13 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     p += align256(3 * kMaxProbes * sizeof(int));
     c->d_probe_xi = (double *)p;
     c->d_probe_target = c->d_probe_xi + 3 * kMaxProbes;
+    p += align256(4 * kMaxProbes * sizeof(double));
     c->probes_dirty = !c->probe_target.empty();
+    if (c->octree) {
+        compute_history_layers(c);  // Dirichlet flags and history leaves for the current setup
+        oct_tables(c, p);
+        if ((st = oct_upload(c, (hipStream_t)stream, true))) return st;
+    }
     c->ws = (char *)workspace;
     c->ws_bytes = bytes;
     c->bound = true;
@@ -889,9 +1151,13 @@ pbf_status pbf_init_state(pbf_ctx *c, double T0, double *T, double *rc, void *st
     if ((st = upload_laws(c, s))) return st;
     PBF_HIP(c, launch_fill(T, T0, n_dofs(c), s));
     PBF_HIP(c, launch_init_dirichlet(T, geometry(c), c->T_D, s));
-    if (n_hist_qp(c) > 0)
-        PBF_HIP(c, launch_init_history(rc, (int)n_hist_cells(c), nq1(c), c->powder_levels.data(),
-                                       c->hist_layers, c->nx, c->ny, s));
+    if (n_hist_qp(c) > 0) {
+        if (c->octree)
+            PBF_HIP(c, launch_oct_init_history(c->od, c->degree, c->powder_depth, rc, s));
+        else
+            PBF_HIP(c, launch_init_history(rc, (int)n_hist_cells(c), nq1(c), c->powder_levels.data(),
+                                           c->hist_layers, c->nx, c->ny, s));
+    }
     return PBF_OK;
 }
 
@@ -907,6 +1173,7 @@ pbf_status pbf_explicit_steps(pbf_ctx *c, double *T, double *T_tmp, double *rc, 
     if (!(dt > 0) || !std::isfinite(t0)) return fail(c, PBF_EINVAL, "need dt > 0 and finite t0");
     if (precision != PBF_PREC_FP64 && precision != PBF_PREC_FP32)
         return fail(c, PBF_EINVAL, "precision must be 64 or 32");
+    if (c->octree && precision != PBF_PREC_FP64) return fail(c, PBF_EINVAL, "octree meshes run in FP64 only");
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_laws(c, s))) return st;
     double *cur = T, *nxt = T_tmp;
@@ -930,6 +1197,7 @@ pbf_status pbf_assemble(pbf_ctx *c, const double *T, double *rc, double t, doubl
     if (n_hist_qp(c) > 0 && !rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
     if (precision != PBF_PREC_FP64 && precision != PBF_PREC_FP32)
         return fail(c, PBF_EINVAL, "precision must be 64 or 32");
+    if (c->octree && precision != PBF_PREC_FP64) return fail(c, PBF_EINVAL, "octree meshes run in FP64 only");
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_laws(c, s))) return st;
     return operator_pass(c, 1, precision, LAW_FULL, T, nullptr, f, C, rc, t, 0.0, s);
@@ -995,10 +1263,8 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
     for (it = 0; it < picard_max_it;) {
         // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_vol, and diag(A(T^i))
         PBF_HIP(c, launch_sub(d, Ti, T_n, N, s));
-        PicardParams qa = picard_params(c, hp, T_n, Ti, d, Ti, y, rc, dt, &bm);
-        PBF_HIP(c, launch_picard(c->degree, 0, qa, hp, s));
-        PicardParams qd = picard_params(c, hp, T_n, Ti, nullptr, nullptr, diag, rc, dt, nullptr);
-        PBF_HIP(c, launch_picard(c->degree, 1, qd, hp, s));
+        if ((st = picard_pass(c, 0, hp, T_n, Ti, d, Ti, y, rc, dt, &bm, s))) return st;
+        if ((st = picard_pass(c, 1, hp, T_n, Ti, nullptr, nullptr, diag, rc, dt, nullptr, s))) return st;
         PBF_HIP(c, launch_cg_start(y, diag, r, z, p, x, c->d_partials, c->d_scal, ge, N, s));
         PBF_HIP(c, hipMemcpyAsync(hs, c->d_scal + CG_RZ0, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
         PBF_HIP(c, hipStreamSynchronize(s));
@@ -1006,9 +1272,8 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
         double rr = hs[CG_RR - CG_RZ0];
         int k = 0, rz_old = CG_RZ0;
         last_rel = bn > 0 ? std::sqrt(rr) / bn : 0.0;
-        PicardParams qp = picard_params(c, hp, T_n, Ti, p, p, Ap, rc, dt, nullptr);
         while (bn > 0 && std::sqrt(rr) > cg_rtol * bn && k < cg_max_it) {
-            PBF_HIP(c, launch_picard(c->degree, 0, qp, hp, s));
+            if ((st = picard_pass(c, 0, hp, T_n, Ti, p, p, Ap, rc, dt, nullptr, s))) return st;
             PBF_HIP(c, launch_cg_pap(p, Ap, c->d_partials, c->d_scal, N, s));
             PBF_HIP(c, launch_cg_update(x, r, z, p, Ap, diag, c->d_partials, c->d_scal, rz_old, N, s));
             PBF_HIP(c, hipMemcpyAsync(&rr, c->d_scal + CG_RR, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1046,6 +1311,7 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
 pbf_status pbf_set_probes(pbf_ctx *c, int n, const double *pts, const double *targets, void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (c->octree) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "probes and the adjoint need a box mesh");
     if (!c->has_mesh) return fail(c, PBF_ESTATE, "no mesh");
     if (n < 0 || n > kMaxProbes) return fail(c, PBF_EINVAL, "number of probes must be in [0, %d]", kMaxProbes);
     if (n > 0 && !pts) return fail(c, PBF_EINVAL, "pts is NULL");
@@ -1105,6 +1371,7 @@ pbf_status pbf_adjoint_step(pbf_ctx *c, const double *T_n, const double *rc_prev
                             double *lam, double *mu, double t_n, double dt, double *dJdW, void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (c->octree) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "probes and the adjoint need a box mesh");
     pbf_status st = check_bound(c);
     if (st) return st;
     if (!T_n || !lam_next || !lam) return fail(c, PBF_EINVAL, "NULL device array");
@@ -1140,6 +1407,7 @@ pbf_status pbf_revolve_schedule(int n_steps, int n_snaps, pbf_revolve_action *ac
 pbf_status pbf_adjoint_work_bytes(const pbf_ctx *c, int n_snaps, size_t *bytes)
 {
     if (!c || !bytes) return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "NULL argument");
+    if (c->octree) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "probes and the adjoint need a box mesh");
     if (!c->has_mesh) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no mesh");
     if (n_snaps < 1) return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "n_snaps must be >= 1");
     *bytes = grad_layout(c, n_snaps, nullptr).bytes;
@@ -1150,6 +1418,7 @@ static pbf_status check_grad_args(pbf_ctx *c, double dt, int n_steps, int n_snap
 {
     pbf_status st = check_bound(c);
     if (st) return st;
+    if (c->octree) return fail(c, PBF_ESTATE, "probes and the adjoint need a box mesh");
     if (!(dt > 0)) return fail(c, PBF_EINVAL, "dt must be > 0");
     if (n_steps < 1 || n_steps > (1 << 24)) return fail(c, PBF_EINVAL, "n_steps must be in [1, 2^24]");
     if (n_snaps < 1) return fail(c, PBF_EINVAL, "n_snaps must be >= 1");
@@ -1289,6 +1558,129 @@ pbf_status pbf_check_finite(pbf_ctx *c, const double *x, int64_t n, int *ok, dou
     if (ok) *ok = r[0] == 0.0;
     if (maxabs) *maxabs = r[1];
     return r[0] == 0.0 ? PBF_OK : fail(c, PBF_ENONFINITE, "%.0f non-finite values", r[0]);
+}
+
+pbf_status pbf_octree_remesh_bytes(pbf_ctx *c, int64_t n_leaves, const int32_t *leaves, size_t *bytes,
+                                   int64_t *new_n_dofs, int64_t *new_n_hist_qp)
+{
+    if (!c || !leaves || !bytes) return fail(c, PBF_EINVAL, "NULL argument");
+    if (!c->octree) return fail(c, PBF_ESTATE, "no octree mesh");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    c->pending.ready = false;
+    OctMesh nm;
+    std::string err;
+    if (!oct_build(nm, c->degree, c->oct.maxl, c->oct.n0, c->oct.L, n_leaves, leaves, err))
+        return fail(c, PBF_EMESH, "%s", err.c_str());
+    oct_finish(nm, c->dmask, c->powder_depth);
+    const OctMesh &om = c->oct;
+    const int P = c->degree, N1 = P + 1;
+    // new dofs: containing old leaf and reference coordinates
+    c->pending.cell.resize(nm.n_dofs);
+    c->pending.xi.resize(3 * nm.n_dofs);
+    for (int64_t i = 0; i < nm.n_dofs; ++i) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = double(nm.dof_key[3 * i + d]) / P;
+        const int32_t e = oct_locate(om, x, &c->pending.xi[3 * i]);
+        if (e < 0) return fail(c, PBF_EMESH, "new dof outside the old mesh");
+        c->pending.cell[i] = e;
+    }
+    // new history points: nearest old Gauss point of the containing old leaf if
+    // that point lies in the powder layer, else the initial value
+    auto gp = [&](int q) { return P == 1 ? Tables<1>::gp(q) : Tables<2>::gp(q); };
+    const int64_t nq = (int64_t)N1 * N1 * N1;
+    c->pending.src.assign(nq * nm.n_hist_cells, -2);
+    for (int64_t e = 0; e < nm.n_cells; ++e) {
+        const int32_t hc = nm.cell_hist[e];
+        if (hc < 0) continue;
+        const double s = (double)(1LL << (nm.maxl - nm.leaf[4 * e]));
+        for (int64_t q = 0; q < nq; ++q) {
+            const int qd[3] = {int(q % N1), int((q / N1) % N1), int(q / (N1 * N1))};
+            double x[3], xi[3];
+            for (int d = 0; d < 3; ++d) x[d] = nm.leaf[4 * e + 1 + d] + gp(qd[d]) * s;
+            const int32_t eo = oct_locate(om, x, xi);
+            if (eo < 0) return fail(c, PBF_EMESH, "new point outside the old mesh");
+            int qo[3];
+            for (int d = 0; d < 3; ++d) {
+                qo[d] = 0;
+                for (int j = 1; j <= P; ++j)
+                    if (std::fabs(xi[d] - gp(j)) < std::fabs(xi[d] - gp(qo[d]))) qo[d] = j;
+            }
+            const double so = (double)(1LL << (om.maxl - om.leaf[4 * eo]));
+            const double zo = om.leaf[4 * eo + 3] * om.unit[2] + gp(qo[2]) * (so * om.unit[2]);
+            const double zn = nm.leaf[4 * e + 3] * nm.unit[2] + gp(qd[2]) * (s * nm.unit[2]);
+            int32_t src;
+            if (om.L[2] - zo <= c->powder_depth && om.cell_hist[eo] >= 0)
+                src = (int32_t)((qo[0] + N1 * (qo[1] + N1 * qo[2])) * om.n_hist_cells + om.cell_hist[eo]);
+            else
+                src = (nm.L[2] - zn <= c->powder_depth) ? -1 : -2;
+            c->pending.src[q * nm.n_hist_cells + hc] = src;
+        }
+    }
+    std::swap(c->oct, nm);  // size the workspace of the new mesh
+    size_t b = 0;
+    st = pbf_workspace_bytes(c, &b);
+    std::swap(c->oct, nm);
+    if (st) return st;
+    b += align256(4 * (size_t)nm.n_dofs) + align256(24 * (size_t)nm.n_dofs) +
+         align256(4 * c->pending.src.size());
+    if (new_n_dofs) *new_n_dofs = nm.n_dofs;
+    if (new_n_hist_qp) *new_n_hist_qp = (int64_t)c->pending.src.size();
+    c->pending.mesh = std::move(nm);
+    c->pending.ready = true;
+    *bytes = b;
+    return PBF_OK;
+}
+
+pbf_status pbf_octree_remesh(pbf_ctx *c, void *workspace, size_t bytes, const double *T_old, const double *rc_old,
+                             double *T_new, double *rc_new, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->octree || !c->pending.ready) return fail(c, PBF_ESTATE, "call pbf_octree_remesh_bytes first");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!T_old || !T_new) return fail(c, PBF_EINVAL, "NULL temperature array");
+    if (n_hist_qp(c) > 0 && !rc_old) return fail(c, PBF_EINVAL, "rc_old is NULL but the old mesh has history");
+    if (c->pending.mesh.n_hist_cells > 0 && !rc_new)
+        return fail(c, PBF_EINVAL, "rc_new is NULL but the new mesh has history");
+    hipStream_t s = (hipStream_t)stream;
+    const OctDev old = c->od;       // old tables stay valid until this call returns
+    const int64_t old_hq = n_hist_qp(c);
+    OctMesh old_mesh = std::move(c->oct);
+    c->oct = std::move(c->pending.mesh);
+    size_t need = 0;
+    st = pbf_workspace_bytes(c, &need);
+    const size_t N = (size_t)c->oct.n_dofs;
+    const size_t total = need + align256(4 * N) + align256(24 * N) + align256(4 * c->pending.src.size());
+    if (!st && bytes < total) st = fail(c, PBF_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, total);
+    if (st) {  // keep the old mesh and binding
+        c->pending.mesh = std::move(c->oct);
+        c->oct = std::move(old_mesh);
+        return st;
+    }
+    c->pending.ready = false;
+    if ((st = pbf_bind_device(c, workspace, bytes, stream))) {
+        c->bound = false;
+        return st;
+    }
+    char *p = (char *)workspace + need;
+    int32_t *d_cell = (int32_t *)p;
+    p += align256(4 * N);
+    double *d_xi = (double *)p;
+    p += align256(24 * N);
+    int32_t *d_src = (int32_t *)p;
+    PBF_HIP(c, hipMemcpyAsync(d_cell, c->pending.cell.data(), 4 * N, hipMemcpyHostToDevice, s));
+    PBF_HIP(c, hipMemcpyAsync(d_xi, c->pending.xi.data(), 24 * N, hipMemcpyHostToDevice, s));
+    if (!c->pending.src.empty())
+        PBF_HIP(c, hipMemcpyAsync(d_src, c->pending.src.data(), 4 * c->pending.src.size(), hipMemcpyHostToDevice, s));
+    PBF_HIP(c, launch_oct_transfer(c->degree, old, T_old, d_cell, d_xi, (int64_t)N, T_new,
+                                   old_hq > 0 ? rc_old : nullptr, d_src, (int64_t)c->pending.src.size(),
+                                   rc_new, s));
+    PBF_HIP(c, hipStreamSynchronize(s));
+    c->pending.cell.clear();
+    c->pending.xi.clear();
+    c->pending.src.clear();
+    return PBF_OK;
 }
 
 pbf_status pbf_timing_begin(pbf_ctx *c, int max_steps)

@@ -260,5 +260,56 @@ __device__ __forceinline__ bool face_node(long long t, const HaloParams &h, Face
     return true;
 }
 
+// ---- Picard operator helpers (implicit step) ----
+
+template <int P>
+struct Dn {  // nodal basis derivative at the Gauss points: l_a'(x_q) = sum_r D(q,r) S(r,a)
+    static constexpr double v(int q, int a)
+    {
+        double s = 0.0;
+        for (int r = 0; r <= P; ++r) s += Tables<P>::D(q, r) * Tables<P>::S(r, a);
+        return s;
+    }
+};
+template <int P> struct TagS2t  { static constexpr double c(int o, int i) { return Tables<P>::S(i, o) * Tables<P>::S(i, o); } };
+template <int P> struct TagDn2t { static constexpr double c(int o, int i) { return Dn<P>::v(i, o) * Dn<P>::v(i, o); } };
+
+// y = S^T-integration of pointwise data in a compact form: out = M3^T M2^T M1^T in
+template <class MX, class MY, class MZ, int N>
+__device__ __forceinline__ void integrate3(const double *in, double *out)
+{
+    double t1[N * N * N], t2[N * N * N];
+    sweep<MX, N, 0>(in, t1);
+    sweep<MY, N, 1>(t1, t2);
+    sweep<MZ, N, 2>(t2, out);
+}
+
+// conductivity at a Gauss point with the lagged consolidated fraction
+template <typename L>
+__device__ __forceinline__ double law_k(L &law, double T, double r)
+{
+    double kpl = law.k0;
+    for (int i = 0; i < law.n_hinge; ++i) kpl = __builtin_fma(law.dk[i], fmax0(T - law.b[i], 0.0), kpl);
+    return kpl * (r + law.phi * (1.0 - r));
+}
+
+template <typename L>
+__device__ __forceinline__ double law_c(L &law, double T)
+{
+    double c = law.c0;
+    for (int i = 0; i < law.n_hinge; ++i) c = __builtin_fma(law.dc[i], fmax0(T - law.b[i], 0.0), c);
+    if (T >= law.Ts && T <= law.Tl) c += law.lat;
+    return c;
+}
+
+// 1D Lagrange basis of degree P (1 or 2) on the equispaced nodes of [0,1]
+__device__ __forceinline__ double lagrange1(int P, int a, double x)
+{
+    if (P == 1) return a == 0 ? 1.0 - x : x;
+    if (a == 0) return 2.0 * (x - 0.5) * (x - 1.0);
+    if (a == 1) return 4.0 * x * (1.0 - x);
+    return 2.0 * x * (x - 0.5);
+}
+
 }  // namespace
 }  // namespace pbf

@@ -6,7 +6,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "pbftherm.h"
@@ -173,6 +175,7 @@ struct HaloParams {
     long long GX, GY, GZ;  // sizes of the x-, y- and z-face groups
     double hx, hy, hz, dt, T_D;
     unsigned dmask;
+    const unsigned char *dflag;  // per-dof Dirichlet flags (octree meshes), else NULL
 };
 
 // Row sum of the 1D mass matrix at node i of n_nodes (degree P, cell size h):
@@ -248,6 +251,71 @@ hipError_t launch_probe_values(const ProbeSet &ps, const double *T, double *vals
 // J = sum_p (T_h(x_p) - T*_p)^2 into J[0]; lam = dJ/dT (lam zeroed here)
 hipError_t launch_objective(const ProbeSet &ps, const double *T, double *J, double *lam, long long n,
                             hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// octree meshes with hanging nodes (octree_mesh.cpp on the host, octree.hip)
+// ---------------------------------------------------------------------------
+struct OctMesh {
+    int P = 0, maxl = 0, n0[3] = {0, 0, 0};
+    double L[3] = {0, 0, 0}, unit[3] = {0, 0, 0};  // unit: finest cell size
+    std::vector<int32_t> leaf;                      // (level, ix, iy, iz) per leaf
+    int64_t n_cells = 0, n_dofs = 0, n_hanging = 0, n_hist_cells = 0;
+    std::vector<int32_t> cidx;                      // NN x n_cells: dof, or -1 - hanging id
+    std::vector<int32_t> hstart, hdof;              // expanded constraints (CSR)
+    std::vector<double> hw;
+    std::vector<int32_t> nstart, nslot;             // per dof: slots a * n_cells + cell
+    std::vector<double> nw, mass, coords;
+    std::vector<int64_t> dof_key;                   // lattice coordinates (step unit / P)
+    std::vector<unsigned char> dflag;               // Dirichlet flags
+    std::vector<int32_t> cell_hist;                 // history cell of each leaf or -1
+    std::vector<double> hist_z;                     // (z origin, z size) per history cell
+    std::unordered_map<uint64_t, int32_t> leaf_map;
+};
+bool oct_build(OctMesh &m, int P, int maxl, const int n0[3], const double L[3], int64_t n_leaves,
+               const int32_t *leaves, std::string &err);
+void oct_finish(OctMesh &m, unsigned dmask, double powder_depth);
+int32_t oct_locate(const OctMesh &m, const double x_finest[3], double xi[3]);
+
+// device view of an octree mesh
+struct OctDev {
+    const int32_t *cidx, *hstart, *hdof, *leaf, *cell_hist, *nstart, *nslot;
+    const double *hw, *nw, *mass, *hist_z;
+    const unsigned char *dflag;
+    double *E;  // NN x n_cells element vectors
+    int n_cells, n_dofs, n_hist_cells, maxl, top_iz;
+    double ux, uy, uz, Lz;
+};
+// parameters of the octree cell passes
+struct OctParams {
+    OctDev m;
+    const double *Tin;        // explicit / assemble
+    const double *Tc, *Tk, *x1, *x2;  // Picard apply / diagonal
+    double *hist;
+    int has_hist, hist_write;
+    double inv_dt;
+    int laser_on, laser_kind;
+    double xb, yb, src_amp, two_over_R2, h_powder;
+    const Law<double> *law;
+};
+// node pass: mode 0 explicit update, 1 assemble f and C~, 2 Picard apply
+// (Dirichlet rows 0), 3 Picard diagonal (squared weights, Dirichlet rows 1)
+struct OctNodeParams {
+    OctDev m;
+    const double *Tin;
+    double *Tout, *fout, *Cout;
+    double dt, T_D;
+    const Law<double> *nlaw;
+};
+hipError_t launch_oct_cells(int degree, const OctParams &p, hipStream_t s);
+hipError_t launch_oct_picard(int degree, int mode, const OctParams &p, hipStream_t s);
+hipError_t launch_oct_nodes(int mode, const OctNodeParams &p, hipStream_t s);
+hipError_t launch_oct_init_history(const OctDev &m, int degree, double powder_depth, double *rc,
+                                   hipStream_t s);
+// remesh transfer: T_new[i] = old field at (cell[i], xi[3i..]); rc_new[i] =
+// src[i] >= 0 ? rc_old[src[i]] : (src[i] == -1 ? 0 : 1)
+hipError_t launch_oct_transfer(int degree, const OctDev &old, const double *T_old, const int32_t *cell,
+                               const double *xi, int64_t n, double *T_new, const double *rc_old,
+                               const int32_t *src, int64_t n_hist, double *rc_new, hipStream_t s);
 
 // binomial checkpoint schedule (revolve.cpp, host only)
 bool revolve_schedule(int l, int c, std::vector<pbf_revolve_action> &acts, long long *advances);

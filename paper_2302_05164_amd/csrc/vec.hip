@@ -14,6 +14,7 @@ constexpr int kRedThreads = 256;
 
 __device__ __forceinline__ bool node_dirichlet(long long g, const HaloParams &h)
 {
+    if (h.dflag) return h.dflag[g] != 0;  // unstructured (octree) dof numbering
     const long long NXY = (long long)h.NX * h.NY;
     const int i = int(g % h.NX), j = int((g / h.NX) % h.NY), k = int(g / NXY);
     const unsigned m = h.dmask;

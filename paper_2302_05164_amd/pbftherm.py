@@ -88,6 +88,12 @@ SIGNATURES = {
                               _vp, _vp, _i64p, _vp],
     "pbf_energy": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, _dp, _vp],
     "pbf_check_finite": [_vp, _vp, C.c_int64, C.POINTER(C.c_int), _dp, _vp],
+    "pbf_mesh_octree": [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                        C.c_int, C.c_int64, C.POINTER(C.c_int32)],
+    "pbf_octree_info": [_vp, _i64p, _i64p, C.POINTER(C.c_int)],
+    "pbf_octree_remesh_bytes": [_vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_size_t), _i64p, _i64p],
+    "pbf_octree_remesh": [_vp, _vp, C.c_size_t, _vp, _vp, _vp, _vp, _vp],
+    "pbf_dof_coords": [_vp, _dp],
     "pbf_timing_begin": [_vp, C.c_int],
     "pbf_timing_end": [_vp, _dp, _dp, _i64p],
 }
@@ -158,12 +164,20 @@ class Simulation:
     set_dirichlet, set_material, set_laser, bind(); then init_state() and the
     stepping calls.  State tensors (T, rc) belong to the caller."""
 
-    def __init__(self, degree, nx, ny, nz, L, device="cuda:0"):
+    def __init__(self, degree, nx, ny, nz, L, device="cuda:0", max_level=None, leaves=None):
+        """Box mesh of nx*ny*nz cells, or (leaves given) an octree over those coarse
+        cells with leaves (n, 4) = (level, ix, iy, iz)."""
         self.lib = load_library()
         self.device = torch.device(device)
         self.ctx = _vp()
         self._check(self.lib.pbf_create(C.byref(self.ctx)), use_ctx=False)
-        self._check(self.lib.pbf_mesh_box(self.ctx, degree, nx, ny, nz, *map(float, L)))
+        if leaves is None:
+            self._check(self.lib.pbf_mesh_box(self.ctx, degree, nx, ny, nz, *map(float, L)))
+        else:
+            lv = np.ascontiguousarray(leaves, dtype=np.int32).reshape(-1, 4)
+            self._check(self.lib.pbf_mesh_octree(self.ctx, degree, nx, ny, nz, *map(float, L), int(max_level),
+                                                 len(lv), lv.ctypes.data_as(C.POINTER(C.c_int32))))
+        self.octree = leaves is not None
         self.workspace = None
         self.n_tracks = 0
         self.n_probes = 0
@@ -282,6 +296,34 @@ class Simulation:
             self._check(st)
         return T_out, info
 
+    # -- dof map and octree remeshing -----------------------------------------------
+    def dof_coords(self):
+        x = np.zeros((self.info()["n_dofs"], 3))
+        self._check(self.lib.pbf_dof_coords(self.ctx, x.ctypes.data_as(_dp)))
+        return x
+
+    def octree_info(self):
+        nl, nh, ml = C.c_int64(), C.c_int64(), C.c_int()
+        self._check(self.lib.pbf_octree_info(self.ctx, C.byref(nl), C.byref(nh), C.byref(ml)))
+        return {"n_leaves": nl.value, "n_hanging": nh.value, "max_level": ml.value}
+
+    def remesh(self, leaves, T, rc):
+        """Move to new octree leaves; returns the transferred (T, rc).  Binds a new
+        workspace (the old one is released afterwards)."""
+        lv = np.ascontiguousarray(leaves, dtype=np.int32).reshape(-1, 4)
+        nb, nd, nh = C.c_size_t(), C.c_int64(), C.c_int64()
+        self._check(self.lib.pbf_octree_remesh_bytes(self.ctx, len(lv), lv.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                     C.byref(nb), C.byref(nd), C.byref(nh)))
+        buf, addr = _aligned(nb.value, self.device)
+        old_info = self.info()
+        T_new = torch.empty(nd.value, dtype=torch.float64, device=self.device)
+        rc_new = torch.empty(max(1, nh.value), dtype=torch.float64, device=self.device)
+        self._check(self.lib.pbf_octree_remesh(self.ctx, C.c_void_p(addr), nb.value, _ptr(T),
+                                               _ptr(rc) if old_info["n_hist_qp"] else None, _ptr(T_new),
+                                               _ptr(rc_new), self._stream()))
+        self.workspace = buf  # the old workspace is released here
+        return T_new, rc_new
+
     # -- diagnostics ----------------------------------------------------------------
     def energy(self, T_prev, T, rc, t, dt):
         """(stored-heat change, absorbed power, Dirichlet heat flow, identity residual)."""
@@ -381,10 +423,13 @@ class Simulation:
         return a.value, b.value, n.value
 
 
-def from_problem(prob, device="cuda:0"):
+def from_problem(prob, device="cuda:0", leaves=None):
     """Simulation set up from a problem description object with the attributes
-    of pbf_workloads.Problem (argument marshalling only)."""
-    s = Simulation(prob.degree, prob.nx, prob.ny, prob.nz, prob.L, device=device)
+    of pbf_workloads.Problem (argument marshalling only); an octree mesh when the
+    problem (or the `leaves` argument) holds leaves."""
+    lv = leaves if leaves is not None else getattr(prob, "leaves", None)
+    s = Simulation(prob.degree, prob.nx, prob.ny, prob.nz, prob.L, device=device,
+                   max_level=getattr(prob, "max_level", 0), leaves=lv)
     s.set_dirichlet(prob.dirichlet_mask, prob.T_D)
     s.set_material(prob.T_bp, prob.k_bp, prob.cp_bp, prob.rho, prob.T_s, prob.T_l, prob.latent,
                    prob.powder_k_factor, prob.powder_depth)

@@ -1,0 +1,229 @@
+"""GPU parity of the octree path (hanging-node constraints) against the octree
+oracle: assembled vectors, explicit steps with the nonlinear law and history,
+the implicit step, the stability estimate and the remesh transfer; plus
+properties at the size of the octree configuration.
+
+The library numbers dofs in order of first appearance, the oracle by
+coordinates; tests map one onto the other by the dof coordinates.  Both sides
+run the same FP64 arithmetic in different summation orders, so results agree
+to ~1e-15 relative; the tolerance is 1e-12 (1e-10 for implicit steps)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pbf_workloads as W
+from tests.gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(p):
+    from paper_2302_05164_amd import pbftherm
+    sim = pbftherm.from_problem(p, device="cuda:0")
+    O = oracle.OctOracle(p)
+    xl = sim.dof_coords()
+    h = p.L[0] / p.nx / 2 ** p.max_level / p.degree
+    kl = {tuple(k): i for i, k in enumerate(np.round(xl / h).astype(np.int64))}
+    ko = np.round(O.dof_coords() / h).astype(np.int64)
+    to_lib = np.empty(O.N, dtype=np.int64)  # T_lib[to_lib[j]] = T_or[j]
+    for j, k in enumerate(ko):
+        to_lib[j] = kl[tuple(k)]
+    return sim, O, to_lib
+
+
+def _lib(v, to_lib):
+    out = np.empty_like(v)
+    out[to_lib] = v
+    return out
+
+
+def _hist_map(p, O):
+    """(oracle index, library index) of the stored history points: leaves with a
+    Gauss point within the powder depth, point-major in leaf order."""
+    xg, _ = oracle.gauss_legendre(p.degree + 1)
+    nq = (p.degree + 1) ** 3
+    unit_z = p.L[2] / p.nz / 2 ** p.max_level
+    hist = []
+    for e, (l, ix, iy, iz) in enumerate(p.leaves):
+        s = 2 ** (p.max_level - l)
+        z = iz * unit_z + xg * (s * unit_z)
+        if np.any(p.L[2] - z <= p.powder_depth):
+            hist.append(e)
+    nhc = len(hist)
+    o_idx, l_idx = [], []
+    for hc, e in enumerate(hist):
+        for q in range(nq):
+            o_idx.append(e * nq + q)
+            l_idx.append(q * nhc + hc)
+    return np.array(o_idx), np.array(l_idx), nhc * nq
+
+
+def _close(a, b, tol, what):
+    err = np.abs(a - b).max() / np.abs(b).max()
+    print(f"CHECK {what}: {err:.2e} (tol {tol:.0e})")
+    assert err <= tol, what
+
+
+def _hist_close(a, b, what):
+    err = np.abs(a - b).max() if len(b) else 0.0
+    print(f"CHECK {what}: max |diff| {err:.2e}")
+    assert err <= 1e-12, what
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_assemble_vs_oracle(deg):
+    need_gpu()
+    p = W.small_octree(degree=deg)
+    sim, O, to_lib = _setup(p)
+    T = O.init_T() + 800.0 * (1.0 + W.seeded_vector(O.N, 6))
+    ro = O.init_history()
+    f, Cl, fv = O.assemble(T, ro, 2e-5)
+    Tl, rl = sim.init_state(p.T0)
+    Tl.copy_(torch.tensor(_lib(T, to_lib)))
+    fg, Cg = sim.assemble(Tl, rl, 2e-5)
+    torch.cuda.synchronize()
+    _close(fg.cpu().numpy()[to_lib], f, 1e-12, "f")
+    _close(Cg.cpu().numpy()[to_lib], Cl, 1e-13, "C")
+    oi, li, nh = _hist_map(p, O)
+    _hist_close(rl.cpu().numpy()[:nh][li], ro[oi], "history")
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_explicit_steps_vs_oracle(deg):
+    need_gpu()
+    p = W.small_octree(degree=deg)
+    sim, O, to_lib = _setup(p)
+    lam = O.stability_lambda(W.seeded_vector(O.N, 1), 60)
+    v0 = torch.tensor(_lib(W.seeded_vector(O.N, 1), to_lib), device="cuda")
+    lam_g = sim.stability_lambda(v0, 60)
+    print(f"CHECK lambda gpu {lam_g:.15e} oracle {lam:.15e}")
+    assert abs(lam_g - lam) <= 1e-10 * lam
+    dt = 0.5 * 2.0 / lam
+    n = 80 if deg == 2 else 12  # the beam still on the short scan at the end
+    T = O.init_T()
+    ro = O.init_history()
+    O.explicit_steps(T, ro, 0.0, dt, n)
+    assert T.max() > p.T_l  # melt pool, consolidation
+    Tl, rl = sim.init_state(p.T0)
+    sim.explicit_steps(Tl, rl, 0.0, dt, n)
+    torch.cuda.synchronize()
+    _close(Tl.cpu().numpy()[to_lib], T, 1e-12, "T")
+    oi, li, nh = _hist_map(p, O)
+    _hist_close(rl.cpu().numpy()[:nh][li], ro[oi], "history")
+    e = sim.energy(torch.tensor(_lib(T, to_lib), device="cuda"), Tl, rl, n * dt, dt)
+    assert np.isfinite(e).all()
+
+
+def test_implicit_step_vs_oracle():
+    need_gpu()
+    p = W.small_octree(degree=2)
+    sim, O, to_lib = _setup(p)
+    dt_ex = 0.5 * 2.0 / O.stability_lambda(W.seeded_vector(O.N, 1), 60)
+    T = O.init_T()
+    ro = O.init_history()
+    O.explicit_steps(T, ro, 0.0, dt_ex, 60)
+    cool = p.replace(laser_kind=W.LASER_OFF)
+    sim_c, Oc, _ = _setup(cool)
+    To, info_o = Oc.implicit_step(T, ro.copy(), 60 * dt_ex, 1e-4, cg_rtol=1e-13, picard_tol=1e-10, picard_max_it=60)
+    assert info_o["status"] == 0
+    oi, li, nh = _hist_map(p, O)
+    rl = np.ones(max(1, nh))
+    rl[li] = ro[oi]
+    Tg, info_g = sim_c.implicit_step(torch.tensor(_lib(T, to_lib), device="cuda"), torch.tensor(rl, device="cuda"),
+                                     60 * dt_ex, 1e-4, cg_rtol=1e-13, picard_tol=1e-10, picard_max_it=60)
+    torch.cuda.synchronize()
+    print("gpu", info_g, "oracle", info_o)
+    _close(Tg.cpu().numpy()[to_lib], To, 1e-10, "T implicit")
+    assert abs(info_g["cg_iters"] - info_o["cg_iters"]) <= max(2, 0.02 * info_o["cg_iters"])
+
+
+def test_remesh_transfer_vs_oracle():
+    need_gpu()
+    p = W.small_octree(degree=2, ahead=30e-6)
+    sim, O, to_lib = _setup(p)
+    dt = 0.5 * 2.0 / O.stability_lambda(W.seeded_vector(O.N, 1), 60)
+    T = O.init_T()
+    ro = O.init_history()
+    O.explicit_steps(T, ro, 0.0, dt, 60)
+    Tl, rl = sim.init_state(p.T0)
+    sim.explicit_steps(Tl, rl, 0.0, dt, 60)
+    new_leaves = W.octree_leaves(p, 120e-6)
+    pn = p.replace(leaves=new_leaves)
+    On = oracle.OctOracle(pn)
+    Tn_o, rn_o = O.transfer(T, ro, On)
+    Tn_g, rn_g = sim.remesh(new_leaves, Tl, rl)
+    torch.cuda.synchronize()
+    xl = sim.dof_coords()
+    h = p.L[0] / p.nx / 2 ** p.max_level / p.degree
+    kl = {tuple(k): i for i, k in enumerate(np.round(xl / h).astype(np.int64))}
+    to_lib_n = np.array([kl[tuple(k)] for k in np.round(On.dof_coords() / h).astype(np.int64)])
+    _close(Tn_g.cpu().numpy()[to_lib_n], Tn_o, 1e-12, "T transferred")
+    oi, li, nh = _hist_map(pn, On)
+    _hist_close(rn_g.cpu().numpy()[:nh][li], rn_o[oi], "history transferred")
+    # the new mesh keeps stepping like the oracle
+    On.explicit_steps(Tn_o, rn_o, 60 * dt, dt, 20)
+    sim.explicit_steps(Tn_g, rn_g, 60 * dt, dt, 20)
+    torch.cuda.synchronize()
+    _close(Tn_g.cpu().numpy()[to_lib_n], Tn_o, 1e-12, "T after remesh")
+
+
+def test_uniform_octree_matches_box_kernels():
+    """All leaves on one level: the octree kernels against the box kernels."""
+    need_gpu()
+    from paper_2302_05164_amd import pbftherm
+    p = W.small_nonlinear(nx=8, ny=6, nz=4, steps=0, n_tracks=2, track_length=0.1e-3, hatch=60e-6)
+    g = np.stack(np.meshgrid(np.arange(8), np.arange(6), np.arange(4), indexing="ij"), -1).reshape(-1, 3)
+    leaves = np.concatenate([np.ones((len(g), 1), dtype=np.int64), g], 1)
+    po = p.replace(nx=4, ny=3, nz=2, max_level=1, leaves=leaves)
+    box = pbftherm.from_problem(p)
+    octs = pbftherm.from_problem(po)
+    xb, xo = box.dof_coords(), octs.dof_coords()
+    h = p.L[0] / p.nx / p.degree
+    kb = {tuple(k): i for i, k in enumerate(np.round(xb / h).astype(np.int64))}
+    perm = np.array([kb[tuple(k)] for k in np.round(xo / h).astype(np.int64)])  # oct dof -> box dof
+    dt = 2e-6
+    Tb, rb = box.init_state(p.T0)
+    box.explicit_steps(Tb, rb, 0.0, dt, 50)
+    To, ro = octs.init_state(p.T0)
+    octs.explicit_steps(To, ro, 0.0, dt, 50)
+    torch.cuda.synchronize()
+    _close(To.cpu().numpy(), Tb.cpu().numpy()[perm], 1e-13, "octree vs box kernels")
+
+
+def test_octree_configuration_properties():
+    """The octree configuration (10x10x5 mm, level 6 around the path): a linear
+    field is a steady state inside for a constant law (all constraints
+    exercised), the per-step energy identity holds, and a remesh keeps the
+    state finite."""
+    need_gpu()
+    from paper_2302_05164_amd import pbftherm
+    p = W.cfg3()
+    lin = p.replace(T_bp=np.array([0.0, 1e4]), k_bp=np.array([25.0, 25.0]), cp_bp=np.array([600.0, 600.0]),
+                    latent=0.0, powder_k_factor=1.0, powder_depth=0.0, laser_kind=W.LASER_OFF)
+    sim = pbftherm.from_problem(lin)
+    info = sim.octree_info()
+    assert info["n_hanging"] > 0
+    x = sim.dof_coords()
+    T = torch.tensor(300.0 + 1e3 * (x[:, 0] - 2.0 * x[:, 1] + 0.5 * x[:, 2]), device="cuda")
+    Tl, rl = sim.init_state(300.0)
+    f, _ = sim.assemble(T, rl, 0.0)
+    torch.cuda.synchronize()
+    inner = np.all((x > 1e-12) & (x < np.array(p.L) - 1e-12), axis=1)
+    fa = np.abs(f.cpu().numpy())
+    print(f"dofs {len(x)}, hanging {info['n_hanging']}, max |f| inside {fa[inner].max():.2e}, on faces {fa.max():.2e}")
+    assert fa[inner].max() <= 1e-11 * fa.max()
+    sim = pbftherm.from_problem(p)
+    v0 = torch.tensor(W.seeded_vector(sim.info()["n_dofs"], 1), device="cuda")
+    dt = 0.5 * 2.0 / sim.stability_lambda(v0, 50)
+    T, rc = sim.init_state(p.T0)
+    Tp = T.clone()
+    sim.explicit_steps(T, rc, 0.0, dt, 1)
+    e = sim.energy(Tp, T, rc, 0.0, dt)
+    assert e[1] > 0 and abs(e[3]) <= 1e-10 * dt * (abs(e[1]) + abs(e[2]))
+    sim.explicit_steps(T, rc, dt, dt, 99)
+    s_now = W.beam_arc_length(p, 100 * dt)
+    T2, rc2 = sim.remesh(W.octree_leaves(p, s_now + p.refine_ahead), T, rc)
+    sim.explicit_steps(T2, rc2, 100 * dt, dt, 20)
+    ok, mx = sim.check_finite(T2)
+    assert ok and p.T0 <= mx < 5000.0
