@@ -254,13 +254,14 @@ pbf_status pbf_check_finite(pbf_ctx *ctx, const double *x, int64_t n, int *ok, d
  * into lam (n_dofs, must not overlap lam_next), replaces mu (n_hist_qp) by
  * mu_{n-1}, and adds the sensitivity of J to the effective power W_eff of the
  * track active at t_n to dJdW[track] (device array of n_tracks).  T_n and
- * rc_prev = r^{n-1} are the step's input state (read only).  Derivative
+ * rc_prev = r^{n-1} are the step's input state, T_next = T_{n+1} its output
+ * (all read only; the capacity term uses dt f/C~ = T_{n+1} - T_n).  Derivative
  * conventions at non-smooth points: the slope of the table segment that the
  * forward evaluation used (zero outside the table), g' = 1/(T_l - T_s) on the
  * open melting interval, no derivative of the latent-heat box, and the max
  * passes the adjoint to T where g(T) > r^{n-1} (to r^{n-1} otherwise, ties
- * included).  FP64.  Uses the workspace f/C scratch.  Asynchronous. */
-pbf_status pbf_adjoint_step(pbf_ctx *ctx, const double *T_n, const double *rc_prev,
+ * included).  FP64.  Asynchronous. */
+pbf_status pbf_adjoint_step(pbf_ctx *ctx, const double *T_n, const double *T_next, const double *rc_prev,
                             const double *lam_next, double *lam, double *mu, double t_n, double dt,
                             double *dJdW, void *stream);
 

@@ -8,6 +8,8 @@
 // is, with a = dt lambda_{n+1} / C~ (0 at Dirichlet nodes):
 //   lambda_n = lambda_{n+1} - a f c'(T)/c(T)          (identity and nodal capacity,
 //                                                      free nodes only)
+// where a f = lambda_{n+1} (T_{n+1} - T_n) at free nodes, so the forward vector f
+// need not be re-assembled: the step's own output gives it.
 //            + sum_e G_e^T [ -sum_q W k grad N . grad a_h            (symmetric part)
 //                            + sum_q N Tbar_q ],                     (law part)
 //   Tbar_q = k_T kbar_q + [g > r^{n-1}] g' rbar_q,  kbar_q = -W grad a_h . grad T_h,
@@ -83,11 +85,12 @@ k_adjoint(const AdjointParams p)
             const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
             const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
             double Tv = 0.0, av = 0.0;
-            if (gi < q.NX && gj < q.NY) {
-                const long long g = (long long)gi + (long long)q.NX * gj + NXY * gk;
-                Tv = q.T[g];
-                if (!on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ)) av = q.dt * q.lam[g] / q.C[g];
-            }
+            const bool in = gi < q.NX && gj < q.NY;
+            const long long g = (long long)gi + (long long)q.NX * gj + NXY * gk;
+            if (in) Tv = q.T[g];
+            // C~ as in the forward step (nodal capacity, same hinge truncation)
+            const double C = node_capacity(law, Tv, gi, gj, gk, P, q.NX, q.NY, q.NZ, q.hx, q.hy, q.hz);
+            if (in && !on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ)) av = q.dt * q.lam[g] / C;
             sT[0][idx] = Tv;
             sT[1][idx] = av;
         }
@@ -218,8 +221,10 @@ k_adjoint(const AdjointParams p)
                                 [&](long long g, int gi, int gj, int gk, int ax, int ay, int az, double fs) {
                 const int li = (az * BY + P * ly + ay) * BX + P * lx + ax;
                 double base = 0.0;
-                if (!on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ))
-                    base = q.lam[g] - sT[1][li] * q.f[g] * capacity_log_slope(law, sT[0][li]);
+                if (!on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ)) {
+                    const double lam = q.lam[g], Tn = sT[0][li];
+                    base = lam - lam * (q.Tn1[g] - Tn) * capacity_log_slope(law, Tn);
+                }
                 q.lam_out[g] = base + fs;
             });
         }
@@ -230,9 +235,9 @@ k_adjoint(const AdjointParams p)
     if (threadIdx.x == 0) p.partials[id] = src_acc;
 }
 
-__global__ void __launch_bounds__(256) k_adjoint_halo(const HaloParams h, const double *lam,
-                                                      const double *C, const double *f, double *lam_out)
+__global__ void __launch_bounds__(256) k_adjoint_halo(const AdjointHalo ah)
 {
+    const HaloParams &h = ah.h;
     FaceNode fn;
     if (!face_node((long long)blockIdx.x * blockDim.x + threadIdx.x, h, fn)) return;
     const long long NT = (long long)h.NX * h.NY * h.NZ;
@@ -241,10 +246,10 @@ __global__ void __launch_bounds__(256) k_adjoint_halo(const HaloParams h, const 
     for (int a = 0; a < fn.n; ++a) fs += h.slots[fn.par[a] * NT + g];
     double base = 0.0;
     if (!on_dirichlet(h.dmask, fn.gi, fn.gj, fn.gk, h.NX, h.NY, h.NZ)) {
-        const double a = h.dt * lam[g] / C[g];
-        base = lam[g] - a * f[g] * capacity_log_slope(const_law(h.nlaw), h.Tin[g]);
+        const double lam = ah.lam[g], Tn = h.Tin[g];
+        base = lam - lam * (ah.Tn1[g] - Tn) * capacity_log_slope(const_law(h.nlaw), Tn);
     }
-    lam_out[g] = base + fs;
+    ah.lam_out[g] = base + fs;
 }
 
 __device__ __forceinline__ double block_sum_256(double v, double *s)
@@ -339,17 +344,16 @@ __global__ void __launch_bounds__(256) k_objective(const ProbeSet ps, const doub
 int adjoint_column_height() { return kATY; }
 int adjoint_resident_columns_per_cu() { return 8; }
 
-hipError_t launch_adjoint(int degree, const AdjointParams &ap, const HaloParams &hp, hipStream_t s)
+hipError_t launch_adjoint(int degree, const AdjointParams &ap, const AdjointHalo &ah, hipStream_t s)
 {
     const dim3 grid(8 * ap.tiles_per_xcd), block(kTX * kATY);
     if (degree == 1) hipLaunchKernelGGL(k_adjoint<1>, grid, block, 0, s, ap);
     else hipLaunchKernelGGL(k_adjoint<2>, grid, block, 0, s, ap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const long long n = hp.GX + hp.GY + hp.GZ;
+    const long long n = ah.h.GX + ah.h.GY + ah.h.GZ;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adjoint_halo, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, hp, ap.lam,
-                       ap.C, ap.f, ap.lam_out);
+    hipLaunchKernelGGL(k_adjoint_halo, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ah);
     return hipGetLastError();
 }
 

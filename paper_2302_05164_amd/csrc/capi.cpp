@@ -71,7 +71,8 @@ struct pbf_ctx {
         const void *work = nullptr;
         int n_steps = 0, n_snaps = 0;
         double t0 = 0, dt = 0;
-        long long forward_advances = 0;
+        const double *cur = nullptr;  // executor state after the forward sweep
+        double *next = nullptr;
         bool valid = false;
     } grad;
     Law<double> h_law64{}, h_lin64{}, h_zero64{};
@@ -624,14 +625,14 @@ pbf_status upload_probes(pbf_ctx *c, hipStream_t s)
     return PBF_OK;
 }
 
-AdjointParams adjoint_params(const pbf_ctx *c, const HaloParams &h, const double *T, const double *rc,
-                             const double *lam_next, double *lam, double *mu, double dt, const Beam &bm)
+AdjointParams adjoint_params(const pbf_ctx *c, const HaloParams &h, const double *T, const double *Tn1,
+                             const double *rc, const double *lam_next, double *lam, double *mu, double dt,
+                             const Beam &bm)
 {
     AdjointParams a{};
     a.T = T;
+    a.Tn1 = Tn1;
     a.lam = lam_next;
-    a.C = c->d_C;
-    a.f = c->d_f;
     a.lam_out = lam;
     a.hist = rc;
     a.mu = mu;
@@ -677,27 +678,28 @@ AdjointParams adjoint_params(const pbf_ctx *c, const HaloParams &h, const double
     return a;
 }
 
-// one reverse step at state (T, rc = r^{n-1}), time t
-pbf_status adjoint_step(pbf_ctx *c, const double *T, const double *rc, const double *lam_next, double *lam,
-                        double *mu, double t, double dt, double *dJdW, hipStream_t s)
+// one reverse step at state (T = T_n, rc = r^{n-1}), time t, with Tn1 = T_{n+1}
+pbf_status adjoint_step(pbf_ctx *c, const double *T, const double *Tn1, const double *rc, const double *lam_next,
+                        double *lam, double *mu, double t, double dt, double *dJdW, hipStream_t s)
 {
-    // f and C~ of the forward step, history read but not written
-    pbf_status st = operator_pass(c, 1, PBF_PREC_FP64, LAW_FULL, T, nullptr, c->d_f, c->d_C,
-                                  const_cast<double *>(rc), t, 0.0, s, false);
-    if (st) return st;
     const Beam bm = beam_at(c, t);
-    HaloParams h = adjoint_geometry(c);
-    h.Tin = T;
-    h.dt = dt;
-    const AdjointParams ap = adjoint_params(c, h, T, rc, lam_next, lam, mu, dt, bm);
-    PBF_HIP(c, launch_adjoint(c->degree, ap, h, s));
+    AdjointHalo ah{};
+    ah.h = adjoint_geometry(c);
+    ah.h.Tin = T;
+    ah.h.dt = dt;
+    ah.Tn1 = Tn1;
+    ah.lam = lam_next;
+    ah.lam_out = lam;
+    const AdjointParams ap = adjoint_params(c, ah.h, T, Tn1, rc, lam_next, lam, mu, dt, bm);
+    PBF_HIP(c, launch_adjoint(c->degree, ap, ah, s));
     if (bm.on) PBF_HIP(c, launch_adjoint_finish(c->d_tiles, ap.ntiles, dJdW, bm.track, s));
     return PBF_OK;
 }
 
-// device buffer of the checkpointed gradient
+// device buffer of the checkpointed gradient: snapshots, three rotating
+// temperature buffers, history, adjoint vectors, parameter gradients
 struct GradWork {
-    double *snapT, *snapR, *Tcur, *Ttmp, *rcur, *rtmp, *lam, *lam2, *mu, *dJdW, *powers, *J;
+    double *snapT, *snapR, *B[3], *rcur, *rtmp, *lam, *lam2, *mu, *dJdW, *powers, *J;
     size_t bytes;
 };
 
@@ -714,8 +716,7 @@ GradWork grad_layout(const pbf_ctx *c, int n_snaps, char *base)
     };
     w.snapT = take((size_t)n_snaps * N);
     w.snapR = take((size_t)n_snaps * H);
-    w.Tcur = take(N);
-    w.Ttmp = take(N);
+    for (int k = 0; k < 3; ++k) w.B[k] = take(N);
     w.rcur = take(H);
     w.rtmp = take(H);
     w.lam = take(N);
@@ -728,41 +729,70 @@ GradWork grad_layout(const pbf_ctx *c, int n_snaps, char *base)
     return w;
 }
 
-// execute schedule actions [i0, i1) from state `cur`; TURN actions run adjoint steps
+// Executor state: the temperature of the current state (a work buffer or a
+// snapshot, read only) and T_{n+1} of the next reverse step (a work buffer).
+// Advances ping-pong between the buffers that hold neither; an advance that
+// ends in a snapshot writes its last step there; a restore only points at the
+// snapshot (the history, updated in place by steps, is copied).
+struct GradState {
+    const double *cur = nullptr;
+    double *next = nullptr;
+    int step = 0;
+};
+
+double *free_buffer(const GradWork &w, const GradState &g)
+{
+    for (double *b : w.B)
+        if (b != g.cur && b != g.next) return b;
+    return nullptr;
+}
+
+// execute schedule actions [i0, i1); TURN actions run adjoint steps
 pbf_status run_actions(pbf_ctx *c, const std::vector<pbf_revolve_action> &acts, size_t i0, size_t i1,
-                       const GradWork &w, int &cur, double *&lam, double *&lam2, double t0, double dt,
+                       const GradWork &w, GradState &g, double *&lam, double *&lam2, double t0, double dt,
                        hipStream_t s)
 {
     const size_t N = (size_t)n_dofs(c), H = (size_t)n_hist_qp(c);
+    auto slotT = [&](int k) { return w.snapT + (size_t)k * N; };
     for (size_t i = i0; i < i1; ++i) {
         const pbf_revolve_action &a = acts[i];
         if (a.kind == PBF_ACT_ADVANCE) {
-            double *x = w.Tcur, *y = w.Ttmp;
-            for (int n = cur; n < a.step; ++n) {
-                pbf_status st = operator_pass(c, 0, PBF_PREC_FP64, LAW_FULL, x, y, nullptr, nullptr,
+            const bool into_slot = i + 1 < i1 && acts[i + 1].kind == PBF_ACT_STORE && acts[i + 1].step == a.step;
+            for (int n = g.step; n < a.step; ++n) {
+                double *dst = (n == a.step - 1 && into_slot) ? slotT(acts[i + 1].slot) : free_buffer(w, g);
+                pbf_status st = operator_pass(c, 0, PBF_PREC_FP64, LAW_FULL, g.cur, dst, nullptr, nullptr,
                                               H ? w.rcur : nullptr, t0 + n * dt, dt, s);
                 if (st) return st;
-                std::swap(x, y);
+                g.cur = dst;
             }
-            if (x != w.Tcur) PBF_HIP(c, hipMemcpyAsync(w.Tcur, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-            cur = a.step;
+            g.step = a.step;
         } else if (a.kind == PBF_ACT_STORE) {
-            PBF_HIP(c, hipMemcpyAsync(w.snapT + (size_t)a.slot * N, w.Tcur, N * sizeof(double),
-                                      hipMemcpyDeviceToDevice, s));
+            if (g.step != a.step) return fail(c, PBF_ESTATE, "checkpoint schedule out of step");
+            if (g.cur != slotT(a.slot))
+                PBF_HIP(c, hipMemcpyAsync(slotT(a.slot), g.cur, N * sizeof(double), hipMemcpyDeviceToDevice, s));
             if (H) PBF_HIP(c, hipMemcpyAsync(w.snapR + (size_t)a.slot * H, w.rcur, H * sizeof(double),
                                              hipMemcpyDeviceToDevice, s));
         } else if (a.kind == PBF_ACT_RESTORE) {
-            PBF_HIP(c, hipMemcpyAsync(w.Tcur, w.snapT + (size_t)a.slot * N, N * sizeof(double),
-                                      hipMemcpyDeviceToDevice, s));
+            g.cur = slotT(a.slot);
             if (H) PBF_HIP(c, hipMemcpyAsync(w.rcur, w.snapR + (size_t)a.slot * H, H * sizeof(double),
                                              hipMemcpyDeviceToDevice, s));
-            cur = a.step;
+            g.step = a.step;
         } else if (a.kind == PBF_ACT_TURN) {
-            if (cur != a.step) return fail(c, PBF_ESTATE, "checkpoint schedule out of step (%d vs %d)", cur, a.step);
-            pbf_status st = adjoint_step(c, w.Tcur, H ? w.rcur : nullptr, lam, lam2, H ? w.mu : nullptr,
+            if (g.step != a.step || !g.next)
+                return fail(c, PBF_ESTATE, "checkpoint schedule out of step (%d vs %d)", g.step, a.step);
+            pbf_status st = adjoint_step(c, g.cur, g.next, H ? w.rcur : nullptr, lam, lam2, H ? w.mu : nullptr,
                                          t0 + a.step * dt, dt, w.dJdW, s);
             if (st) return st;
             std::swap(lam, lam2);
+            // T_n is T_{n+1} of the next reverse step; keep it in a work buffer
+            double *keep = nullptr;
+            for (double *b : w.B)
+                if (b == g.cur) keep = b;
+            if (!keep) {
+                keep = g.next;  // T_{n+1} is no longer needed
+                PBF_HIP(c, hipMemcpyAsync(keep, g.cur, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            g.next = keep;
         }
     }
     return PBF_OK;
@@ -1367,14 +1397,15 @@ pbf_status pbf_objective(pbf_ctx *c, const double *T, double *J, double *lam, vo
     return PBF_OK;
 }
 
-pbf_status pbf_adjoint_step(pbf_ctx *c, const double *T_n, const double *rc_prev, const double *lam_next,
-                            double *lam, double *mu, double t_n, double dt, double *dJdW, void *stream)
+pbf_status pbf_adjoint_step(pbf_ctx *c, const double *T_n, const double *T_next, const double *rc_prev,
+                            const double *lam_next, double *lam, double *mu, double t_n, double dt, double *dJdW,
+                            void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
     if (c->octree) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "probes and the adjoint need a box mesh");
     pbf_status st = check_bound(c);
     if (st) return st;
-    if (!T_n || !lam_next || !lam) return fail(c, PBF_EINVAL, "NULL device array");
+    if (!T_n || !T_next || !lam_next || !lam) return fail(c, PBF_EINVAL, "NULL device array");
     if (lam == lam_next) return fail(c, PBF_EINVAL, "lam and lam_next must be distinct arrays");
     if (n_hist_qp(c) > 0 && (!rc_prev || !mu))
         return fail(c, PBF_EINVAL, "rc_prev and mu are required when the mesh has history");
@@ -1382,7 +1413,7 @@ pbf_status pbf_adjoint_step(pbf_ctx *c, const double *T_n, const double *rc_prev
     if (!(dt > 0) || !std::isfinite(t_n)) return fail(c, PBF_EINVAL, "need dt > 0 and finite t_n");
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_laws(c, s))) return st;
-    return adjoint_step(c, T_n, n_hist_qp(c) > 0 ? rc_prev : nullptr, lam_next, lam,
+    return adjoint_step(c, T_n, T_next, n_hist_qp(c) > 0 ? rc_prev : nullptr, lam_next, lam,
                         n_hist_qp(c) > 0 ? mu : nullptr, t_n, dt, dJdW, s);
 }
 
@@ -1448,32 +1479,33 @@ pbf_status pbf_gradient_forward(pbf_ctx *c, const double *T0, const double *rc0,
     while (first_turn < acts.size() && acts[first_turn].kind != PBF_ACT_TURN) ++first_turn;
     const GradWork w = grad_layout(c, n_snaps, (char *)work);
     const size_t N = (size_t)n_dofs(c), H = (size_t)n_hist_qp(c);
-    PBF_HIP(c, hipMemcpyAsync(w.Tcur, T0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PBF_HIP(c, hipMemcpyAsync(w.B[0], T0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (H) PBF_HIP(c, hipMemcpyAsync(w.rcur, rc0, H * sizeof(double), hipMemcpyDeviceToDevice, s));
     std::vector<double> P(std::max<size_t>(c->tracks.size(), 1), 0.0);
     for (size_t k = 0; k < c->tracks.size(); ++k) P[k] = c->tracks[k].power;
     PBF_HIP(c, hipMemcpyAsync(w.powers, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, s));
     PBF_HIP(c, hipStreamSynchronize(s));
-    int cur = 0;
+    GradState g;
+    g.cur = w.B[0];
     double *lam = w.lam, *lam2 = w.lam2;
-    long long fwd = 0;
-    for (size_t i = 0; i < first_turn; ++i)
-        if (acts[i].kind == PBF_ACT_ADVANCE) fwd = acts[i].step;  // forward sweep: 0 -> step
-    if ((st = run_actions(c, acts, 0, first_turn, w, cur, lam, lam2, t0, dt, s))) return st;
-    // last step (l-1 -> l) on copies, then the objective at T_N
+    if ((st = run_actions(c, acts, 0, first_turn, w, g, lam, lam2, t0, dt, s))) return st;
+    // last step (l-1 -> l) on a copy of the history; T_N is T_{n+1} of the first reverse step
     if (H) PBF_HIP(c, hipMemcpyAsync(w.rtmp, w.rcur, H * sizeof(double), hipMemcpyDeviceToDevice, s));
-    st = operator_pass(c, 0, PBF_PREC_FP64, LAW_FULL, w.Tcur, w.Ttmp, nullptr, nullptr, H ? w.rtmp : nullptr,
+    double *TN = free_buffer(w, g);
+    st = operator_pass(c, 0, PBF_PREC_FP64, LAW_FULL, g.cur, TN, nullptr, nullptr, H ? w.rtmp : nullptr,
                        t0 + (n_steps - 1) * dt, dt, s);
     if (st) return st;
-    PBF_HIP(c, launch_objective(probe_set(c), w.Ttmp, w.J, w.lam, (long long)N, s));
-    if (T_N) PBF_HIP(c, hipMemcpyAsync(T_N, w.Ttmp, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    g.next = TN;
+    PBF_HIP(c, launch_objective(probe_set(c), TN, w.J, w.lam, (long long)N, s));
+    if (T_N) PBF_HIP(c, hipMemcpyAsync(T_N, TN, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (J) PBF_HIP(c, hipMemcpyAsync(J, w.J, sizeof(double), hipMemcpyDeviceToDevice, s));
     c->grad.work = work;
     c->grad.n_steps = n_steps;
     c->grad.n_snaps = n_snaps;
     c->grad.t0 = t0;
     c->grad.dt = dt;
-    c->grad.forward_advances = fwd;
+    c->grad.cur = g.cur;
+    c->grad.next = g.next;
     c->grad.valid = true;
     return PBF_OK;
 }
@@ -1500,9 +1532,12 @@ pbf_status pbf_gradient_backward(pbf_ctx *c, double t0, double dt, int n_steps, 
     const size_t N = (size_t)n_dofs(c), H = (size_t)n_hist_qp(c), K = c->tracks.size();
     if (H) PBF_HIP(c, launch_fill(w.mu, 0.0, (long long)H, s));
     PBF_HIP(c, launch_fill(w.dJdW, 0.0, (long long)std::max<size_t>(K, 1), s));
-    int cur = n_steps - 1;
+    GradState g;
+    g.cur = c->grad.cur;
+    g.next = c->grad.next;
+    g.step = n_steps - 1;
     double *lam = w.lam, *lam2 = w.lam2;
-    if ((st = run_actions(c, acts, first_turn, acts.size(), w, cur, lam, lam2, t0, dt, s))) return st;
+    if ((st = run_actions(c, acts, first_turn, acts.size(), w, g, lam, lam2, t0, dt, s))) return st;
     if (K > 0) {
         if (dJdP || dJdA) PBF_HIP(c, launch_adjoint_params(w.dJdW, w.powers, c->absorptivity, (int)K, dJdP, dJdA, s));
         if (dJdW) PBF_HIP(c, hipMemcpyAsync(dJdW, w.dJdW, K * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -137,9 +137,8 @@ struct PicardParams {
 // Parameters of the adjoint cell kernel (reverse of one explicit step).
 struct AdjointParams {
     const double *T;     // T_n
+    const double *Tn1;   // T_{n+1}
     const double *lam;   // lambda_{n+1}
-    const double *C;     // lumped capacity C~(T_n)
-    const double *f;     // f(T_n, r^n)
     double *lam_out;     // lambda_n
     const double *hist;  // r^{n-1} (read only)
     double *mu;          // history adjoint: mu_n in, mu_{n-1} out
@@ -176,6 +175,13 @@ struct HaloParams {
     double hx, hy, hz, dt, T_D;
     unsigned dmask;
     const unsigned char *dflag;  // per-dof Dirichlet flags (octree meshes), else NULL
+};
+
+// tile-face completion of the adjoint kernel
+struct AdjointHalo {
+    HaloParams h;  // h.Tin = T_n
+    const double *Tn1, *lam;
+    double *lam_out;
 };
 
 // Row sum of the 1D mass matrix at node i of n_nodes (degree P, cell size h):
@@ -240,7 +246,7 @@ hipError_t launch_sub(double *d, const double *a, const double *b, long long n, 
 // discrete adjoint (adjoint.hip)
 int adjoint_column_height();
 int adjoint_resident_columns_per_cu();
-hipError_t launch_adjoint(int degree, const AdjointParams &ap, const HaloParams &hp, hipStream_t s);
+hipError_t launch_adjoint(int degree, const AdjointParams &ap, const AdjointHalo &hp, hipStream_t s);
 // dJdW[track] += sum of the per-tile partials (one workgroup, fixed order)
 hipError_t launch_adjoint_finish(const double *partials, int ntiles, double *dJdW, int track,
                                  hipStream_t s);

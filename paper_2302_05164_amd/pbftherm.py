@@ -79,7 +79,7 @@ SIGNATURES = {
     "pbf_set_probes": [_vp, C.c_int, _dp, _dp, _vp],
     "pbf_probe": [_vp, _vp, _vp, _vp],
     "pbf_objective": [_vp, _vp, _vp, _vp, _vp],
-    "pbf_adjoint_step": [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp],
+    "pbf_adjoint_step": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp],
     "pbf_revolve_schedule": [C.c_int, C.c_int, C.POINTER(_Action), C.c_int, C.POINTER(C.c_int), _i64p],
     "pbf_adjoint_work_bytes": [_vp, C.c_int, C.POINTER(C.c_size_t)],
     "pbf_gradient_forward": [_vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, C.c_size_t,
@@ -369,13 +369,13 @@ class Simulation:
                                            self._stream()))
         return J, lam
 
-    def adjoint_step(self, T_n, rc_prev, lam_next, mu, t_n, dt, dJdW, lam=None):
+    def adjoint_step(self, T_n, T_next, rc_prev, lam_next, mu, t_n, dt, dJdW, lam=None):
         i = self.info()
         if lam is None:
             lam = torch.empty_like(lam_next)
         h = i["n_hist_qp"] > 0
         self._check(self.lib.pbf_adjoint_step(
-            self.ctx, _f64(T_n, i["n_dofs"], "T_n"), _ptr(rc_prev) if h else None,
+            self.ctx, _f64(T_n, i["n_dofs"], "T_n"), _f64(T_next, i["n_dofs"], "T_next"), _ptr(rc_prev) if h else None,
             _f64(lam_next, i["n_dofs"], "lam_next"), _f64(lam, i["n_dofs"], "lam"),
             _ptr(mu) if h else None, float(t_n), float(dt), _ptr(dJdW) if self.n_tracks else None,
             self._stream()))
