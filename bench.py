@@ -20,6 +20,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+TIMING_EVERY = 10  # kernel events on every 10th timed step
+
 # peaks of one MI355X (public figures)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
@@ -85,7 +87,12 @@ def pmc_summary(fetch_dir, write_dir, out_path, workload, kernel="k_cells<2, dou
             rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == name]
         return rows
 
-    res = {"workload": workload, "kernel": kernel, "kernel_source_sha256_16": kernel_source_hash()}
+    run = ("python3 <repo>/bench.py --steps 30 --warmup 5 --no-cpu --no-fp32 --no-adjoint --calib-copy")
+    res = {"workload": workload, "kernel": kernel, "kernel_source_sha256_16": kernel_source_hash(),
+           "commands": ["cd /tmp && export TMPDIR=/tmp",
+                        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/fetch -o run -- {run}",
+                        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/write -o run -- {run}",
+                        f"python3 <repo>/bench.py --pmc-summary <out>/fetch <out>/write {os.path.basename(out_path)}"]}
     for d, name in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         rows = read(d, name)
         copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
@@ -221,9 +228,10 @@ def main():
         T_tmp = torch.empty_like(T)
         sim.explicit_steps(T, rc, 0.0, dt, args.warmup, precision=prec, T_tmp=T_tmp)
         torch.cuda.synchronize()
-        # timed region: K steps, kernel durations recorded with HIP events on the
-        # same stream
-        sim.timing_begin(args.steps)
+        # timed region: K steps; the library records HIP events on its stream
+        # around the kernels of every 10th step (events on every step would add
+        # ~20 us per step of launch gaps to the timed region)
+        sim.timing_begin(args.steps, every=TIMING_EVERY)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()

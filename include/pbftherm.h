@@ -309,13 +309,15 @@ pbf_status pbf_gradient_backward(pbf_ctx *ctx, double t0, double dt, int n_steps
                                  double *dJdA, double *lam0, int64_t *n_advances, void *stream);
 
 /* ---- kernel timing (instrumentation) ------------------------------------------
- * pbf_timing_begin: from now on pbf_explicit_steps records HIP events on the
- * caller's stream before and after each cell-kernel and tile-face-kernel launch,
- * for at most max_steps steps (host-side event pool, created here).
+ * pbf_timing_begin: from now on pbf_explicit_steps has the dispatches of the
+ * cell kernel and of the tile-face kernel record HIP start/stop events on the
+ * caller's stream (execution time of each kernel) on every `every`-th step
+ * (1: all), for at most max_steps timed steps (host-side event pool, created
+ * here).
  * pbf_timing_end: waits for the recorded events and returns the average
  * duration in milliseconds of the cell kernel and of the tile-face kernel and
  * the number of timed steps; releases the events.  Synchronizes. */
-pbf_status pbf_timing_begin(pbf_ctx *ctx, int max_steps);
+pbf_status pbf_timing_begin(pbf_ctx *ctx, int max_steps, int every);
 pbf_status pbf_timing_end(pbf_ctx *ctx, double *cell_ms, double *face_ms, int64_t *n_steps);
 
 #ifdef __cplusplus

@@ -77,10 +77,13 @@ struct pbf_ctx {
     } grad;
     Law<double> h_law64{}, h_lin64{}, h_zero64{};
     Law<float> h_law32{};
-    // kernel timing: 3 events per timed step (before cells, between, after faces)
+    // kernel timing: 4 events per timed step (cell kernel start/stop, face kernel
+    // start/stop), on every `timing_every`-th explicit step
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
     bool timing = false;
+    int timing_every = 1;
+    long long timing_seen = 0;
 };
 
 namespace {
@@ -439,10 +442,14 @@ pbf_status oct_pass(pbf_ctx *c, int mode, int law, const double *Tin, double *To
     p.hist = rc;
     p.has_hist = law == LAW_FULL && rc != nullptr;
     p.hist_write = hist_write ? 1 : 0;
-    const bool timed = c->timing && mode == 0 && c->tev_used + 3 <= c->tev.size();
+    const bool timed = c->timing && mode == 0 && (c->timing_seen++ % c->timing_every) == 0 &&
+                       c->tev_used + 4 <= c->tev.size();
     if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used], s));
     PBF_HIP(c, launch_oct_cells(c->degree, p, s));
-    if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
+    if (timed) {
+        PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
+        PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 2], s));
+    }
     OctNodeParams np{};
     np.m = c->od;
     np.Tin = Tin;
@@ -454,8 +461,8 @@ pbf_status oct_pass(pbf_ctx *c, int mode, int law, const double *Tin, double *To
     np.nlaw = law == LAW_CRITICAL ? c->d_lin64 : c->d_law64;
     PBF_HIP(c, launch_oct_nodes(mode, np, s));
     if (timed) {
-        PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 2], s));
-        c->tev_used += 3;
+        PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 3], s));
+        c->tev_used += 4;
     }
     return PBF_OK;
 }
@@ -492,10 +499,11 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const dou
         set_beam(c, pf, t);
     }
     if (linear) pd.nlaw = c->d_lin64;
-    const bool timed = c->timing && mode == 0 && c->tev_used + 3 <= c->tev.size();
-    if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used], s));
-    PBF_HIP(c, launch_cells(c->degree, precision, mode, column_height(), pd, pf, s));
-    if (timed) PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
+    const bool timed = c->timing && mode == 0 && (c->timing_seen++ % c->timing_every) == 0 &&
+                       c->tev_used + 4 <= c->tev.size();
+    hipEvent_t *ev = timed ? &c->tev[c->tev_used] : nullptr;
+    PBF_HIP(c, launch_cells(c->degree, precision, mode, column_height(), pd, pf, s, ev ? ev[0] : nullptr,
+                            ev ? ev[1] : nullptr));
     HaloParams h = geometry(c);
     if (linear) h.nlaw = c->d_lin64;
     h.Tin = Tin;
@@ -503,10 +511,14 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const dou
     h.fout = f;
     h.Cout = C;
     h.dt = dt;
-    PBF_HIP(c, launch_halo(mode, h, s));
+    const bool faces = h.GX + h.GY + h.GZ > 0;
+    PBF_HIP(c, launch_halo(mode, h, s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
     if (timed) {
-        PBF_HIP(c, hipEventRecord(c->tev[c->tev_used + 2], s));
-        c->tev_used += 3;
+        if (!faces) {  // no tile-face kernel: zero-length face interval
+            PBF_HIP(c, hipEventRecord(ev[2], s));
+            PBF_HIP(c, hipEventRecord(ev[3], s));
+        }
+        c->tev_used += 4;
     }
     return PBF_OK;
 }
@@ -1718,12 +1730,15 @@ pbf_status pbf_octree_remesh(pbf_ctx *c, void *workspace, size_t bytes, const do
     return PBF_OK;
 }
 
-pbf_status pbf_timing_begin(pbf_ctx *c, int max_steps)
+pbf_status pbf_timing_begin(pbf_ctx *c, int max_steps, int every)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
     if (max_steps < 1 || max_steps > (1 << 22)) return fail(c, PBF_EINVAL, "max_steps out of range");
+    if (every < 1) return fail(c, PBF_EINVAL, "every must be >= 1");
+    c->timing_every = every;
+    c->timing_seen = 0;
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
-    c->tev.assign((size_t)max_steps * 3, nullptr);
+    c->tev.assign((size_t)max_steps * 4, nullptr);
     for (auto &e : c->tev) PBF_HIP(c, hipEventCreate(&e));
     c->tev_used = 0;
     c->timing = true;
@@ -1736,12 +1751,12 @@ pbf_status pbf_timing_end(pbf_ctx *c, double *cell_ms, double *face_ms, int64_t 
     if (!c->timing) return fail(c, PBF_ESTATE, "timing was not started");
     c->timing = false;
     double a = 0.0, b = 0.0;
-    const size_t n = c->tev_used / 3;
+    const size_t n = c->tev_used / 4;
     if (n > 0) PBF_HIP(c, hipEventSynchronize(c->tev[c->tev_used - 1]));
     for (size_t k = 0; k < n; ++k) {
         float t1 = 0.f, t2 = 0.f;
-        PBF_HIP(c, hipEventElapsedTime(&t1, c->tev[3 * k], c->tev[3 * k + 1]));
-        PBF_HIP(c, hipEventElapsedTime(&t2, c->tev[3 * k + 1], c->tev[3 * k + 2]));
+        PBF_HIP(c, hipEventElapsedTime(&t1, c->tev[4 * k], c->tev[4 * k + 1]));
+        PBF_HIP(c, hipEventElapsedTime(&t2, c->tev[4 * k + 2], c->tev[4 * k + 3]));
         a += t1;
         b += t2;
     }

@@ -44,8 +44,10 @@ __device__ __forceinline__ AS4<T> *kernarg_params()
     return kp;
 }
 
-template <typename R> __device__ __forceinline__ R fmax0(R a, R b) { return a > b ? a : b; }
-template <typename R> __device__ __forceinline__ R fmin0(R a, R b) { return a < b ? a : b; }
+// max/min of finite values (one v_max/v_min instruction; the sign of a zero
+// result never matters where these are used)
+template <typename R> __device__ __forceinline__ R fmax0(R a, R b) { return fmax(a, b); }
+template <typename R> __device__ __forceinline__ R fmin0(R a, R b) { return fmin(a, b); }
 
 // compile-time loop
 template <int B, int E, typename F>

@@ -32,6 +32,7 @@
 // Workgroups are mapped so that each XCD gets a contiguous range of columns
 // and segments (neighbours then share face nodes in the same L2).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "cellkit.h"
 
@@ -40,8 +41,9 @@ namespace {
 
 // Flux and source at the Gauss points of one cell, accumulated into the
 // collocation-space integrand w.  FAST: at most one hinge of the law active, no
-// history and no source in the wave (uniform branch-free straight-line code).
-template <int P, typename R, bool FAST, typename PP, typename L>
+// source and no history update in the wave (uniform branch-free straight-line
+// code); FHIST: the FAST cell reads its (unchanged) consolidated fraction.
+template <int P, typename R, bool FAST, bool FHIST = false, typename PP, typename L>
 __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int nhinge, bool melt,
                                             bool has_hist, long long hc, bool src_cell, int cx, int cy,
                                             int cz)
@@ -52,6 +54,30 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
     const R b0 = law.b[0];
     const R dk0 = nhinge > 0 ? R(law.dk[0]) : R(0);
     const R detJ = p.detJ, ih2x = p.ih2x, ih2y = p.ih2y, ih2z = p.ih2z;
+    // General cells: the hinge sums of all points first, one hinge at a time
+    // (each coefficient is read once per cell; every point still adds its
+    // hinges in increasing order), and the Gaussian source once per (x, y)
+    // column of points (its exponent does not depend on z).
+    R kq[FAST ? 1 : NN];
+    double sq[FAST ? 1 : N * N];
+    if constexpr (!FAST) {
+#pragma unroll
+        for (int q = 0; q < NN; ++q) kq[q] = k0;
+        for (int i = 0; i < nhinge; ++i) {
+            const R bi = law.b[i], dki = law.dk[i];
+#pragma unroll
+            for (int q = 0; q < NN; ++q) kq[q] = ffma(dki, fmax0(v[q] - bi, R(0)), kq[q]);
+        }
+        if (src_cell) {
+            sfor<0, N * N>([&](auto ic) {
+                constexpr int i = decltype(ic)::value % N, j = decltype(ic)::value / N;
+                constexpr double xiq = TB::gp(i), etq = TB::gp(j);  // folded at compile time
+                const double dxb = (cx + xiq) * p.hx - p.xb;
+                const double dyb = (cy + etq) * p.hy - p.yb;
+                sq[decltype(ic)::value] = p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
+            });
+        }
+    }
     sfor<0, NN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
@@ -68,9 +94,12 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
         R k;
         if constexpr (FAST) {
             k = ffma(dk0, fmax0(T - b0, R(0)), k0);
+            if constexpr (FHIST) {
+                const R r = R(p.hist[(long long)q * p.n_hist_cells + hc]);
+                k = k * (r + law.phi * (R(1) - r));
+            }
         } else {
-            R kpl = k0;
-            for (int i = 0; i < nhinge; ++i) kpl = ffma(law.dk[i], fmax0(T - law.b[i], R(0)), kpl);
+            const R kpl = kq[q];
             k = kpl;
             if (has_hist) {
                 const long long hi = (long long)q * p.n_hist_cells + hc;
@@ -99,15 +128,10 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
         });
         if constexpr (!FAST) {
             if (src_cell) {
-                constexpr double xiq = TB::gp(qx), etq = TB::gp(qy), zeq = TB::gp(qz);
+                constexpr double zeq = TB::gp(qz);
                 const double zq = (cz + zeq) * p.hz;
                 const double depth = p.Lz - zq;
-                if (depth >= 0.0 && depth <= p.h_powder) {
-                    const double dxb = (cx + xiq) * p.hx - p.xb;
-                    const double dyb = (cy + etq) * p.hy - p.yb;
-                    const double s = p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
-                    w[q] = ffma(R(wq) * detJ, R(s), w[q]);
-                }
+                if (depth >= 0.0 && depth <= p.h_powder) w[q] = ffma(R(wq) * detJ, R(sq[qy * N + qx]), w[q]);
             }
         }
     });
@@ -143,18 +167,31 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
     // history of powder cells (point-major storage)
     const bool has_hist = cz >= p.hist_cz0;
     const long long hc = has_hist ? (long long)cx + (long long)p.nx * (cy + (long long)p.ny * (cz - p.hist_cz0)) : 0;
-    const bool src_cell = p.laser_on && p.laser_kind == 1 && cz >= p.src_cz0;
+    bool src_cell = p.laser_on && p.laser_kind == 1 && cz >= p.src_cz0;
+    if (src_cell) {
+        // Gauss points at least as far from the beam axis as the cell's box:
+        // where the Gaussian's exponent is below -750 it underflows to exactly
+        // zero in double precision, so the source adds exactly nothing there
+        const double ex = fmax(0.0, fmax(cx * p.hx - p.xb, p.xb - (cx + 1) * p.hx));
+        const double ey = fmax(0.0, fmax(cy * p.hy - p.yb, p.yb - (cy + 1) * p.hy));
+        src_cell = (ex * ex + ey * ey) * p.two_over_R2 < 750.0;
+    }
 
     R w[NN];  // collocation-space integrand of f
 #pragma unroll
     for (int q = 0; q < NN; ++q) w[q] = R(0);
-    // Most cells of a scan are cold, consolidated and away from the beam: for
-    // them the 27 points run as one straight-line block (one hinge at most, no
-    // history, no source), which lets the scheduler interleave independent
-    // points.  Both paths evaluate the same arithmetic.
-    if (nhinge <= 1 && !has_hist && !src_cell)
-        flux_points<P, R, true>(p, law, v, w, nhinge, melt, false, 0, false, cx, cy, cz);
-    else
+    // Most cells of a scan are cold and away from the beam: for them the points
+    // run as one straight-line block (one hinge at most, no source, no history
+    // update), which lets the scheduler interleave independent points.  All
+    // paths evaluate the same arithmetic.
+    // (a wave with a source cell takes the general path as a whole: running
+    // both paths under masks would cost their sum)
+    if (nhinge <= 1 && !__any(src_cell) && !(has_hist && melt)) {
+        if (has_hist)
+            flux_points<P, R, true, true>(p, law, v, w, nhinge, false, true, hc, false, cx, cy, cz);
+        else
+            flux_points<P, R, true>(p, law, v, w, nhinge, false, false, 0, false, cx, cy, cz);
+    } else
         flux_points<P, R, false>(p, law, v, w, nhinge, melt, has_hist, hc, src_cell, cx, cy, cz);
 
     // integrate f: transposed interpolation sweeps
@@ -191,6 +228,93 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
     }
 }
 
+// Owner-computes completion of the nodes of one cell layer (explicit step or
+// assembly).  The lane of cell (lx, ly) owns the nodes of its cell with local
+// x and y in 1..P (plus 0 on the column's low faces).  The sum order of every
+// node is fixed: carry (cells below), own, right, upper, diagonal neighbour.
+// Top-plane sums are carried in sC to the next layer; nodes on column faces and
+// segment ends go to the parity slot array; the others are completed here.
+// Everything is straight-line per lane: the law constants are read once, the
+// capacity hinges are truncated once per layer to those that some node of the
+// wave exceeds, and every node ends in one store through a selected address.
+template <int P, int kTY, int MODE, typename Q, typename R>
+__device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS, double *sC,
+                                             const double *sTl, int r0, int tid, int lx, int ly,
+                                             int cx, int cy, int k0, bool first, bool last,
+                                             double *slots, long long NXY)
+{
+    constexpr int N = P + 1, kTPB = kTX * kTY;
+    constexpr int BX = P * kTX + 1, BY = P * kTY + 1, PLANE = BX * BY;
+    const bool hasR = lx < kTX - 1 && cx + 1 < q.nx;
+    const bool hasU = ly < kTY - 1 && cy + 1 < q.ny;
+    const double *sTz[N];  // node plane az of the layer (rotating slots)
+#pragma unroll
+    for (int az = 0; az < N; ++az) sTz[az] = sTl + (r0 + az < N ? r0 + az : r0 + az - N) * PLANE;
+    ConstLaw<double> &L = const_law(q.nlaw);
+    // capacity hinges that some node of the wave exceeds (hinges above every
+    // node add exactly zero)
+    double tmax = sTz[0][0];
+#pragma unroll
+    for (int a = 1; a < N * N * N; ++a) tmax = fmax(tmax, sTz[a / (N * N)][((a / N) % N) * BX + a % N]);
+    int nh = 0;
+    while (nh < L.n_hinge && __any(tmax > L.b[nh])) ++nh;
+    const double c0 = L.c0, Ts = L.Ts, Tl = L.Tl, lat = L.lat, rho = L.rho;
+    const int NX = q.NX, NY = q.NY, NZ = q.NZ;
+    const unsigned dmask = q.dmask;
+    const double hx = q.hx, hy = q.hy, hz = q.hz, dt = q.dt, T_D = q.T_D;
+#pragma unroll
+    for (int az = 0; az < N; ++az) {
+#pragma unroll
+        for (int ay = 0; ay < N; ++ay) {
+#pragma unroll
+            for (int ax = 0; ax < N; ++ax) {
+                const int n = (az * N + ay) * N + ax;
+                double f = 0.0;
+                if (az == 0 && !first) f = sC[(ay * N + ax) * kTPB + tid];
+                f += double(fe[n]);
+                if (ax == P) {
+                    const double r = sS[(az * N + ay) * kTPB + tid + 1];
+                    f += hasR ? r : 0.0;
+                }
+                if (ay == P) {
+                    const double u = ax == 0 ? sS[(az * N) * kTPB + tid + kTX]
+                                             : sS[(N * N + az * P + ax - 1) * kTPB + tid + kTX];
+                    f += hasU ? u : 0.0;
+                }
+                if (ax == P && ay == P) {
+                    const double d = sS[(az * N) * kTPB + tid + kTX + 1];
+                    f += (hasR && hasU) ? d : 0.0;
+                }
+                if (az == P && !last) {  // uniform: completed by the next layer
+                    sC[(ay * N + ax) * kTPB + tid] = f;
+                    continue;
+                }
+                const bool own = (ax != 0 || lx == 0) && (ay != 0 || ly == 0);
+                const int gi = P * cx + ax, gj = P * cy + ay, gk = k0 + az;
+                const long long g = (long long)gi + (long long)NX * gj + NXY * gk;
+                const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1) ||
+                                  is_face(gi, P * kTX, NX) || is_face(gj, P * kTY, NY);
+                const double T = sTz[az][ay * BX + ax];
+                double c = c0 + ((T >= Ts && T <= Tl) ? lat : 0.0);
+                for (int h = 0; h < nh; ++h) c = __builtin_fma(L.dc[h], fmax0(T - L.b[h], 0.0), c);
+                const double m = lumped_mass_1d(gi, NX, P, hx) * lumped_mass_1d(gj, NY, P, hy) *
+                                 lumped_mass_1d(gk, NZ, P, hz);
+                const double C = rho * c * m;
+                if (MODE == 0) {
+                    const double upd = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ) ? T_D : T + dt * f / C;
+                    double *dst = face ? slots + g : q.Tout + g;
+                    const double val = face ? f : upd;
+                    if (own) *dst = val;
+                } else {
+                    double *dst = face ? slots + g : q.fout + g;
+                    if (own) *dst = f;
+                    if (own && !face) q.Cout[g] = C;
+                }
+            }
+        }
+    }
+}
+
 // MODE 0: explicit step (fused update into Tout); MODE 1: assemble f and C~.
 //
 // Node ownership inside a column: the lane of cell (lx, ly) owns the nodes of
@@ -200,6 +324,12 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
 // small LDS staging area (each cell stages its x = 0 plane and its y = 0 row);
 // the top node plane is carried per lane to the next layer.  The sum order of
 // every node is fixed: carry, own, right, upper, diagonal.
+//
+// Node planes live in N rotating LDS slots (global plane k in slot k mod N):
+// the top plane of a layer stays resident as the bottom plane of the next, and
+// the P new planes of the next layer are loaded into registers before the
+// node completion of the current one (which hides their latency) and stored
+// into the slots of the planes that layer no longer needs.
 template <int P, typename R, int MODE, int kTY>
 __global__ void __launch_bounds__(kTX * kTY) __attribute__((amdgpu_waves_per_eu(P == 2 && sizeof(R) == 8 ? 2 : (P == 2 ? 3 : 4))))
 k_cells(const CellParams<R> p)
@@ -208,12 +338,23 @@ k_cells(const CellParams<R> p)
     constexpr int N = P + 1, NN = N * N * N;
     constexpr int BX = P * kTX + 1, BY = P * kTY + 1, PLANE = BX * BY, NB = N * PLANE;
     constexpr int NSH = N * N + P * N;  // staged per cell: x = 0 plane, then y = 0 row for x = 1..P
+    constexpr int NPF = (P * PLANE + kTPB - 1) / kTPB;  // prefetched values per lane
     __shared__ double sT[NB];
-    __shared__ double sS[NSH * kTPB];
+    __shared__ double sS[NSH * kTPB + kTX + 1];  // padded: neighbour reads of edge lanes stay inside
     __shared__ double sC[N * N * kTPB];  // carry: top-plane partial sums per lane, (y, x) major
 
+    // Each XCD owns a contiguous range of tiles (whole columns when the range
+    // is a multiple of the segment count).  Within it the top segments, which
+    // hold the powder layer, the beam and the hottest cells, are dispatched
+    // first: the first workgroup on a CU is the older one and wins the issue
+    // arbitration against a later one, which shortens the critical path.
     const int b = blockIdx.x;
-    const int id = (b & 7) * p.tiles_per_xcd + (b >> 3);
+    const int xcd = b & 7, j = b >> 3;
+    int id = xcd * p.tiles_per_xcd + j;
+    if (p.tiles_per_xcd % p.MZ == 0) {
+        const int cpx = p.tiles_per_xcd / p.MZ;
+        id = (xcd * cpx + j % cpx) * p.MZ + (p.MZ - 1 - j / cpx);
+    }
     if (id >= p.ntiles) return;  // uniform over the workgroup
     const int seg = id % p.MZ, col = id / p.MZ;
     const int tx = col % p.MX, ty = col / p.MX;
@@ -222,36 +363,38 @@ k_cells(const CellParams<R> p)
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
     const long long NXY = (long long)p.NX * p.NY, NT = NXY * p.NZ;
 
+    // the N node planes of the first layer
+    for (unsigned idx = threadIdx.x; idx < unsigned(NB); idx += kTPB) {
+        const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
+        const unsigned li = rem % BX, lj = rem / BX;
+        const int gi = i0 + int(li), gj = j0 + int(lj), gk = P * z0 + int(lp);
+        double val = 0.0;
+        if (gi < p.NX && gj < p.NY) val = p.Tin[(long long)gi + (long long)p.NX * gj + NXY * gk];
+        sT[(gk % N) * PLANE + rem] = val;
+    }
+    __syncthreads();
+
 #pragma clang loop unroll(disable)
     for (int cz = z0; cz < z1; ++cz) {
-        const int k0 = P * cz;
+        const int k0 = P * cz, r0 = k0 % N;
         // Everything derived from the lane index is recomputed inside the layer
         // loop: hoisting it would hold registers across the whole march.
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         AS4<CellParams<R>> &q = *kernarg_params<CellParams<R>>();
         const Law<R> *lawp = q.law;
-        const Law<double> *nlawp = q.nlaw;
         const int lx = tid % kTX, ly = tid / kTX;
         const int cx = kTX * tx + lx, cy = kTY * ty + ly;
         const bool active = cx < q.nx && cy < q.ny;
-        // 1. stage the node planes of the layer
-        for (int idx = tid; idx < NB; idx += kTPB) {
-            const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
-            const int gi = i0 + li, gj = j0 + lj;
-            double val = 0.0;
-            if (gi < q.NX && gj < q.NY)
-                val = q.Tin[(long long)gi + (long long)q.NX * gj + NXY * (k0 + lk)];
-            sT[idx] = val;
-        }
-        __syncthreads();
-        // 2. cell operator (every lane gathers, so that no value of a previous
+        const double *sTl = sT + P * (ly * BX + lx);  // node (0,0,.) of the lane's cell
+        // 1. cell operator (every lane gathers, so that no value of a previous
         // layer stays live across the loop)
         R u[NN];
 #pragma unroll
         for (int a = 0; a < NN; ++a) {
             const int ax = a % N, ay = (a / N) % N, az = a / (N * N);
-            const double tv = sT[(az * BY + P * ly + ay) * BX + P * lx + ax];
+            const int sl = r0 + az < N ? r0 + az : r0 + az - N;
+            const double tv = sTl[sl * PLANE + ay * BX + ax];
             if constexpr (std::is_same<R, double>::value) u[a] = tv;
             else u[a] = R(tv - q.Tref);
         }
@@ -261,24 +404,42 @@ k_cells(const CellParams<R> p)
             stage_shared<P, kTPB>(sS, fe, tid);
         }
         __syncthreads();
+        // 2. loads of the next layer's new planes (global planes k0+N .. k0+N+P-1)
+        const bool more = cz + 1 < z1;
+        double pf[NPF];
+        if (more) {
+#pragma unroll
+            for (int e = 0; e < NPF; ++e) {
+                const unsigned idx = unsigned(tid) + unsigned(e * kTPB);
+                pf[e] = 0.0;
+                if (idx < unsigned(P * PLANE)) {
+                    const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
+                    const unsigned li = rem % BX, lj = rem / BX;
+                    const int gi = i0 + int(li), gj = j0 + int(lj);
+                    if (gi < q.NX && gj < q.NY)
+                        pf[e] = q.Tin[(long long)gi + (long long)q.NX * gj + NXY * (k0 + N + int(lp))];
+                }
+            }
+        }
         // 3. owned nodes: sum, carry, completion
         if (active) {
-            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
-                                q.NX, q.NY, q.NZ, q.slots + tpar * NT, NXY,
-                                [&](long long g, int gi, int gj, int gk, int ax, int ay, int az, double f) {
-                const double T = sT[(az * BY + P * ly + ay) * BX + P * lx + ax];
-                const double C = node_capacity(const_law(nlawp), T, gi, gj, gk, P, q.NX, q.NY, q.NZ,
-                                               q.hx, q.hy, q.hz);
-                if (MODE == 0) {
-                    q.Tout[g] = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ) ? q.T_D
-                                                                                    : T + q.dt * f / C;
-                } else {
-                    q.fout[g] = f;
-                    q.Cout[g] = C;
-                }
-            });
+            owner_update<P, kTY, MODE>(q, fe, sS, sC, sTl, r0, tid, lx, ly, cx, cy, k0, cz == z0,
+                                       cz == z1 - 1, q.slots + tpar * NT, NXY);
         }
         __syncthreads();
+        // 4. the new planes replace planes k0 .. k0+P-1 (slots r0 .. r0+P-1 mod N)
+        if (more) {
+#pragma unroll
+            for (int e = 0; e < NPF; ++e) {
+                const unsigned idx = unsigned(tid) + unsigned(e * kTPB);
+                if (idx < unsigned(P * PLANE)) {
+                    const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
+                    const int sl = r0 + int(lp) < N ? r0 + int(lp) : r0 + int(lp) - N;
+                    sT[sl * PLANE + rem] = pf[e];
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -308,13 +469,23 @@ __global__ void __launch_bounds__(256) k_halo(const HaloParams h)
 }  // namespace
 
 namespace {
+// Launch, with optional start/stop events recorded by the dispatch itself
+// (kernel execution time only, no queue gaps).
+template <typename K, typename A>
+void launch_maybe_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                        const A &arg)
+{
+    if (e0) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, arg);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, arg);
+}
+
 template <int TY>
 void launch_ty(int degree, int precision, int mode, const CellParams<double> &pd,
-               const CellParams<float> &pf, hipStream_t s)
+               const CellParams<float> &pf, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int tpx = precision == PBF_PREC_FP32 ? pf.tiles_per_xcd : pd.tiles_per_xcd;
     const dim3 grid(8 * tpx), block(kTX * TY);
-#define PBF_LAUNCH(P_, R_, M_, prm) hipLaunchKernelGGL((k_cells<P_, R_, M_, TY>), grid, block, 0, s, prm)
+#define PBF_LAUNCH(P_, R_, M_, prm) launch_maybe_timed(k_cells<P_, R_, M_, TY>, grid, block, s, e0, e1, prm)
     if (precision == PBF_PREC_FP64) {
         if (degree == 1) { if (mode == 0) PBF_LAUNCH(1, double, 0, pd); else PBF_LAUNCH(1, double, 1, pd); }
         else { if (mode == 0) PBF_LAUNCH(2, double, 0, pd); else PBF_LAUNCH(2, double, 1, pd); }
@@ -333,21 +504,21 @@ int column_height() { return 16; }
 int resident_columns_per_cu(int ty) { return ty == 4 ? 8 : (ty == 8 ? 4 : 2); }
 
 hipError_t launch_cells(int degree, int precision, int mode, int ty, const CellParams<double> &pd,
-                        const CellParams<float> &pf, hipStream_t s)
+                        const CellParams<float> &pf, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    if (ty == 4) launch_ty<4>(degree, precision, mode, pd, pf, s);
-    else if (ty == 8) launch_ty<8>(degree, precision, mode, pd, pf, s);
-    else launch_ty<16>(degree, precision, mode, pd, pf, s);
+    if (ty == 4) launch_ty<4>(degree, precision, mode, pd, pf, s, e0, e1);
+    else if (ty == 8) launch_ty<8>(degree, precision, mode, pd, pf, s, e0, e1);
+    else launch_ty<16>(degree, precision, mode, pd, pf, s, e0, e1);
     return hipGetLastError();
 }
 
-hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s)
+hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const long long n = hp.GX + hp.GY + hp.GZ;
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    if (mode == 0) hipLaunchKernelGGL(k_halo<0>, grid, block, 0, s, hp);
-    else hipLaunchKernelGGL(k_halo<1>, grid, block, 0, s, hp);
+    if (mode == 0) launch_maybe_timed(k_halo<0>, grid, block, s, e0, e1, hp);
+    else launch_maybe_timed(k_halo<1>, grid, block, s, e0, e1, hp);
     return hipGetLastError();
 }
 

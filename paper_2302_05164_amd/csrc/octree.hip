@@ -80,8 +80,9 @@ __device__ __forceinline__ void surface_flux(const OctParams &p, const CellGeo &
     double qs[N * N];
     sfor<0, N * N>([&](auto ic) {
         constexpr int i = decltype(ic)::value % N, j = decltype(ic)::value / N;
-        const double dxb = g.x0 + TB::gp(i) * g.hx - p.xb, dyb = g.y0 + TB::gp(j) * g.hy - p.yb;
-        qs[decltype(ic)::value] = TB::gw(i) * TB::gw(j) * g.hx * g.hy * p.src_amp *
+        constexpr double xi = TB::gp(i), et = TB::gp(j), w2 = TB::gw(i) * TB::gw(j);
+        const double dxb = g.x0 + xi * g.hx - p.xb, dyb = g.y0 + et * g.hy - p.yb;
+        qs[decltype(ic)::value] = w2 * g.hx * g.hy * p.src_amp *
                                   exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
     });
     sfor<0, N * N>([&](auto nc) {
@@ -149,9 +150,10 @@ k_oct_cells(const OctParams p)
             if constexpr (dz != 0.0) w[tidx<N, 2>(r, qx, qy)] = __builtin_fma(dz, Fz, w[tidx<N, 2>(r, qx, qy)]);
         });
         if (p.laser_on && p.laser_kind == 1) {
-            const double depth = p.m.Lz - (g.z0 + TB::gp(qz) * g.hz);
+            constexpr double xi = TB::gp(qx), et = TB::gp(qy), ze = TB::gp(qz);
+            const double depth = p.m.Lz - (g.z0 + ze * g.hz);
             if (depth >= 0.0 && depth <= p.h_powder) {
-                const double dxb = g.x0 + TB::gp(qx) * g.hx - p.xb, dyb = g.y0 + TB::gp(qy) * g.hy - p.yb;
+                const double dxb = g.x0 + xi * g.hx - p.xb, dyb = g.y0 + et * g.hy - p.yb;
                 w[q] = __builtin_fma(wq * g.detJ, p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2), w[q]);
             }
         }
@@ -209,9 +211,10 @@ k_oct_picard(const OctParams p)
                 constexpr int q = decltype(qc)::value;
                 constexpr int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
                 constexpr double wq = TB::gw(qx) * TB::gw(qy) * TB::gw(qz);
-                const double depth = p.m.Lz - (g.z0 + TB::gp(qz) * g.hz);
+                constexpr double xi = TB::gp(qx), et = TB::gp(qy), ze = TB::gp(qz);
+                const double depth = p.m.Lz - (g.z0 + ze * g.hz);
                 if (depth >= 0.0 && depth <= p.h_powder) {
-                    const double dxb = g.x0 + TB::gp(qx) * g.hx - p.xb, dyb = g.y0 + TB::gp(qy) * g.hy - p.yb;
+                    const double dxb = g.x0 + xi * g.hx - p.xb, dyb = g.y0 + et * g.hy - p.yb;
                     m[q] -= wq * g.detJ * p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
                 }
             });
@@ -294,7 +297,10 @@ __global__ void k_oct_init_history(const OctDev m, double depth, double *rc)
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= (long long)m.n_hist_cells * NQ) return;
     const int q = int(i / m.n_hist_cells), hc = int(i % m.n_hist_cells);
-    const double z = m.hist_z[2 * hc] + Tables<P>::gp(q / (N * N)) * m.hist_z[2 * hc + 1];
+    constexpr double g0 = Tables<P>::gp(0), g1 = Tables<P>::gp(1), g2 = Tables<P>::gp(P);
+    const int qz = q / (N * N);
+    const double zeta = qz == 0 ? g0 : (qz == 1 ? g1 : g2);
+    const double z = m.hist_z[2 * hc] + zeta * m.hist_z[2 * hc + 1];
     rc[i] = (m.Lz - z <= depth) ? 0.0 : 1.0;
 }
 

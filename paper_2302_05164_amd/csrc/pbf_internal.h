@@ -190,7 +190,7 @@ __host__ __device__ inline double lumped_mass_1d(int i, int n_nodes, int P, doub
 {
     if (P == 1) return (i == 0 || i == n_nodes - 1) ? 0.5 * h : h;
     if (i & 1) return (2.0 / 3.0) * h;
-    return (i == 0 || i == n_nodes - 1) ? h / 6.0 : h / 3.0;
+    return (i == 0 || i == n_nodes - 1) ? (1.0 / 6.0) * h : (1.0 / 3.0) * h;
 }
 
 // Cell kernels: a workgroup owns a column of kTX x TY cells (one cell per
@@ -198,12 +198,15 @@ __host__ __device__ inline double lumped_mass_1d(int i, int n_nodes, int P, doub
 constexpr int kTX = 16;
 
 // launchers (explicit.hip)
+// e0/e1 (optional): events recorded by the dispatch around the kernel's execution
 hipError_t launch_cells(int degree, int precision, int mode, int ty, const CellParams<double> &pd,
-                        const CellParams<float> &pf, hipStream_t s);
+                        const CellParams<float> &pf, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 // column height in cells (16 x ty columns) and resident workgroups per CU
 int column_height();
 int resident_columns_per_cu(int ty);
-hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s);
+hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 // implicit step (implicit.hip): mode 0 apply, 1 Jacobi diagonal
 int picard_column_height();
 hipError_t launch_picard(int degree, int mode, const PicardParams &pp, const HaloParams &hp,

@@ -94,7 +94,7 @@ SIGNATURES = {
     "pbf_octree_remesh_bytes": [_vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_size_t), _i64p, _i64p],
     "pbf_octree_remesh": [_vp, _vp, C.c_size_t, _vp, _vp, _vp, _vp, _vp],
     "pbf_dof_coords": [_vp, _dp],
-    "pbf_timing_begin": [_vp, C.c_int],
+    "pbf_timing_begin": [_vp, C.c_int, C.c_int],
     "pbf_timing_end": [_vp, _dp, _dp, _i64p],
 }
 
@@ -414,8 +414,9 @@ class Simulation:
         out["n_advances"] = adv.value
         return out
 
-    def timing_begin(self, max_steps):
-        self._check(self.lib.pbf_timing_begin(self.ctx, int(max_steps)))
+    def timing_begin(self, max_steps, every=1):
+        """Record kernel events on every `every`-th explicit step (at most max_steps)."""
+        self._check(self.lib.pbf_timing_begin(self.ctx, int(max_steps), int(every)))
 
     def timing_end(self):
         a, b, n = C.c_double(), C.c_double(), C.c_int64()
