@@ -30,6 +30,9 @@ class OrProblem(C.Structure):
         ("laser_kind", C.c_int), ("radius", C.c_double), ("absorptivity", C.c_double),
         ("h_powder", C.c_double), ("t_start", C.c_double),
         ("n_tracks", C.c_int), ("tracks", _dp), ("track_power", _dp),
+        ("emissivity", C.c_double), ("T_inf", C.c_double), ("evap_on", C.c_int),
+        ("T_v", C.c_double), ("C_P", C.c_double), ("C_T", C.c_double), ("C_M", C.c_double),
+        ("h_v", C.c_double), ("T_h0", C.c_double), ("dT_max", C.c_double),
     ]
 
 
@@ -70,6 +73,9 @@ def lib():
         L.or_volume_source.restype = C.c_double
         L.or_surface_source.argtypes = [P, C.c_double, C.c_double, C.c_double]
         L.or_surface_source.restype = C.c_double
+        L.or_surface_loss.argtypes = [P, C.c_double]
+        L.or_surface_loss.restype = C.c_double
+        L.or_surface_loss_vector.argtypes = [P, _dp, _dp]
         L.or_n_dofs.argtypes = [P]
         L.or_n_dofs.restype = C.c_int64
         L.or_n_qp.argtypes = [P]
@@ -153,6 +159,13 @@ class Oracle:
             s.track_power = _ptr(arr(track_power))
         else:
             s.track_power = None
+        s.emissivity = getattr(prob, "emissivity", 0.0)
+        t_inf = getattr(prob, "T_inf", None)
+        s.T_inf = prob.T_D if t_inf is None else t_inf
+        s.evap_on = 1 if getattr(prob, "evap_on", False) else 0
+        for name, default in (("T_v", 3000.0), ("C_P", 54.0e3), ("C_T", 5.0e4), ("C_M", 1.0e-3),
+                              ("h_v", 6.0e6), ("T_h0", 663.0), ("dT_max", 1000.0)):
+            setattr(s, name, getattr(prob, name, default))
         self.s = s
         self.L = lib()
         self.N = int(self.L.or_n_dofs(C.byref(s)))
@@ -201,6 +214,13 @@ class Oracle:
         self.L.or_explicit_steps(C.byref(self.s), _ptr(T), _ptr(rc), t0, dt, n)
         return T
 
+    def surface_loss_vector(self, T):
+        """f_RE(T): the radiation and evaporation terms alone, assembled."""
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        f = np.zeros(self.N)
+        self.L.or_surface_loss_vector(C.byref(self.s), _ptr(T), _ptr(f))
+        return f
+
     def explicit_step_sampled(self, T, rc, t, dt, nodes):
         nodes = np.ascontiguousarray(nodes, dtype=np.int64)
         out = np.zeros(len(nodes))
@@ -244,14 +264,20 @@ class Oracle:
         dW = np.zeros(max(1, self.s.n_tracks))
         TN = np.zeros(self.N)
         lam0 = np.zeros(self.N) if with_lam0 else None
-        self.L.or_adjoint_run(C.byref(self.s), _ptr(np.ascontiguousarray(T0)), t0, dt, n_steps,
-                              len(pts), _ptr(pts), _ptr(tg), C.byref(J), _ptr(dW), _ptr(TN),
-                              _ptr(lam0) if with_lam0 else None)
+        rc = self.L.or_adjoint_run(C.byref(self.s), _ptr(np.ascontiguousarray(T0)), t0, dt, n_steps,
+                                   len(pts), _ptr(pts), _ptr(tg), C.byref(J), _ptr(dW), _ptr(TN),
+                                   _ptr(lam0) if with_lam0 else None)
+        if rc == -2:
+            raise ValueError("the oracle adjoint covers the model without surface losses")
         if with_lam0:
             return J.value, dW[: self.s.n_tracks], TN, lam0
         return J.value, dW[: self.s.n_tracks], TN
 
     # -- scalar material law and laser (for pins) ------------------------------------
+    def surface_loss(self, T):
+        """Outward heat flux density q_rad + q_evap through the free surface at T."""
+        return self.L.or_surface_loss(C.byref(self.s), T)
+
     def liquid_fraction(self, T):
         return self.L.or_liquid_fraction(C.byref(self.s), T)
 

@@ -301,10 +301,51 @@ static void scatter(const or_octree *O, int64_t e, const double *fe, double *f)
 
 enum { HIST_UPDATE = 0, HIST_PEEK = 1, HIST_LAGGED = 2 };
 
+/* radiation and evaporation on the face of leaf e at z = Lz, if it has one:
+ * fe[a] -= int N_a q_RE(T) dA (eq. bc_rad_evap) */
+static void surface_loss_face(const or_octree *O, int64_t e, const double *Te, double *fe)
+{
+    const ref_elem *R = &O->R;
+    const or_problem *P = &O->P;
+    int64_t top = ((int64_t)P->nz << O->maxl);
+    if (!or_surface_loss_on(P) || O->leaf[4 * e + 3] + ((int64_t)1 << (O->maxl - O->leaf[4 * e])) != top) return;
+    double x0[3], h[3];
+    leaf_geometry(O, e, x0, h);
+    int n1 = R->n1;
+    for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+            double Na_s[MAXNN], Ts = 0.0;
+            for (int a = 0; a < R->nn; ++a) {
+                int ax = a % n1, ay = (a / n1) % n1, az = a / (n1 * n1);
+                Na_s[a] = or_lagrange(P->degree, ax, R->xg[i]) * or_lagrange(P->degree, ay, R->xg[j]) *
+                          or_lagrange(P->degree, az, 1.0);
+                Ts += Na_s[a] * Te[a];
+            }
+            double q = or_surface_loss(P, Ts);
+            double W = R->wg[i] * R->wg[j] * h[0] * h[1];
+            for (int a = 0; a < R->nn; ++a) fe[a] -= W * Na_s[a] * q;
+        }
+}
+
+/* f_RE(T) alone on the octree (constraint transpose included) */
+static void oct_surface_loss_vector(const or_octree *O, const double *T, double *f)
+{
+    memset(f, 0, sizeof(double) * O->ndofs);
+    double Te[MAXNN], fe[MAXNN];
+    for (int64_t e = 0; e < O->nl; ++e) {
+        gather(O, e, T, Te);
+        for (int a = 0; a < O->R.nn; ++a) fe[a] = 0.0;
+        surface_loss_face(O, e, Te, fe);
+        scatter(O, e, fe, f);
+    }
+}
+
 /* element vector of leaf e (diffusion + volume source + top-face flux) */
 static void oct_cell(const or_octree *O, int64_t e, const double *T, double *rc_cell, int hist, double t,
                      double *fe, double *fv)
 {
+    /* the implicit residual takes the surface losses lagged at T_n (separately) */
+    const int with_re = hist != HIST_LAGGED;
     const ref_elem *R = &O->R;
     const or_problem *P = &O->P;
     double x0[3], h[3];
@@ -350,6 +391,7 @@ static void oct_cell(const or_octree *O, int64_t e, const double *T, double *rc_
                 }
             }
     }
+    if (with_re) surface_loss_face(O, e, Te, fe);
 }
 
 int or_oct_assemble(const or_octree *O, const double *T, double *rc, double t, double *f, double *C,
@@ -397,6 +439,8 @@ double or_oct_stability_lambda(const or_octree *O, const double *v0, int iters)
     L.P.latent = 0.0;
     L.P.powder_k_factor = 1.0;
     L.P.laser_kind = -1;
+    L.P.emissivity = 0.0; /* the criterion involves K_diff only */
+    L.P.evap_on = 0;
     int64_t N = O->ndofs, nq = O->nl * O->R.nq;
     double *v = malloc(sizeof(double) * N), *f = malloc(sizeof(double) * N), *C = malloc(sizeof(double) * N),
            *rc = malloc(sizeof(double) * nq);
@@ -506,7 +550,9 @@ int or_oct_implicit_step(const or_octree *O, const double *Tn, double *rc, doubl
     double *res = calloc(N, sizeof(double)), *f = calloc(N, sizeof(double)), *Cl = calloc(N, sizeof(double)),
            *fv = calloc(N, sizeof(double)), *Cx = calloc(N, sizeof(double)), *diag = calloc(N, sizeof(double)),
            *x = calloc(N, sizeof(double)), *r = calloc(N, sizeof(double)), *z = calloc(N, sizeof(double)),
-           *p = calloc(N, sizeof(double)), *Ap = calloc(N, sizeof(double)), *dTn = calloc(N, sizeof(double));
+           *p = calloc(N, sizeof(double)), *Ap = calloc(N, sizeof(double)), *dTn = calloc(N, sizeof(double)),
+           *fre = calloc(N, sizeof(double));
+    oct_surface_loss_vector(O, Tn, fre); /* f_RE lagged at T_n */
     for (int64_t i = 0; i < N; ++i) Ti[i] = oct_is_dirichlet(O, i) ? O->P.T_D : Tn[i];
     int total = 0, status = 0, it;
     double last_rel = 0.0;
@@ -516,7 +562,7 @@ int or_oct_implicit_step(const or_octree *O, const double *Tn, double *rc, doubl
         oct_picard(O, Tn, Ti, rc, dt, NULL, NULL, NULL, Cx, dTn);
         double bn = 0.0;
         for (int64_t i = 0; i < N; ++i) {
-            res[i] = oct_is_dirichlet(O, i) ? 0.0 : -(Cx[i] / dt - f[i]);
+            res[i] = oct_is_dirichlet(O, i) ? 0.0 : -(Cx[i] / dt - f[i] - fre[i]);
             bn += res[i] * res[i];
         }
         bn = sqrt(bn);
@@ -565,6 +611,7 @@ int or_oct_implicit_step(const or_octree *O, const double *Tn, double *rc, doubl
     if (cg_iters_total) *cg_iters_total = total;
     if (picard_iters) *picard_iters = it;
     if (final_rel_res) *final_rel_res = last_rel;
+    free(fre);
     free(res); free(f); free(Cl); free(fv); free(Cx); free(diag); free(x); free(r); free(z); free(p); free(Ap);
     free(dTn);
     return status;

@@ -273,6 +273,36 @@ double or_surface_source(const or_problem *P, double x, double y, double t)
 }
 
 /* ------------------------------------------------------------------------- */
+/* radiation and evaporation on the free surface (eqs. bc_rad_evap,          */
+/* bc_radiation, bc_evaporation)                                              */
+/* ------------------------------------------------------------------------- */
+
+int or_surface_loss_on(const or_problem *P) { return P->emissivity != 0.0 || P->evap_on; }
+
+/* q_rad = eps sigma_S (T^4 - T_inf^4); q_evap = mdot(h_v + c([T] - T_h0)) with
+ * the evaporation mass flux mdot = 0.82 C_P exp(-C_T (1/[T] - 1/T_v)) sqrt(C_M/[T]),
+ * only where [T] > T_v, and [T] = min(T, T_v + dT_max).  c is the specific heat
+ * of the law at [T] (no latent part: [T] > T_v lies above the liquidus). */
+double or_surface_loss(const or_problem *P, double T)
+{
+    double q = 0.0;
+    if (P->emissivity != 0.0) {
+        double T2 = T * T, Ti2 = P->T_inf * P->T_inf;
+        q += P->emissivity * OR_SIGMA_SB * (T2 * T2 - Ti2 * Ti2);
+    }
+    if (P->evap_on) {
+        double Tmax = P->T_v + P->dT_max;
+        double Tc = T < Tmax ? T : Tmax;
+        if (Tc > P->T_v) {
+            double mdot = 0.82 * P->C_P * exp(-P->C_T * (1.0 / Tc - 1.0 / P->T_v)) * sqrt(P->C_M / Tc);
+            double c = or_piecewise_linear(P->n_bp, P->T_bp, P->cp_bp, Tc);
+            q += mdot * (P->h_v + c * (Tc - P->T_h0));
+        }
+    }
+    return q;
+}
+
+/* ------------------------------------------------------------------------- */
 /* mesh bookkeeping                                                           */
 /* ------------------------------------------------------------------------- */
 
@@ -336,7 +366,7 @@ enum { HIST_UPDATE = 0, HIST_PEEK = 1, HIST_LAGGED = 2 };
  * step); HIST_PEEK: the same value is used but not stored; HIST_LAGGED: the
  * stored r is used as it is (implicit step, history lagged at the step start). */
 static void cell_eval(const or_problem *P, const ref_elem *R, int cx, int cy, int cz,
-                      const double *T, double *rc_cell, int hist, double t,
+                      const double *T, double *rc_cell, int hist, int with_re, double t,
                       double *fe, double *ce, double *fv)
 {
     double h[3] = {P->Lx / P->nx, P->Ly / P->ny, P->Lz / P->nz};
@@ -389,6 +419,23 @@ static void cell_eval(const or_problem *P, const ref_elem *R, int cx, int cy, in
                 }
             }
     }
+    /* radiation and evaporation: -int N_a q_RE(T) dA over the top face z = Lz */
+    if (with_re && or_surface_loss_on(P) && cz == P->nz - 1) {
+        int n1 = R->n1;
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                double Na_s[MAXNN], Ts = 0.0;
+                for (int a = 0; a < R->nn; ++a) {
+                    int ax = a % n1, ay = (a / n1) % n1, az = a / (n1 * n1);
+                    Na_s[a] = or_lagrange(P->degree, ax, R->xg[i]) * or_lagrange(P->degree, ay, R->xg[j]) *
+                              or_lagrange(P->degree, az, 1.0);
+                    Ts += Na_s[a] * Te[a];
+                }
+                double q = or_surface_loss(P, Ts);
+                double W = R->wg[i] * R->wg[j] * h[0] * h[1];
+                for (int a = 0; a < R->nn; ++a) fe[a] -= W * Na_s[a] * q;
+            }
+    }
 }
 
 /* eq. vector_evaluation: f = sum_e G_e^T f_e; the lumped capacity is
@@ -403,7 +450,8 @@ int or_assemble(const or_problem *P, const double *T, double *rc, double t, doub
     return assemble_mode(P, T, rc, t, f, C, fvol, HIST_UPDATE);
 }
 
-/* f and C~ with the history held fixed (implicit residual) */
+/* f and C~ with the history held fixed and without the surface losses
+ * (implicit residual: they enter it lagged at T_n, see or_implicit_step) */
 int or_assemble_lagged(const or_problem *P, const double *T, const double *rc, double t, double *f,
                        double *C, double *fvol)
 {
@@ -424,7 +472,7 @@ static int assemble_mode(const or_problem *P, const double *T, double *rc, doubl
     for (int cz = 0; cz < P->nz; ++cz)
         for (int cy = 0; cy < P->ny; ++cy)
             for (int cx = 0; cx < P->nx; ++cx, ++cell) {
-                cell_eval(P, R, cx, cy, cz, T, rc + cell * R->nq, hist, t, fe, ce, fv);
+                cell_eval(P, R, cx, cy, cz, T, rc + cell * R->nq, hist, hist != HIST_LAGGED, t, fe, ce, fv);
                 for (int a = 0; a < R->nn; ++a) {
                     int64_t g = cell_node(P, cx, cy, cz, a);
                     f[g] += fe[a];
@@ -433,6 +481,37 @@ static int assemble_mode(const or_problem *P, const double *T, double *rc, doubl
                 }
             }
     for (int64_t i = 0; i < N; ++i) C[i] *= P->rho * or_capacity(P, T[i]);
+    free(R);
+    return 0;
+}
+
+/* f_RE(T) = -sum over top faces of int N_a q_RE(T) dA (eq. bc_rad_evap), the
+ * surface-loss part of f alone */
+int or_surface_loss_vector(const or_problem *P, const double *T, double *f)
+{
+    ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
+    int64_t N = or_n_dofs(P);
+    memset(f, 0, sizeof(double) * N);
+    if (or_surface_loss_on(P)) {
+        double h[2] = {P->Lx / P->nx, P->Ly / P->ny};
+        int n1 = R->n1, cz = P->nz - 1;
+        for (int cy = 0; cy < P->ny; ++cy)
+            for (int cx = 0; cx < P->nx; ++cx)
+                for (int j = 0; j < n1; ++j)
+                    for (int i = 0; i < n1; ++i) {
+                        double Na_s[MAXNN], Ts = 0.0;
+                        for (int a = 0; a < R->nn; ++a) {
+                            int ax = a % n1, ay = (a / n1) % n1, az = a / (n1 * n1);
+                            Na_s[a] = or_lagrange(P->degree, ax, R->xg[i]) *
+                                      or_lagrange(P->degree, ay, R->xg[j]) * or_lagrange(P->degree, az, 1.0);
+                            Ts += Na_s[a] * T[cell_node(P, cx, cy, cz, a)];
+                        }
+                        double q = or_surface_loss(P, Ts);
+                        double W = R->wg[i] * R->wg[j] * h[0] * h[1];
+                        for (int a = 0; a < R->nn; ++a) f[cell_node(P, cx, cy, cz, a)] -= W * Na_s[a] * q;
+                    }
+    }
     free(R);
     return 0;
 }
@@ -477,7 +556,7 @@ int or_explicit_step_sampled(const or_problem *P, const double *T, const double 
                     if (i < (int64_t)p * cx || i > (int64_t)p * cx + p) continue;
                     int64_t cell = cx + (int64_t)P->nx * (cy + (int64_t)P->ny * cz);
                     memcpy(rtmp, rc + cell * R->nq, sizeof(double) * R->nq);
-                    cell_eval(P, R, cx, cy, cz, T, rtmp, HIST_PEEK, t, fe, ce, fv);
+                    cell_eval(P, R, cx, cy, cz, T, rtmp, HIST_PEEK, 1, t, fe, ce, fv);
                     int a = (int)(i - p * cx) + n1 * ((int)(j - p * cy) + n1 * (int)(k - p * cz));
                     fsum += fe[a];
                     csum += ce[a];
@@ -511,6 +590,8 @@ double or_stability_lambda(const or_problem *P, const double *v0, int iters)
     L.latent = 0.0;
     L.powder_k_factor = 1.0;
     L.laser_kind = -1;
+    L.emissivity = 0.0; /* the criterion involves K_diff only */
+    L.evap_on = 0;
     int64_t N = or_n_dofs(P), nq = or_n_qp(P);
     double *v = (double *)malloc(sizeof(double) * N), *f = (double *)malloc(sizeof(double) * N),
            *C = (double *)malloc(sizeof(double) * N), *rc = (double *)malloc(sizeof(double) * nq);
@@ -626,7 +707,8 @@ static void picard_apply(const or_problem *P, const ref_elem *R, const double *T
 }
 
 /* Backward Euler step with Picard iterations A(T^i) dT = -R(T^i), where
- * R(T) = C(T_n)(T - T_n)/dt - f_diff(T) - f_vol(t + dt), A = C(T_n)/dt + K(T^i);
+ * R(T) = C(T_n)(T - T_n)/dt - f_diff(T) - f_RE(T_n) - f_vol(t + dt), A = C(T_n)/dt + K(T^i)
+ * (the surface losses are lagged at T_n, as the paper states for the implicit scheme);
  * the capacity and the consolidated fraction are lagged at the start of the
  * step.  Each linear system is solved by Jacobi-preconditioned CG from zero to
  * ||r|| <= cg_rtol ||b||.  Stops when ||dT||_inf <= picard_tol.  The history is
@@ -645,7 +727,8 @@ int or_implicit_step(const or_problem *P, const double *Tn, double *rc, double t
            *x = calloc(N, sizeof(double)), *r = calloc(N, sizeof(double)),
            *z = calloc(N, sizeof(double)), *p = calloc(N, sizeof(double)),
            *Ap = calloc(N, sizeof(double)), *rtmp = malloc(sizeof(double) * nq),
-           *dTn = calloc(N, sizeof(double));
+           *dTn = calloc(N, sizeof(double)), *fre = calloc(N, sizeof(double));
+    or_surface_loss_vector(P, Tn, fre);
     for (int64_t i = 0; i < N; ++i) Ti[i] = or_is_dirichlet(P, i) ? P->T_D : Tn[i];
     int total = 0, status = 0, it;
     double last_rel = 0.0;
@@ -656,7 +739,7 @@ int or_implicit_step(const or_problem *P, const double *Tn, double *rc, double t
         or_capacity_apply(P, Tn, dTn, Cx);
         double bn = 0.0;
         for (int64_t i = 0; i < N; ++i) {
-            res[i] = or_is_dirichlet(P, i) ? 0.0 : -(Cx[i] / dt - f[i]);
+            res[i] = or_is_dirichlet(P, i) ? 0.0 : -(Cx[i] / dt - f[i] - fre[i]);
             bn += res[i] * res[i];
         }
         bn = sqrt(bn);
@@ -709,7 +792,7 @@ int or_implicit_step(const or_problem *P, const double *Tn, double *rc, double t
     if (picard_iters) *picard_iters = it;
     if (final_rel_res) *final_rel_res = last_rel;
     free(res); free(f); free(Cl); free(fv); free(Cx); free(diag); free(x); free(r); free(z);
-    free(p); free(Ap); free(rtmp); free(dTn); free(R);
+    free(p); free(Ap); free(rtmp); free(dTn); free(fre); free(R);
     return status;
 }
 
@@ -769,6 +852,7 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
                    int n_probes, const double *pts, const double *targets, double *J,
                    double *dJ_dW, double *T_final, double *lam0)
 {
+    if (or_surface_loss_on(P)) return -2; /* the adjoint covers the model without surface losses */
     ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
     if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
     int64_t N = or_n_dofs(P), nq = or_n_qp(P);

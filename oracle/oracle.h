@@ -32,6 +32,11 @@ typedef struct {
     int n_tracks;
     const double *tracks; /* n_tracks x 8: x0 y0 z0 x1 y1 z1 speed power */
     const double *track_power; /* optional override of the nominal powers (n_tracks) */
+    /* radiation and evaporation on the free top surface z = Lz (eqs. bc_radiation,
+     * bc_evaporation); off when emissivity == 0 and evap_on == 0 */
+    double emissivity, T_inf;
+    int evap_on;
+    double T_v, C_P, C_T, C_M, h_v, T_h0, dT_max; /* [T] = min(T, T_v + dT_max) */
 } or_problem;
 
 /* reference element ------------------------------------------------------- */
@@ -49,6 +54,10 @@ double or_capacity(const or_problem *P, double T);
 int or_beam(const or_problem *P, double t, double *xb, double *yb, double *W, int *track);
 double or_volume_source(const or_problem *P, double x, double y, double z, double t);
 double or_surface_source(const or_problem *P, double x, double y, double t);
+/* outward heat flux density q_rad + q_evap through the free surface at T */
+double or_surface_loss(const or_problem *P, double T);
+/* f_RE(T): the surface-loss terms alone, assembled (zero when they are off) */
+int or_surface_loss_vector(const or_problem *P, const double *T, double *f);
 
 /* mesh bookkeeping ------------------------------------------------------------ */
 int64_t or_n_dofs(const or_problem *P);

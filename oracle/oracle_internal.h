@@ -3,6 +3,8 @@
 #ifndef ORACLE_INTERNAL_H
 #define ORACLE_INTERNAL_H
 
+#include "oracle.h"
+
 #define MAXN1 4  /* up to cubic elements */
 #define MAXNN 64 /* (p+1)^3 */
 
@@ -17,5 +19,11 @@ typedef struct {
 } ref_elem;
 
 int or_make_ref(int p, ref_elem *R);
+
+/* Stefan-Boltzmann constant (exact in the 2019 SI), W m^-2 K^-4 */
+#define OR_SIGMA_SB 5.670374419e-8
+
+/* surface losses switched on (radiation or evaporation) */
+int or_surface_loss_on(const or_problem *P);
 
 #endif

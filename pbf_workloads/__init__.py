@@ -67,12 +67,29 @@ class Problem:
     leaves: np.ndarray = None
     implicit_steps: int = 0
     implicit_dt: float = 0.0
+    # radiation and evaporation on the free top surface (off by default); the
+    # constants default to the stainless-steel values of the paper's Table 2
+    # (T_inf is the ambient temperature; None: T_D)
+    emissivity: float = 0.0
+    T_inf: float = None
+    evap_on: bool = False
+    T_v: float = 3000.0
+    C_P: float = 54.0e3
+    C_T: float = 5.0e4
+    C_M: float = 1.0e-3
+    h_v: float = 6.0e6
+    T_h0: float = 663.0
+    dT_max: float = 1000.0
 
     # --- counting helpers (mesh bookkeeping only) ---
     @property
     def nodes_per_dim(self):
         p = self.degree
         return (p * self.nx + 1, p * self.ny + 1, p * self.nz + 1)
+
+    @property
+    def ambient(self) -> float:
+        return self.T_D if self.T_inf is None else self.T_inf
 
     @property
     def n_dofs(self) -> int:
@@ -195,6 +212,12 @@ def small_nonlinear(nx=20, ny=18, nz=10, steps=200, seed=2302, h=31.25e-6, track
         track_length = 0.6 * L[0]
     return _base_nonlinear(f"small_q2_{nx}x{ny}x{nz}", seed, nx, ny, nz, L, steps,
                            track_length=track_length, n_tracks=n_tracks, hatch=hatch)
+
+
+def with_surface_losses(p: Problem, emissivity=0.7, evap=True) -> Problem:
+    """The same problem with radiation (emissivity of the paper's Table 2) and
+    evaporation on the top surface."""
+    return p.replace(name=p.name + "_re", emissivity=emissivity, evap_on=evap)
 
 
 def sine_mode(degree: int, n: int, k=20.0, rho=7900.0, cp=500.0) -> Problem:
