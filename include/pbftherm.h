@@ -156,6 +156,30 @@ typedef struct {
     const pbf_track *tracks;   /* host array, copied */
 } pbf_laser;
 pbf_status pbf_set_laser(pbf_ctx *ctx, const pbf_laser *l);
+
+/* ---- radiation and evaporation (Section 2, eqs. bc_rad_evap, bc_radiation,
+ * bc_evaporation) ---------------------------------------------------------------
+ * Outward heat flux density through the free top surface z = Lz (boxes) or
+ * through the faces of leaves on z = Lz (octrees):
+ *   q = emissivity sigma_S (T^4 - T_inf^4)
+ *     + 0.82 C_P exp(-C_T (1/[T] - 1/T_v)) sqrt(C_M/[T]) (h_v + c_p([T]) ([T] - T_h0)),
+ * the evaporation term only where [T] > T_v, with [T] = min(T, T_v + dT_max) and
+ * sigma_S = 5.670374419e-8 W m^-2 K^-4.  c_p is the material's specific heat
+ * (pbf_set_material) at [T].  Units: K, Pa (C_P), K s^2 m^-2 (C_M), J/kg (h_v).
+ * It enters f (explicit steps, pbf_assemble, pbf_energy's external power) at
+ * the current state and the implicit residual lagged at T_n (Section 3.2).  The
+ * stability estimate leaves it out (it concerns K_diff only).  s == NULL, or
+ * emissivity == 0 with evap_on == 0, switches the term off (the default).
+ * Errors: PBF_EINVAL for negative or non-finite constants (with evap_on:
+ * T_v, C_M, dT_max must be > 0 and C_P, C_T, h_v >= 0).  The discrete adjoint
+ * (pbf_adjoint_step, pbf_gradient_*) does not cover this term and returns
+ * PBF_ESTATE while it is on. */
+typedef struct {
+    double emissivity, T_inf;
+    int evap_on;
+    double T_v, C_P, C_T, C_M, h_v, T_h0, dT_max;
+} pbf_surface_loss;
+pbf_status pbf_set_surface_loss(pbf_ctx *ctx, const pbf_surface_loss *s);
 /* Replace the nominal track powers (host array of n_tracks) and absorptivity. */
 pbf_status pbf_set_track_powers(pbf_ctx *ctx, const double *power, double absorptivity);
 

@@ -36,6 +36,8 @@ struct pbf_ctx {
     double radius = 0, absorptivity = 0, h_powder = 0, t_start = 0;
     std::vector<pbf_track> tracks;
     std::vector<double> track_t0, track_len;
+    // radiation and evaporation on the free top surface (law pointer set per pass)
+    SurfaceLoss re{};
     // FP32 reference temperature
     double Tref = 0.0;
     // device binding
@@ -410,8 +412,18 @@ pbf_status upload_laws(pbf_ctx *c, hipStream_t s)
 }
 
 // law of an operator pass: the material law, the linear law at the critical
-// breakpoint (stability estimate), or k = 0 (source terms only)
-enum { LAW_FULL = 0, LAW_CRITICAL = 1, LAW_SOURCE = 2 };
+// breakpoint (stability estimate: no source, no surface losses), k = 0 (source
+// and surface terms only), or k = 0 without the source (surface losses alone)
+enum { LAW_FULL = 0, LAW_CRITICAL = 1, LAW_SOURCE = 2, LAW_SURFACE = 3 };
+
+// surface-loss parameters of a pass (off for the stability estimate)
+SurfaceLoss surface_params(const pbf_ctx *c, int law)
+{
+    SurfaceLoss r = c->re;
+    if (law == LAW_CRITICAL) r.on = 0;
+    r.law = c->d_law64;
+    return r;
+}
 
 OctParams oct_params(const pbf_ctx *c, const Law<double> *law, const Beam &bm)
 {
@@ -437,7 +449,8 @@ pbf_status oct_pass(pbf_ctx *c, int mode, int law, const double *Tin, double *To
 {
     const Law<double> *L = law == LAW_FULL ? c->d_law64 : (law == LAW_CRITICAL ? c->d_lin64 : c->d_zero64);
     const Beam off{false, 0, 0, 0, -1};
-    OctParams p = oct_params(c, L, law == LAW_CRITICAL ? off : beam_at(c, t));
+    OctParams p = oct_params(c, L, (law == LAW_CRITICAL || law == LAW_SURFACE) ? off : beam_at(c, t));
+    p.re = surface_params(c, law);
     p.Tin = Tin;
     p.hist = rc;
     p.has_hist = law == LAW_FULL && rc != nullptr;
@@ -486,7 +499,8 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const dou
         pd.hist = rc;
         pd.dt = dt;
         pd.hist_write = hist_write ? 1 : 0;
-        if (!linear) set_beam(c, pd, t);
+        if (!linear && law != LAW_SURFACE) set_beam(c, pd, t);
+        pd.re = surface_params(c, law);
     } else {
         pf = cell_params<float>(c, c->d_law32, true);
         pf.Tin = Tin;
@@ -497,6 +511,7 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const dou
         pf.dt = dt;
         pf.hist_write = hist_write ? 1 : 0;
         set_beam(c, pf, t);
+        pf.re = surface_params(c, law);
     }
     if (linear) pd.nlaw = c->d_lin64;
     const bool timed = c->timing && mode == 0 && (c->timing_seen++ % c->timing_every) == 0 &&
@@ -1093,6 +1108,36 @@ pbf_status pbf_set_laser(pbf_ctx *c, const pbf_laser *l)
     return PBF_OK;
 }
 
+pbf_status pbf_set_surface_loss(pbf_ctx *c, const pbf_surface_loss *r)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    SurfaceLoss q{};
+    if (r && (r->emissivity != 0.0 || r->evap_on)) {
+        if (!(r->emissivity >= 0 && std::isfinite(r->emissivity)) || !(r->T_inf >= 0 && std::isfinite(r->T_inf)))
+            return fail(c, PBF_EINVAL, "need finite emissivity >= 0 and T_inf >= 0");
+        if (r->evap_on && !(r->T_v > 0 && r->C_M > 0 && r->dT_max > 0 && r->C_P >= 0 && r->C_T >= 0 &&
+                            r->h_v >= 0 && std::isfinite(r->T_v + r->C_M + r->dT_max + r->C_P + r->C_T + r->h_v +
+                                                         r->T_h0)))
+            return fail(c, PBF_EINVAL, "evaporation: need T_v, C_M, dT_max > 0 and C_P, C_T, h_v >= 0, all finite");
+        const double sigma_S = 5.670374419e-8;  // W m^-2 K^-4 (exact in the 2019 SI)
+        const double Ti2 = r->T_inf * r->T_inf;
+        q.on = 1;
+        q.evap = r->evap_on ? 1 : 0;
+        q.eps_sigma = r->emissivity * sigma_S;
+        q.Tinf4 = Ti2 * Ti2;
+        q.Tv = r->T_v;
+        q.inv_Tv = r->evap_on ? 1.0 / r->T_v : 0.0;
+        q.Tmax = r->T_v + r->dT_max;
+        q.CP82 = 0.82 * r->C_P;
+        q.CT = r->C_T;
+        q.CM = r->C_M;
+        q.hv = r->h_v;
+        q.Th0 = r->T_h0;
+    }
+    c->re = q;
+    return PBF_OK;
+}
+
 pbf_status pbf_set_track_powers(pbf_ctx *c, const double *power, double absorptivity)
 {
     if (!c || (!power && !c->tracks.empty())) return fail(c, PBF_EINVAL, "NULL argument");
@@ -1298,14 +1343,20 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
     PBF_HIP(c, hipMemcpyAsync(Ti, T_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     PBF_HIP(c, launch_init_dirichlet(Ti, ge, c->T_D, s));
     const Beam bm = beam_at(c, t + dt);
+    // surface losses lagged at T_n (Section 3.2): f_RE(T_n) once per step
+    const bool re = c->re.on != 0;
+    if (re && (st = operator_pass(c, 1, PBF_PREC_FP64, LAW_SURFACE, T_n, nullptr, c->d_f, c->d_C, nullptr, t,
+                                  0.0, s)))
+        return st;
     int total = 0, it = 0;
     bool cg_fail = false, converged = false;
     double last_rel = 0.0;
     double hs[8];
     for (it = 0; it < picard_max_it;) {
-        // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_vol, and diag(A(T^i))
+        // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_RE(T_n) - f_vol, and diag(A(T^i))
         PBF_HIP(c, launch_sub(d, Ti, T_n, N, s));
         if ((st = picard_pass(c, 0, hp, T_n, Ti, d, Ti, y, rc, dt, &bm, s))) return st;
+        if (re) PBF_HIP(c, launch_sub(y, y, c->d_f, N, s));
         if ((st = picard_pass(c, 1, hp, T_n, Ti, nullptr, nullptr, diag, rc, dt, nullptr, s))) return st;
         PBF_HIP(c, launch_cg_start(y, diag, r, z, p, x, c->d_partials, c->d_scal, ge, N, s));
         PBF_HIP(c, hipMemcpyAsync(hs, c->d_scal + CG_RZ0, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1414,6 +1465,7 @@ pbf_status pbf_adjoint_step(pbf_ctx *c, const double *T_n, const double *T_next,
                             void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (c->re.on) return fail(c, PBF_ESTATE, "the adjoint does not cover surface losses (pbf_set_surface_loss)");
     if (c->octree) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "probes and the adjoint need a box mesh");
     pbf_status st = check_bound(c);
     if (st) return st;
@@ -1476,6 +1528,7 @@ pbf_status pbf_gradient_forward(pbf_ctx *c, const double *T0, const double *rc0,
                                 double *J, void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (c->re.on) return fail(c, PBF_ESTATE, "the adjoint does not cover surface losses (pbf_set_surface_loss)");
     pbf_status st = check_grad_args(c, dt, n_steps, n_snaps, work, work_bytes);
     if (st) return st;
     if (!T0 || (n_hist_qp(c) > 0 && !rc0)) return fail(c, PBF_EINVAL, "NULL initial state");
@@ -1527,6 +1580,7 @@ pbf_status pbf_gradient_backward(pbf_ctx *c, double t0, double dt, int n_steps, 
                                  int64_t *n_advances, void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (c->re.on) return fail(c, PBF_ESTATE, "the adjoint does not cover surface losses (pbf_set_surface_loss)");
     pbf_status st = check_grad_args(c, dt, n_steps, n_snaps, work, work_bytes);
     if (st) return st;
     if (!c->grad.valid || c->grad.work != work || c->grad.n_steps != n_steps || c->grad.n_snaps != n_snaps ||

@@ -144,6 +144,59 @@ __device__ __forceinline__ double node_capacity(ConstLaw<double> &L, double T, i
 }
 
 
+// Outward heat flux density through the free surface at temperature T
+// (radiation plus evaporation, see SurfaceLoss); the specific heat of the
+// enthalpy term is the law's c_p at [T] (all hinges).
+template <typename S>
+__device__ __forceinline__ double surface_loss(S &s, double T)
+{
+    const double T2 = T * T;
+    double q = s.eps_sigma * (T2 * T2 - s.Tinf4);
+    if (s.evap) {
+        const double Tc = fmin(T, s.Tmax);
+        if (Tc > s.Tv) {
+            ConstLaw<double> &L = const_law(s.law);
+            double c = L.c0;
+            for (int h = 0; h < L.n_hinge; ++h) c = __builtin_fma(L.dc[h], fmax(Tc - L.b[h], 0.0), c);
+            const double mdot = s.CP82 * exp(-s.CT * (1.0 / Tc - s.inv_Tv)) * sqrt(s.CM / Tc);
+            q += mdot * (s.hv + c * (Tc - s.Th0));
+        }
+    }
+    return q;
+}
+
+// Surface losses of a cell with a face on z = Lz: fe[top node layer] -=
+// S^T (w_i w_j hx hy q(T_ij)), T_ij interpolated at the face Gauss points from
+// the top node layer values Ttop(ax, ay) (Section 2, eq. bc_rad_evap, weak form).
+template <int P, typename S, typename F, typename R>
+__device__ __forceinline__ void surface_loss_face(S &s, double hx, double hy, F &&Ttop, R *fe)
+{
+    using TB = Tables<P>;
+    constexpr int N = P + 1;
+    double qs[N * N];
+    sfor<0, N * N>([&](auto ic) {
+        constexpr int i = decltype(ic)::value % N, j = decltype(ic)::value / N;
+        double Ts = 0.0;
+        sfor<0, N * N>([&](auto nc) {
+            constexpr int ax = decltype(nc)::value % N, ay = decltype(nc)::value / N;
+            constexpr double cc = TB::S(i, ax) * TB::S(j, ay);
+            if constexpr (cc != 0.0) Ts = __builtin_fma(cc, Ttop(ax, ay), Ts);
+        });
+        constexpr double w2 = TB::gw(i) * TB::gw(j);
+        qs[decltype(ic)::value] = w2 * hx * hy * surface_loss(s, Ts);
+    });
+    sfor<0, N * N>([&](auto nc) {
+        constexpr int ax = decltype(nc)::value % N, ay = decltype(nc)::value / N;
+        double acc = 0.0;
+        sfor<0, N * N>([&](auto ic) {
+            constexpr int i = decltype(ic)::value % N, j = decltype(ic)::value / N;
+            constexpr double cc = TB::S(i, ax) * TB::S(j, ay);
+            if constexpr (cc != 0.0) acc = __builtin_fma(cc, qs[decltype(ic)::value], acc);
+        });
+        fe[(P * N + ay) * N + ax] -= R(acc);
+    });
+}
+
 // Stage the contributions of a cell that neighbours need: its x = 0 node plane
 // and its y = 0 node row (x = 1..P), NSH = (P+1)^2 + P (P+1) values per lane.
 template <int P, int kTPB, typename R>

@@ -401,6 +401,11 @@ k_cells(const CellParams<R> p)
         R fe[NN];
         if (active) {
             cell_operator<P, R>(q, lawp, u, cx, cy, cz, fe);
+            if (q.re.on && cz == q.nz - 1) {  // top face: radiation and evaporation
+                const int st = r0 + P < N ? r0 + P : r0 + P - N;
+                const double *top = sTl + st * PLANE;
+                surface_loss_face<P>(q.re, q.hx, q.hy, [&](int ax, int ay) { return top[ay * BX + ax]; }, fe);
+            }
             stage_shared<P, kTPB>(sS, fe, tid);
         }
         __syncthreads();

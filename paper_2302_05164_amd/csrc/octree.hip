@@ -162,6 +162,10 @@ k_oct_cells(const OctParams p)
     sweep<TagSt<P>, N, 1>(t1, t2);
     sweep<TagSt<P>, N, 2>(t2, u);
     if (p.laser_on && p.laser_kind == 0 && g.top) surface_flux<P>(p, g, 1.0, u);
+    if (p.re.on && g.top) {  // radiation and evaporation on the face z = Lz
+        oct_gather<P>(p.m, p.Tin, c, t1);
+        surface_loss_face<P>(p.re, g.hx, g.hy, [&](int ax, int ay) { return t1[(P * N + ay) * N + ax]; }, u);
+    }
 #pragma unroll
     for (int a = 0; a < NN; ++a) p.m.E[(long long)a * p.m.n_cells + c] = u[a];
 }

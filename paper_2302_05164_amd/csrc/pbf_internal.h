@@ -94,6 +94,20 @@ struct Law {
     R phi, rho;
 };
 
+// Radiation and evaporation on the free top surface z = Lz (Section 2, eqs.
+// bc_radiation and bc_evaporation): outward flux density
+//   q(T) = eps sigma_S (T^4 - T_inf^4)
+//        + 0.82 C_P exp(-C_T (1/[T] - 1/T_v)) sqrt(C_M/[T]) (h_v + c_p([T]) ([T] - T_h0))
+// (second term only where [T] > T_v), [T] = min(T, T_v + dT_max).  on == 0: off.
+struct SurfaceLoss {
+    int on, evap;
+    double eps_sigma, Tinf4;   // eps sigma_S, T_inf^4
+    double Tv, inv_Tv, Tmax;   // boiling point, 1/T_v, clamp T_v + dT_max
+    double CP82, CT, CM;       // 0.82 C_P, C_T, C_M
+    double hv, Th0;            // latent heat of evaporation, enthalpy reference temperature
+    const Law<double> *law;    // material law (specific heat of the enthalpy term)
+};
+
 // Parameters of one cell-kernel launch (passed by value).
 template <typename R>
 struct CellParams {
@@ -115,6 +129,7 @@ struct CellParams {
     double xb, yb, src_amp, two_over_R2, h_powder;
     const Law<R> *law;          // quadrature-point law (device copy, uniform indices)
     const Law<double> *nlaw;    // nodal capacity law (always double)
+    SurfaceLoss re;             // top-surface losses (evaluated in double)
 };
 
 // Parameters of the Picard-operator kernels of the implicit step.
@@ -305,6 +320,7 @@ struct OctParams {
     int laser_on, laser_kind;
     double xb, yb, src_amp, two_over_R2, h_powder;
     const Law<double> *law;
+    SurfaceLoss re;  // top-surface losses of leaves with a face on z = Lz
 };
 // node pass: mode 0 explicit update, 1 assemble f and C~, 2 Picard apply
 // (Dirichlet rows 0), 3 Picard diagonal (squared weights, Dirichlet rows 1)

@@ -41,6 +41,12 @@ class _Track(C.Structure):
                 ("power", C.c_double)]
 
 
+class _SurfaceLoss(C.Structure):
+    _fields_ = [("emissivity", C.c_double), ("T_inf", C.c_double), ("evap_on", C.c_int),
+                ("T_v", C.c_double), ("C_P", C.c_double), ("C_T", C.c_double), ("C_M", C.c_double),
+                ("h_v", C.c_double), ("T_h0", C.c_double), ("dT_max", C.c_double)]
+
+
 class _Laser(C.Structure):
     _fields_ = [("kind", C.c_int), ("radius", C.c_double), ("absorptivity", C.c_double),
                 ("h_powder", C.c_double), ("t_start", C.c_double), ("n_tracks", C.c_int),
@@ -67,6 +73,7 @@ SIGNATURES = {
     "pbf_set_dirichlet": [_vp, C.c_uint, C.c_double],
     "pbf_set_material": [_vp, C.POINTER(_Material)],
     "pbf_set_laser": [_vp, C.POINTER(_Laser)],
+    "pbf_set_surface_loss": [_vp, C.POINTER(_SurfaceLoss)],
     "pbf_set_track_powers": [_vp, _dp, C.c_double],
     "pbf_workspace_bytes": [_vp, C.POINTER(C.c_size_t)],
     "pbf_bind_device": [_vp, _vp, C.c_size_t, _vp],
@@ -225,6 +232,14 @@ class Simulation:
                    len(tr), arr)
         self._check(self.lib.pbf_set_laser(self.ctx, C.byref(l)))
         self.n_tracks = len(tr)
+
+    def set_surface_loss(self, emissivity=0.0, T_inf=293.0, evap_on=False, T_v=3000.0, C_P=54.0e3,
+                         C_T=5.0e4, C_M=1.0e-3, h_v=6.0e6, T_h0=663.0, dT_max=1000.0):
+        """Radiation and evaporation on the free top surface (off when emissivity
+        is 0 and evap_on is False)."""
+        r = _SurfaceLoss(float(emissivity), float(T_inf), 1 if evap_on else 0, float(T_v), float(C_P),
+                         float(C_T), float(C_M), float(h_v), float(T_h0), float(dT_max))
+        self._check(self.lib.pbf_set_surface_loss(self.ctx, C.byref(r)))
 
     def set_track_powers(self, powers, absorptivity):
         p = np.ascontiguousarray(powers, dtype=np.float64)
@@ -436,5 +451,9 @@ def from_problem(prob, device="cuda:0", leaves=None):
                    prob.powder_k_factor, prob.powder_depth)
     s.set_laser(prob.laser_kind, prob.radius, prob.absorptivity, prob.h_powder, prob.t_start,
                 prob.tracks)
+    if getattr(prob, "emissivity", 0.0) or getattr(prob, "evap_on", False):
+        t_inf = getattr(prob, "T_inf", None)
+        s.set_surface_loss(prob.emissivity, prob.T_D if t_inf is None else t_inf, prob.evap_on, prob.T_v,
+                           prob.C_P, prob.C_T, prob.C_M, prob.h_v, prob.T_h0, prob.dT_max)
     s.bind()
     return s

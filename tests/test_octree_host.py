@@ -67,3 +67,21 @@ def test_invalid_leaf_sets_are_rejected():
         assert _mesh(L, ctx, p, lv) == 0
     finally:
         L.pbf_destroy(ctx)
+
+
+def test_surface_loss_parameters_validated():
+    """pbf_set_surface_loss rejects negative or non-finite constants (no GPU)."""
+    from paper_2302_05164_amd import pbftherm
+    L, ctx = _ctx()
+    try:
+        S = pbftherm._SurfaceLoss
+        ok = S(0.7, 293.0, 1, 3000.0, 54e3, 5e4, 1e-3, 6e6, 663.0, 1000.0)
+        assert L.pbf_set_surface_loss(ctx, C.byref(ok)) == 0
+        assert L.pbf_set_surface_loss(ctx, None) == 0  # off
+        for bad in (S(-0.1, 293.0, 0, 0, 0, 0, 0, 0, 0, 0), S(float("nan"), 293.0, 0, 0, 0, 0, 0, 0, 0, 0),
+                    S(0.7, 293.0, 1, 3000.0, 54e3, 5e4, 0.0, 6e6, 663.0, 1000.0),
+                    S(0.7, 293.0, 1, 3000.0, 54e3, 5e4, 1e-3, 6e6, 663.0, -5.0)):
+            assert L.pbf_set_surface_loss(ctx, C.byref(bad)) != 0
+            assert L.pbf_last_error(ctx)
+    finally:
+        L.pbf_destroy(ctx)
