@@ -76,6 +76,12 @@ def lib():
         L.or_surface_loss.argtypes = [P, C.c_double]
         L.or_surface_loss.restype = C.c_double
         L.or_surface_loss_vector.argtypes = [P, _dp, _dp]
+        L.or_jacobian_apply.argtypes = [P, _dp, _dp, _dp, C.c_double, _dp, _dp]
+        L.or_picard_apply.argtypes = [P, _dp, _dp, _dp, C.c_double, _dp, _dp]
+        L.or_implicit_residual.argtypes = [P, _dp, _dp, _dp, C.c_double, C.c_double, _dp]
+        L.or_implicit_step_newton.argtypes = [P, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                              C.c_double, C.c_int, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                              C.POINTER(C.c_double)]
         L.or_n_dofs.argtypes = [P]
         L.or_n_dofs.restype = C.c_int64
         L.or_n_qp.argtypes = [P]
@@ -247,6 +253,35 @@ class Oracle:
                                      cg_rtol, cg_max_it, picard_tol, picard_max_it, _ptr(out),
                                      C.byref(it), C.byref(pit), C.byref(res))
         return out, dict(status=st, cg_iters=it.value, picard_iters=pit.value, rel_res=res.value)
+
+    def picard_apply(self, Tn, Ti, rc, dt, x):
+        """y = (C(T_n)/dt + K(T^i)) x, the symmetric part of the Jacobian."""
+        y = np.zeros(self.N)
+        c = np.ascontiguousarray
+        self.L.or_picard_apply(C.byref(self.s), _ptr(c(Tn)), _ptr(c(Ti)), _ptr(c(rc)), dt, _ptr(c(x)), _ptr(y))
+        return y
+
+    def jacobian_apply(self, Tn, Ti, rc, dt, x):
+        """y = J(T^i) x of the implicit residual (Newton, eq. Newton_1)."""
+        y = np.zeros(self.N)
+        c = np.ascontiguousarray
+        self.L.or_jacobian_apply(C.byref(self.s), _ptr(c(Tn)), _ptr(c(Ti)), _ptr(c(rc)), dt, _ptr(c(x)), _ptr(y))
+        return y
+
+    def implicit_residual(self, Tn, T, rc, t, dt):
+        r = np.zeros(self.N)
+        c = np.ascontiguousarray
+        self.L.or_implicit_residual(C.byref(self.s), _ptr(c(Tn)), _ptr(c(T)), _ptr(c(rc)), t, dt, _ptr(r))
+        return r
+
+    def implicit_step_newton(self, Tn, rc, t, dt, lin_rtol=1e-10, restart=30, lin_max_it=5000,
+                             newton_tol=1e-8, newton_max_it=30):
+        out = np.zeros(self.N)
+        it, nit, res = C.c_int(0), C.c_int(0), C.c_double(0)
+        st = self.L.or_implicit_step_newton(C.byref(self.s), _ptr(np.ascontiguousarray(Tn)), _ptr(rc), t, dt,
+                                            lin_rtol, restart, lin_max_it, newton_tol, newton_max_it, _ptr(out),
+                                            C.byref(it), C.byref(nit), C.byref(res))
+        return out, dict(status=st, lin_iters=it.value, newton_iters=nit.value, rel_res=res.value)
 
     # -- probes and adjoint ---------------------------------------------------------
     def probe(self, T, pts):

@@ -706,6 +706,222 @@ static void picard_apply(const or_problem *P, const ref_elem *R, const double *T
         }
 }
 
+/* Newton Jacobian of the implicit residual (eq. Newton_1 with the capacity,
+ * history and surface losses lagged at the step start): y = J x with
+ *   J = C(T_n)/dt + K(T^i) + L(T^i),  L_ab = sum_q W k_T(T^i_q, r_q) N_b(q) gradN_a(q) . gradT^i_q,
+ * k_T the derivative of k at fixed consolidated fraction (eq. material_parameter_interp).
+ * x is taken as zero on Dirichlet nodes, whose rows of y are zero. */
+static void newton_apply(const or_problem *P, const ref_elem *R, const double *Tn, const double *Ti,
+                         const double *rc, double dt, const double *x, double *y)
+{
+    double h[3] = {P->Lx / P->nx, P->Ly / P->ny, P->Lz / P->nz};
+    double detJ = h[0] * h[1] * h[2];
+    int64_t N = or_n_dofs(P);
+    picard_apply(P, R, Tn, Ti, rc, dt, x, y, NULL);
+    int64_t cell = 0;
+    for (int cz = 0; cz < P->nz; ++cz)
+        for (int cy = 0; cy < P->ny; ++cy)
+            for (int cx = 0; cx < P->nx; ++cx, ++cell) {
+                int64_t gn[MAXNN];
+                double xe[MAXNN];
+                for (int a = 0; a < R->nn; ++a) {
+                    gn[a] = cell_node(P, cx, cy, cz, a);
+                    xe[a] = !or_is_dirichlet(P, gn[a]) ? x[gn[a]] : 0.0;
+                }
+                for (int q = 0; q < R->nq; ++q) {
+                    double Tiq = 0.0, xq = 0.0, gT[3] = {0, 0, 0};
+                    for (int b = 0; b < R->nn; ++b) {
+                        Tiq += R->N[b][q] * Ti[gn[b]];
+                        xq += R->N[b][q] * xe[b];
+                        for (int d = 0; d < 3; ++d) gT[d] += R->dN[b][q][d] / h[d] * Ti[gn[b]];
+                    }
+                    double kT = conductivity_dT(P, Tiq, rc[cell * R->nq + q]);
+                    double W = R->wq[q] * detJ;
+                    for (int a = 0; a < R->nn; ++a) {
+                        double gg = 0.0;
+                        for (int d = 0; d < 3; ++d) gg += R->dN[a][q][d] / h[d] * gT[d];
+                        y[gn[a]] += W * kT * xq * gg;
+                    }
+                }
+            }
+    for (int64_t i = 0; i < N; ++i)
+        if (or_is_dirichlet(P, i)) y[i] = 0.0;
+}
+
+int or_picard_apply(const or_problem *P, const double *Tn, const double *Ti, const double *rc, double dt,
+                    const double *x, double *y)
+{
+    ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
+    picard_apply(P, R, Tn, Ti, rc, dt, x, y, NULL);
+    free(R);
+    return 0;
+}
+
+int or_jacobian_apply(const or_problem *P, const double *Tn, const double *Ti, const double *rc, double dt,
+                      const double *x, double *y)
+{
+    ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
+    if (!R || or_make_ref(P->degree, R)) { free(R); return -1; }
+    newton_apply(P, R, Tn, Ti, rc, dt, x, y);
+    free(R);
+    return 0;
+}
+
+/* Implicit residual R(T) = C(T_n)(T - T_n)/dt - f_diff(T) - f_RE(T_n) - f_vol(t + dt)
+ * (eq. backward_euler_nonlinear), zero on Dirichlet rows; fre = f_RE(T_n). */
+static void implicit_residual(const or_problem *P, const double *Tn, const double *T, const double *rc,
+                              double t1, double dt, const double *fre, double *res, double *work)
+{
+    int64_t N = or_n_dofs(P);
+    double *f = work, *Cl = work + N, *fv = work + 2 * N, *dTn = work + 3 * N, *Cx = work + 4 * N;
+    or_assemble_lagged(P, T, rc, t1, f, Cl, fv);
+    for (int64_t i = 0; i < N; ++i) dTn[i] = T[i] - Tn[i];
+    or_capacity_apply(P, Tn, dTn, Cx);
+    for (int64_t i = 0; i < N; ++i) res[i] = or_is_dirichlet(P, i) ? 0.0 : Cx[i] / dt - f[i] - fre[i];
+}
+
+int or_implicit_residual(const or_problem *P, const double *Tn, const double *T, const double *rc, double t,
+                         double dt, double *res)
+{
+    int64_t N = or_n_dofs(P);
+    double *fre = malloc(sizeof(double) * N), *work = malloc(sizeof(double) * 5 * N);
+    or_surface_loss_vector(P, Tn, fre);
+    implicit_residual(P, Tn, T, rc, t + dt, dt, fre, res, work);
+    free(fre);
+    free(work);
+    return 0;
+}
+
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* Restarted GMRES(m) for J x = b from x = 0, right-preconditioned with
+ * M = diag (Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.5):
+ * Arnoldi on J M^{-1} with classical Gram-Schmidt applied twice, Givens
+ * rotations on the Hessenberg matrix, stop when the residual estimate
+ * |g_{j+1}| <= rtol ||b||; x = M^{-1} V_j y_j at each restart.  Returns the
+ * number of Arnoldi steps; *rel gets the final true relative residual. */
+static int gmres(const or_problem *P, const ref_elem *R, const double *Tn, const double *Ti, const double *rc,
+                 double dt, const double *diag, const double *b, double *x, int m, double rtol, int max_it,
+                 double *rel, int *ok)
+{
+    int64_t N = or_n_dofs(P);
+    double *V = malloc(sizeof(double) * N * (m + 1)), *w = malloc(sizeof(double) * N),
+           *z = malloc(sizeof(double) * N), *r = malloc(sizeof(double) * N);
+    double *H = calloc((size_t)(m + 1) * m, sizeof(double)), *cs = calloc(m, sizeof(double)),
+           *sn = calloc(m, sizeof(double)), *g = calloc(m + 1, sizeof(double)), *hc = calloc(m + 1, sizeof(double)),
+           *y = calloc(m, sizeof(double));
+    double bn = sqrt(dot(N, b, b));
+    int it = 0;
+    *ok = 0;
+    for (int64_t i = 0; i < N; ++i) x[i] = 0.0;
+    memcpy(r, b, sizeof(double) * N);
+    double rn = bn;
+    while (bn > 0 && rn > rtol * bn && it < max_it) {
+        for (int64_t i = 0; i < N; ++i) V[i] = r[i] / rn;
+        for (int k = 0; k <= m; ++k) g[k] = 0.0;
+        g[0] = rn;
+        int j;
+        for (j = 0; j < m && it < max_it; ++j) {
+            for (int64_t i = 0; i < N; ++i) z[i] = V[(int64_t)j * N + i] / diag[i];
+            newton_apply(P, R, Tn, Ti, rc, dt, z, w);
+            for (int k = 0; k <= j; ++k) hc[k] = 0.0;
+            for (int pass = 0; pass < 2; ++pass) { /* classical Gram-Schmidt, twice */
+                double hp[64];
+                for (int k = 0; k <= j; ++k) hp[k] = dot(N, w, V + (int64_t)k * N);
+                for (int k = 0; k <= j; ++k) {
+                    for (int64_t i = 0; i < N; ++i) w[i] -= hp[k] * V[(int64_t)k * N + i];
+                    hc[k] += hp[k];
+                }
+            }
+            double hn = sqrt(dot(N, w, w));
+            ++it;
+            for (int64_t i = 0; i < N; ++i) V[(int64_t)(j + 1) * N + i] = hn > 0 ? w[i] / hn : 0.0;
+            /* previous rotations, then a new one that zeroes hn */
+            for (int k = 0; k < j; ++k) {
+                double a = cs[k] * hc[k] + sn[k] * hc[k + 1];
+                hc[k + 1] = -sn[k] * hc[k] + cs[k] * hc[k + 1];
+                hc[k] = a;
+            }
+            double den = sqrt(hc[j] * hc[j] + hn * hn);
+            cs[j] = den > 0 ? hc[j] / den : 1.0;
+            sn[j] = den > 0 ? hn / den : 0.0;
+            hc[j] = den;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = hc[k];
+            if (fabs(g[j + 1]) <= rtol * bn || hn == 0.0) { ++j; break; }
+        }
+        /* y = H^{-1} g (upper triangular j x j), x += M^{-1} V y */
+        for (int k = j - 1; k >= 0; --k) {
+            double s = g[k];
+            for (int l = k + 1; l < j; ++l) s -= H[(size_t)k * m + l] * y[l];
+            y[k] = s / H[(size_t)k * m + k];
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < j; ++k) s += y[k] * V[(int64_t)k * N + i];
+            x[i] += s / diag[i];
+        }
+        newton_apply(P, R, Tn, Ti, rc, dt, x, w);
+        for (int64_t i = 0; i < N; ++i) r[i] = b[i] - w[i];
+        rn = sqrt(dot(N, r, r));
+    }
+    *rel = bn > 0 ? rn / bn : 0.0;
+    *ok = !(bn > 0 && rn > rtol * bn);
+    free(V); free(w); free(z); free(r); free(H); free(cs); free(sn); free(g); free(hc); free(y);
+    return it;
+}
+
+/* Backward Euler step by Newton's method (eqs. Newton_1, Newton_2): J(T^i) dT =
+ * -R(T^i) solved by restarted GMRES(m) with Jacobi (the diagonal of the Picard
+ * matrix C(T_n)/dt + K(T^i)) on the right, to ||r|| <= lin_rtol ||b||; stops
+ * when ||dT||_inf <= newton_tol.  The history is committed after convergence.
+ * Returns 0, 1 if a linear solve missed its tolerance, 2 if Newton did not converge. */
+int or_implicit_step_newton(const or_problem *P, const double *Tn, double *rc, double t, double dt,
+                            double lin_rtol, int restart, int lin_max_it, double newton_tol, int newton_max_it,
+                            double *T_out, int *lin_iters_total, int *newton_iters, double *final_rel_res)
+{
+    ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
+    if (!R || or_make_ref(P->degree, R) || restart < 1 || restart > 63) { free(R); return -1; }
+    int64_t N = or_n_dofs(P);
+    double *Ti = T_out;
+    double *res = malloc(sizeof(double) * N), *b = malloc(sizeof(double) * N), *x = malloc(sizeof(double) * N),
+           *diag = malloc(sizeof(double) * N), *fre = malloc(sizeof(double) * N),
+           *work = malloc(sizeof(double) * 5 * N), *f = malloc(sizeof(double) * N), *Cl = malloc(sizeof(double) * N);
+    or_surface_loss_vector(P, Tn, fre);
+    for (int64_t i = 0; i < N; ++i) Ti[i] = or_is_dirichlet(P, i) ? P->T_D : Tn[i];
+    int total = 0, status = 0, it;
+    double last_rel = 0.0;
+    for (it = 0; it < newton_max_it; ++it) {
+        implicit_residual(P, Tn, Ti, rc, t + dt, dt, fre, res, work);
+        for (int64_t i = 0; i < N; ++i) b[i] = -res[i];
+        picard_apply(P, R, Tn, Ti, rc, dt, NULL, NULL, diag);
+        int ok = 0;
+        total += gmres(P, R, Tn, Ti, rc, dt, diag, b, x, restart, lin_rtol, lin_max_it, &last_rel, &ok);
+        if (!ok) status = 1;
+        double dmax = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            if (or_is_dirichlet(P, i)) continue;
+            Ti[i] += x[i];
+            if (fabs(x[i]) > dmax) dmax = fabs(x[i]);
+        }
+        if (dmax <= newton_tol) { ++it; break; }
+    }
+    if (it >= newton_max_it && status == 0) status = 2;
+    or_assemble(P, Ti, rc, t + dt, f, Cl, NULL); /* commit the history */
+    if (lin_iters_total) *lin_iters_total = total;
+    if (newton_iters) *newton_iters = it;
+    if (final_rel_res) *final_rel_res = last_rel;
+    free(res); free(b); free(x); free(diag); free(fre); free(work); free(f); free(Cl); free(R);
+    return status;
+}
+
 /* Backward Euler step with Picard iterations A(T^i) dT = -R(T^i), where
  * R(T) = C(T_n)(T - T_n)/dt - f_diff(T) - f_RE(T_n) - f_vol(t + dt), A = C(T_n)/dt + K(T^i)
  * (the surface losses are lagged at T_n, as the paper states for the implicit scheme);

@@ -80,6 +80,19 @@ int or_capacity_apply(const or_problem *P, const double *Tn, const double *x, do
 int or_implicit_step(const or_problem *P, const double *Tn, double *rc, double t, double dt,
                      double cg_rtol, int cg_max_it, double picard_tol, int picard_max_it,
                      double *T_out, int *cg_iters_total, int *picard_iters, double *final_rel_res);
+/* Picard matrix: y = (C(T_n)/dt + K(T^i)) x (x zero on Dirichlet nodes, rows zero there) */
+int or_picard_apply(const or_problem *P, const double *Tn, const double *Ti, const double *rc, double dt,
+                    const double *x, double *y);
+/* Newton: y = J(T^i) x (eq. Newton_1, capacity/history/surface losses lagged) */
+int or_jacobian_apply(const or_problem *P, const double *Tn, const double *Ti, const double *rc, double dt,
+                      const double *x, double *y);
+/* R(T) of eq. backward_euler_nonlinear with f_RE lagged at T_n (0 on Dirichlet rows) */
+int or_implicit_residual(const or_problem *P, const double *Tn, const double *T, const double *rc, double t,
+                         double dt, double *res);
+/* backward Euler step by Newton + restarted GMRES(restart), Jacobi on the right */
+int or_implicit_step_newton(const or_problem *P, const double *Tn, double *rc, double t, double dt,
+                            double lin_rtol, int restart, int lin_max_it, double newton_tol, int newton_max_it,
+                            double *T_out, int *lin_iters_total, int *newton_iters, double *final_rel_res);
 
 /* probes and the adjoint -------------------------------------------------------- */
 int or_probe(const or_problem *P, const double *T, int n, const double *pts, double *vals);
