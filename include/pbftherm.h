@@ -238,6 +238,29 @@ pbf_status pbf_implicit_step(pbf_ctx *ctx, const double *T_n, double *T_out, dou
                              int picard_max_it, int *cg_iters_total, int *picard_iters,
                              double *final_rel_res, void *stream);
 
+/* ---- implicit step by Newton's method (Section 3.2, eqs. Newton_1, Newton_2) ---
+ * The same step and residual as pbf_implicit_step, solved with the full Jacobian
+ *   J(T^i) = C(T_n)/dt + K(T^i) + L(T^i),
+ *   L_ab = sum_q W_q k_T(T^i_q, r_q) N_b(x_q) grad N_a(x_q) . grad T^i(x_q)
+ * (the nonsymmetric term of eq. matrix_free_eval; k_T is dk/dT at fixed
+ * consolidated fraction, the slope of the table segment containing T:
+ * right-continuous at interior breakpoints, zero outside the open table range).
+ * Each Newton system J dT = -R(T^i) is solved from zero by restarted GMRES(restart)
+ * (Arnoldi with classical Gram-Schmidt applied twice, Givens rotations) with
+ * Jacobi on the right, M = diag(C(T_n)/dt + K(T^i)), to ||r|| <= lin_rtol ||b||
+ * (at most lin_max_it Arnoldi steps); Newton stops when max|dT| <= newton_tol
+ * (at most newton_max_it iterations).  Boxes only (PBF_ESTATE on octrees).
+ * work: caller-owned device buffer, 256-byte aligned, of pbf_newton_work_bytes
+ * (restart + 1 Krylov vectors of n_dofs doubles plus reduction scratch);
+ * restart in [1, 63].  Outputs and errors as pbf_implicit_step (PBF_ENOCONV when
+ * a limit is reached, T_out holding the last iterate).  Synchronizes (a few
+ * scalar reads per Arnoldi step). */
+pbf_status pbf_newton_work_bytes(pbf_ctx *ctx, int restart, size_t *bytes);
+pbf_status pbf_implicit_step_newton(pbf_ctx *ctx, const double *T_n, double *T_out, double *rc, double t,
+                                    double dt, double lin_rtol, int restart, int lin_max_it, double newton_tol,
+                                    int newton_max_it, void *work, size_t work_bytes, int *lin_iters_total,
+                                    int *newton_iters, double *final_rel_res, void *stream);
+
 /* ---- probes and objective (Section 3.1, eq. bubnov_galerkin) -----------------
  * pbf_set_probes: n points (host array pts[3n], inside the box) and targets
  * (host array of n, may be NULL for zeros), n in [0, 4096], copied and uploaded

@@ -1401,6 +1401,175 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
     return PBF_OK;
 }
 
+// ---- Newton step with restarted GMRES ----------------------------------------
+
+struct NewtonWork {
+    double *V, *partials, *h1, *h2, *hn, *y;
+};
+
+size_t newton_work_layout(long long N, int restart, char *base, NewtonWork *w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return (double *)p;
+    };
+    NewtonWork t{};
+    t.V = take((size_t)(restart + 1) * N * sizeof(double));
+    t.partials = take((size_t)kRedBlocks * kGmMax * sizeof(double));
+    t.h1 = take(kGmMax * sizeof(double));
+    t.h2 = take(kGmMax * sizeof(double));
+    t.hn = take(kGmMax * sizeof(double));
+    t.y = take(kGmMax * sizeof(double));
+    if (w) *w = t;
+    return off;
+}
+
+pbf_status pbf_newton_work_bytes(pbf_ctx *c, int restart, size_t *bytes)
+{
+    if (!c || !bytes) return fail(c, PBF_EINVAL, "NULL argument");
+    if (!c->has_mesh) return fail(c, PBF_ESTATE, "no mesh");
+    if (restart < 1 || restart > kGmMax - 1) return fail(c, PBF_EINVAL, "restart must be in [1, %d]", kGmMax - 1);
+    *bytes = newton_work_layout(n_dofs(c), restart, nullptr, nullptr);
+    return PBF_OK;
+}
+
+pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out, double *rc, double t, double dt,
+                                    double lin_rtol, int restart, int lin_max_it, double newton_tol,
+                                    int newton_max_it, void *work, size_t work_bytes, int *lin_iters_total,
+                                    int *newton_iters, double *final_rel_res, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (c->octree) return fail(c, PBF_ESTATE, "the Newton step needs a box mesh (use pbf_implicit_step)");
+    if (!T_n || !T_out || T_n == T_out) return fail(c, PBF_EINVAL, "T_n and T_out must be distinct device arrays");
+    if (n_hist_qp(c) > 0 && !rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
+    if (!(dt > 0) || !std::isfinite(t)) return fail(c, PBF_EINVAL, "need dt > 0 and finite t");
+    if (!(lin_rtol > 0) || lin_max_it < 1 || !(newton_tol > 0) || newton_max_it < 1)
+        return fail(c, PBF_EINVAL, "tolerances must be > 0 and iteration limits >= 1");
+    if (restart < 1 || restart > kGmMax - 1) return fail(c, PBF_EINVAL, "restart must be in [1, %d]", kGmMax - 1);
+    const long long N = n_dofs(c);
+    NewtonWork nw{};
+    const size_t need = newton_work_layout(N, restart, (char *)work, &nw);
+    if (!work || work_bytes < need || ((uintptr_t)work & 255))
+        return fail(c, PBF_EINVAL, "work must be a 256-byte aligned device buffer of pbf_newton_work_bytes");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    const HaloParams ge = geometry(c);
+    const HaloParams hp = geometry(c, picard_column_height(), 3);
+    double *y = c->d_cg[0], *diag = c->d_cg[1], *r = c->d_cg[2], *z = c->d_cg[3], *b = c->d_cg[4],
+           *w = c->d_cg[5], *x = c->d_cg[6], *d = c->d_cg[7];
+    double *Ti = T_out, *V = nw.V;
+    PBF_HIP(c, hipMemcpyAsync(Ti, T_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PBF_HIP(c, launch_init_dirichlet(Ti, ge, c->T_D, s));
+    const Beam bm = beam_at(c, t + dt);
+    const bool re = c->re.on != 0;
+    if (re && (st = operator_pass(c, 1, PBF_PREC_FP64, LAW_SURFACE, T_n, nullptr, c->d_f, c->d_C, nullptr, t,
+                                  0.0, s)))
+        return st;
+    const int m = restart;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hc(m + 1), yy(m), h1(kGmMax), h2(kGmMax);
+    auto norm2 = [&](const double *v, double *out) -> pbf_status {  // ||v||, synchronizing
+        PBF_HIP(c, launch_mdot(v, v, 0, 1, nw.partials, nw.hn, N, s));
+        double v2 = 0.0;
+        PBF_HIP(c, hipMemcpyAsync(&v2, nw.hn, sizeof(double), hipMemcpyDeviceToHost, s));
+        PBF_HIP(c, hipStreamSynchronize(s));
+        *out = std::sqrt(v2);
+        return PBF_OK;
+    };
+    int total = 0, it = 0;
+    bool lin_fail = false, converged = false;
+    double last_rel = 0.0;
+    for (it = 0; it < newton_max_it;) {
+        // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_RE(T_n) - f_vol; b = -R
+        PBF_HIP(c, launch_sub(d, Ti, T_n, N, s));
+        if ((st = picard_pass(c, 0, hp, T_n, Ti, d, Ti, y, rc, dt, &bm, s))) return st;
+        if (re) PBF_HIP(c, launch_sub(y, y, c->d_f, N, s));
+        PBF_HIP(c, launch_neg(b, y, N, s));
+        if ((st = picard_pass(c, 1, hp, T_n, Ti, nullptr, nullptr, diag, rc, dt, nullptr, s))) return st;
+        // GMRES(m) from x = 0 on J(T^i) x = b, Jacobi on the right
+        PBF_HIP(c, launch_fill(x, 0.0, N, s));
+        PBF_HIP(c, hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        double bn = 0.0, rn = 0.0;
+        if ((st = norm2(b, &bn))) return st;
+        rn = bn;
+        int k = 0;
+        while (bn > 0 && rn > lin_rtol * bn && k < lin_max_it) {
+            PBF_HIP(c, launch_div_scalar(V, r, rn, N, s));
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = rn;
+            int j;
+            for (j = 0; j < m && k < lin_max_it; ++j) {
+                double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N;
+                PBF_HIP(c, launch_div(z, Vj, diag, N, s));
+                if ((st = picard_pass(c, 2, hp, T_n, Ti, z, z, w, rc, dt, nullptr, s))) return st;
+                // classical Gram-Schmidt, twice
+                PBF_HIP(c, launch_mdot(w, V, N, j + 1, nw.partials, nw.h1, N, s));
+                PBF_HIP(c, launch_maxpy(w, V, N, j + 1, nw.h1, N, s));
+                PBF_HIP(c, launch_mdot(w, V, N, j + 1, nw.partials, nw.h2, N, s));
+                PBF_HIP(c, launch_maxpy(w, V, N, j + 1, nw.h2, N, s));
+                PBF_HIP(c, hipMemcpyAsync(h1.data(), nw.h1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                PBF_HIP(c, hipMemcpyAsync(h2.data(), nw.h2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                double hn = 0.0;
+                if ((st = norm2(w, &hn))) return st;
+                ++k;
+                for (int q = 0; q <= j; ++q) hc[q] = h1[q] + h2[q];
+                if (hn > 0) PBF_HIP(c, launch_div_scalar(Vn, w, hn, N, s));
+                else PBF_HIP(c, launch_fill(Vn, 0.0, N, s));
+                for (int q = 0; q < j; ++q) {  // previous rotations
+                    const double a = cs[q] * hc[q] + sn[q] * hc[q + 1];
+                    hc[q + 1] = -sn[q] * hc[q] + cs[q] * hc[q + 1];
+                    hc[q] = a;
+                }
+                const double den = std::sqrt(hc[j] * hc[j] + hn * hn);
+                cs[j] = den > 0 ? hc[j] / den : 1.0;
+                sn[j] = den > 0 ? hn / den : 0.0;
+                hc[j] = den;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                for (int q = 0; q <= j; ++q) H[(size_t)q * m + j] = hc[q];
+                if (std::fabs(g[j + 1]) <= lin_rtol * bn || hn == 0.0) {
+                    ++j;
+                    break;
+                }
+            }
+            for (int q = j - 1; q >= 0; --q) {  // back substitution
+                double sum = g[q];
+                for (int l = q + 1; l < j; ++l) sum -= H[(size_t)q * m + l] * yy[l];
+                yy[q] = sum / H[(size_t)q * m + q];
+            }
+            PBF_HIP(c, hipMemcpyAsync(nw.y, yy.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+            PBF_HIP(c, launch_gm_update(x, V, N, j, nw.y, diag, N, s));
+            if ((st = picard_pass(c, 2, hp, T_n, Ti, x, x, w, rc, dt, nullptr, s))) return st;
+            PBF_HIP(c, launch_sub(r, b, w, N, s));
+            if ((st = norm2(r, &rn))) return st;
+        }
+        total += k;
+        last_rel = bn > 0 ? rn / bn : 0.0;
+        if (bn > 0 && rn > lin_rtol * bn) lin_fail = true;
+        PBF_HIP(c, launch_picard_update(Ti, x, c->d_partials, c->d_scal, ge, N, s));
+        double dmax = 0.0;
+        PBF_HIP(c, hipMemcpyAsync(&dmax, c->d_scal + CG_DMAX, sizeof(double), hipMemcpyDeviceToHost, s));
+        PBF_HIP(c, hipStreamSynchronize(s));
+        ++it;
+        if (!std::isfinite(dmax)) return fail(c, PBF_ENONFINITE, "non-finite Newton update");
+        if (dmax <= newton_tol) {
+            converged = true;
+            break;
+        }
+    }
+    st = operator_pass(c, 1, PBF_PREC_FP64, LAW_FULL, Ti, nullptr, c->d_f, c->d_C, rc, t + dt, 0.0, s);
+    if (st) return st;
+    if (lin_iters_total) *lin_iters_total = total;
+    if (newton_iters) *newton_iters = it;
+    if (final_rel_res) *final_rel_res = last_rel;
+    if (lin_fail) return fail(c, PBF_ENOCONV, "GMRES did not reach the relative tolerance %g", lin_rtol);
+    if (!converged) return fail(c, PBF_ENOCONV, "Newton did not converge in %d iterations", newton_max_it);
+    return PBF_OK;
+}
+
 pbf_status pbf_set_probes(pbf_ctx *c, int n, const double *pts, const double *targets, void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");

@@ -348,6 +348,18 @@ __device__ __forceinline__ double law_k(L &law, double T, double r)
     return kpl * (r + law.phi * (1.0 - r));
 }
 
+// d k / d T at fixed consolidated fraction r: the slope of the table segment
+// containing T (right-continuous at interior breakpoints, zero outside the
+// open table range), times the phase factor
+template <typename L>
+__device__ __forceinline__ double law_kT(L &law, double T, double r)
+{
+    double s = 0.0;
+    for (int i = 0; i < law.n_hinge; ++i)
+        if (i == 0 ? T > law.b[0] : T >= law.b[i]) s += law.dk[i];
+    return s * (r + law.phi * (1.0 - r));
+}
+
 template <typename L>
 __device__ __forceinline__ double law_c(L &law, double T)
 {

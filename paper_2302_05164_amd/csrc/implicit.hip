@@ -1,7 +1,7 @@
 // Kernels of the implicit backward-Euler step (Section 3.2, eqs.
-// backward_euler_nonlinear, Newton_1, Newton_2) solved with the symmetric
-// Picard matrix A(T^i) = C(T_n)/dt + K(T^i) and Jacobi-preconditioned CG, all
-// matrix-free (Section 4.2, eq. matrix_free_eval without the L_e term):
+// backward_euler_nonlinear, Newton_1, Newton_2): the symmetric Picard matrix
+// A(T^i) = C(T_n)/dt + K(T^i) (Jacobi-preconditioned CG) and the full Newton
+// Jacobian A + L (GMRES), all matrix-free (Section 4.2, eq. matrix_free_eval):
 //   apply:    y = C(Tc) x1 / dt + K(Tk) x2 - s f_vol      (free rows; 0 on Dirichlet rows)
 //   diagonal: diag(A(Tk)) with C(Tc), by sum factorization of squared 1D tables
 // with C_ab = sum_q w detJ rho c(Tc_q) N_a N_b (consistent, apparent capacity)
@@ -20,16 +20,18 @@ namespace {
 
 constexpr int kPTY = 4;  // one wavefront per column workgroup
 
-// MODE 0: apply, MODE 1: diagonal
+// MODE 0: apply, MODE 1: diagonal, MODE 2: Newton Jacobian apply
+// y = C(Tc) x/dt + K(Tk) x + L(Tk) x with the nonsymmetric term
+// L_ab = sum_q W k_T(Tk_q, r_q) N_b grad N_a . grad Tk_q (x1 = x2 = x, no source)
 template <int P, int MODE>
-__global__ void __launch_bounds__(kTX * kPTY) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kTX * kPTY) __attribute__((amdgpu_waves_per_eu(P == 2 && MODE == 2 ? 1 : 2)))
 k_picard(const PicardParams p)
 {
     constexpr int kTY = kPTY, kTPB = kTX * kTY;
     constexpr int N = P + 1, NN = N * N * N;
     constexpr int BX = P * kTX + 1, BY = P * kTY + 1, PLANE = BX * BY, NB = N * PLANE;
     constexpr int NSH = N * N + P * N;
-    constexpr int NV = MODE == 0 ? 4 : 2;  // staged vectors: Tc, Tk (, x1, x2)
+    constexpr int NV = MODE != 1 ? 4 : 2;  // staged vectors: Tc, Tk (, x1, x2)
     using TB = Tables<P>;
     __shared__ double sT[NV][NB];
     __shared__ double sS[NSH * kTPB];
@@ -62,7 +64,7 @@ k_picard(const PicardParams p)
             const long long g = (long long)gi + (long long)q.NX * gj + NXY * (k0 + lk);
             sT[0][idx] = in ? q.Tc[g] : 0.0;
             sT[1][idx] = in ? q.Tk[g] : 0.0;
-            if constexpr (MODE == 0) {
+            if constexpr (MODE != 1) {
                 sT[2][idx] = in ? q.x1[g] : 0.0;
                 sT[3][idx] = in ? q.x2[g] : 0.0;
             }
@@ -101,7 +103,7 @@ k_picard(const PicardParams p)
                 const double r = has_hist ? q.hist[(long long)qq * q.n_hist_cells + hc] : 1.0;
                 kw[qq] = wq * q.detJ * law_k(law, kw[qq], r);
             });
-            if constexpr (MODE == 0) {
+            if constexpr (MODE != 1) {
                 // mass part: m_q * x1_q, minus the source, as the value integrand
                 gather(2, u);
                 sweep<TagS<P>, N, 0>(u, t1);
@@ -109,7 +111,7 @@ k_picard(const PicardParams p)
                 sweep<TagS<P>, N, 2>(t2, u);
 #pragma unroll
                 for (int a = 0; a < NN; ++a) m[a] *= u[a];
-                if (q.src_on && q.laser_kind == 1 && cz >= q.src_cz0) {
+                if (MODE == 0 && q.src_on && q.laser_kind == 1 && cz >= q.src_cz0) {
                     sfor<0, NN>([&](auto qc) {
                         constexpr int qq = decltype(qc)::value;
                         constexpr int qx = qq % N, qy = (qq / N) % N, qz = qq / (N * N);
@@ -144,9 +146,37 @@ k_picard(const PicardParams p)
                         if constexpr (dz != 0.0) m[tidx<N, 2>(r, qx, qy)] = __builtin_fma(dz, Fz, m[tidx<N, 2>(r, qx, qy)]);
                     });
                 });
+                if constexpr (MODE == 2) {
+                    // nonsymmetric term: + D^T (W k_T(Tk_q, r_q) x_q h^-2 grad Tk_q), with the
+                    // point values of Tk recomputed into kw (no longer needed) and x in u
+                    gather(1, kw);
+                    sweep<TagS<P>, N, 0>(kw, t1);
+                    sweep<TagS<P>, N, 1>(t1, t2);
+                    sweep<TagS<P>, N, 2>(t2, kw);
+                    sfor<0, NN>([&](auto qc) {
+                        constexpr int qq = decltype(qc)::value;
+                        constexpr int qx = qq % N, qy = (qq / N) % N, qz = qq / (N * N);
+                        constexpr double wq = TB::gw(qx) * TB::gw(qy) * TB::gw(qz);
+                        const double r = has_hist ? q.hist[(long long)qq * q.n_hist_cells + hc] : 1.0;
+                        const double kd = wq * q.detJ * law_kT(law, kw[qq], r) * u[qq];
+                        auto gxf = [&](auto rc) { return kw[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
+                        auto gyf = [&](auto rc) { return kw[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
+                        auto gzf = [&](auto rc) { return kw[tidx<N, 2>(decltype(rc)::value, qx, qy)]; };
+                        const double Fx = kd * q.ih2x * rowdot<TagD<P>, qx, 0, N, false>(gxf, 0.0);
+                        const double Fy = kd * q.ih2y * rowdot<TagD<P>, qy, 0, N, false>(gyf, 0.0);
+                        const double Fz = kd * q.ih2z * rowdot<TagD<P>, qz, 0, N, false>(gzf, 0.0);
+                        sfor<0, N>([&](auto rc) {
+                            constexpr int r2 = decltype(rc)::value;
+                            constexpr double dx = TB::D(qx, r2), dy = TB::D(qy, r2), dz = TB::D(qz, r2);
+                            if constexpr (dx != 0.0) m[tidx<N, 0>(r2, qy, qz)] = __builtin_fma(dx, Fx, m[tidx<N, 0>(r2, qy, qz)]);
+                            if constexpr (dy != 0.0) m[tidx<N, 1>(r2, qx, qz)] = __builtin_fma(dy, Fy, m[tidx<N, 1>(r2, qx, qz)]);
+                            if constexpr (dz != 0.0) m[tidx<N, 2>(r2, qx, qy)] = __builtin_fma(dz, Fz, m[tidx<N, 2>(r2, qx, qy)]);
+                        });
+                    });
+                }
                 integrate3<TagSt<P>, TagSt<P>, TagSt<P>, N>(m, fe);
                 // Gaussian surface flux on the top face, subtracted like the volume source
-                if (q.src_on && q.laser_kind == 0 && cz == q.nz - 1) {
+                if (MODE == 0 && q.src_on && q.laser_kind == 0 && cz == q.nz - 1) {
                     sfor<0, N>([&](auto ac) {
                         constexpr int ax = decltype(ac)::value;
                         sfor<0, N>([&](auto bc) {
@@ -187,7 +217,7 @@ k_picard(const PicardParams p)
                                 q.NX, q.NY, q.NZ, q.slots + tpar * NT, NXY,
                                 [&](long long g, int gi, int gj, int gk, int, int, int, double f) {
                 const bool dir = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ);
-                q.yout[g] = dir ? (MODE == 0 ? 0.0 : 1.0) : f;
+                q.yout[g] = dir ? (MODE != 1 ? 0.0 : 1.0) : f;
             });
         }
         __syncthreads();
@@ -217,17 +247,19 @@ hipError_t launch_picard(int degree, int mode, const PicardParams &pp, const Hal
     const dim3 grid(8 * pp.tiles_per_xcd), block(kTX * kPTY);
     if (degree == 1) {
         if (mode == 0) hipLaunchKernelGGL((k_picard<1, 0>), grid, block, 0, s, pp);
-        else hipLaunchKernelGGL((k_picard<1, 1>), grid, block, 0, s, pp);
+        else if (mode == 1) hipLaunchKernelGGL((k_picard<1, 1>), grid, block, 0, s, pp);
+        else hipLaunchKernelGGL((k_picard<1, 2>), grid, block, 0, s, pp);
     } else {
         if (mode == 0) hipLaunchKernelGGL((k_picard<2, 0>), grid, block, 0, s, pp);
-        else hipLaunchKernelGGL((k_picard<2, 1>), grid, block, 0, s, pp);
+        else if (mode == 1) hipLaunchKernelGGL((k_picard<2, 1>), grid, block, 0, s, pp);
+        else hipLaunchKernelGGL((k_picard<2, 2>), grid, block, 0, s, pp);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long n = hp.GX + hp.GY + hp.GZ;
     if (n == 0) return hipSuccess;
     const dim3 g2((unsigned)((n + 255) / 256)), b2(256);
-    if (mode == 0) hipLaunchKernelGGL(k_picard_halo<0>, g2, b2, 0, s, hp, pp.yout);
+    if (mode != 1) hipLaunchKernelGGL(k_picard_halo<0>, g2, b2, 0, s, hp, pp.yout);
     else hipLaunchKernelGGL(k_picard_halo<1>, g2, b2, 0, s, hp, pp.yout);
     return hipGetLastError();
 }

@@ -260,6 +260,17 @@ hipError_t launch_cg_direction(double *p, const double *z, const double *scal, i
 hipError_t launch_picard_update(double *Ti, const double *x, double *partials, double *scal,
                                 const HaloParams &geom, long long n, hipStream_t s);
 hipError_t launch_sub(double *d, const double *a, const double *b, long long n, hipStream_t s);
+// GMRES vector kernels (deterministic reductions); at most kGmMax Krylov vectors
+constexpr int kGmMax = 64;
+hipError_t launch_mdot(const double *w, const double *V, long long ldv, int k, double *partials, double *out,
+                       long long n, hipStream_t s);
+hipError_t launch_maxpy(double *w, const double *V, long long ldv, int k, const double *h, long long n,
+                        hipStream_t s);
+hipError_t launch_gm_update(double *x, const double *V, long long ldv, int k, const double *y, const double *diag,
+                            long long n, hipStream_t s);
+hipError_t launch_div(double *z, const double *v, const double *d, long long n, hipStream_t s);
+hipError_t launch_div_scalar(double *v, const double *w, double h, long long n, hipStream_t s);
+hipError_t launch_neg(double *b, const double *y, long long n, hipStream_t s);
 
 // discrete adjoint (adjoint.hip)
 int adjoint_column_height();

@@ -274,9 +274,112 @@ __global__ void k_power_scale(double *v, const double *scal, long long n)
     if (i < n) v[i] = v[i] / sqrt(scal[2]);
 }
 
+// ---- GMRES (restarted, classical Gram-Schmidt twice, Jacobi on the right) ----
+constexpr int kMdotChunk = 16;  // Krylov vectors per multi-dot pass
+
+// partials[b * kGmMax + i0 + i] = block b's part of w . V_{i0+i}, i < kc <= kMdotChunk
+__global__ void __launch_bounds__(kRedThreads) k_mdot(const double *w, const double *V, long long ldv, int i0,
+                                                       int kc, double *partials, long long n)
+{
+    double s[kMdotChunk];
+#pragma unroll
+    for (int i = 0; i < kMdotChunk; ++i) s[i] = 0.0;
+    for (long long j = (long long)blockIdx.x * kRedThreads + threadIdx.x; j < n;
+         j += (long long)gridDim.x * kRedThreads) {
+        const double wj = w[j];
+#pragma unroll
+        for (int i = 0; i < kMdotChunk; ++i)
+            if (i < kc) s[i] += wj * V[(long long)(i0 + i) * ldv + j];
+    }
+    block_sum<kMdotChunk>(s);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kc; ++i) partials[(long long)blockIdx.x * kGmMax + i0 + i] = s[i];
+}
+
+// w -= sum_{i<k} h_i V_i, the products subtracted in order of i
+__global__ void k_maxpy(double *w, const double *V, long long ldv, int k, const double *h, long long n)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double wj = w[j];
+    for (int i = 0; i < k; ++i) wj -= h[i] * V[(long long)i * ldv + j];
+    w[j] = wj;
+}
+
+// x += (sum_{i<k} y_i V_i) / diag
+__global__ void k_gm_update(double *x, const double *V, long long ldv, int k, const double *y, const double *diag,
+                            long long n)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += y[i] * V[(long long)i * ldv + j];
+    x[j] += s / diag[j];
+}
+
+__global__ void k_div(double *z, const double *v, const double *d, long long n)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) z[j] = v[j] / d[j];
+}
+
+__global__ void k_div_scalar(double *v, const double *w, double h, long long n)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) v[j] = w[j] / h;
+}
+
+__global__ void k_neg(double *b, const double *y, long long n)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) b[j] = -y[j];
+}
+
 inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+hipError_t launch_mdot(const double *w, const double *V, long long ldv, int k, double *partials, double *out,
+                       long long n, hipStream_t s)
+{
+    for (int i0 = 0; i0 < k; i0 += kMdotChunk)
+        hipLaunchKernelGGL(k_mdot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, w, V, ldv, i0,
+                           k - i0 < kMdotChunk ? k - i0 : kMdotChunk, partials, n);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, kGmMax, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpy(double *w, const double *V, long long ldv, int k, const double *h, long long n,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_maxpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, V, ldv, k, h, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gm_update(double *x, const double *V, long long ldv, int k, const double *y, const double *diag,
+                            long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, V, ldv, k, y, diag, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_div(double *z, const double *v, const double *d, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_div, dim3(blocks_for(n, 256)), dim3(256), 0, s, z, v, d, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_div_scalar(double *v, const double *w, double h, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_div_scalar, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, w, h, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_neg(double *b, const double *y, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_neg, dim3(blocks_for(n, 256)), dim3(256), 0, s, b, y, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill(double *x, double v, long long n, hipStream_t s)
 {

@@ -83,6 +83,10 @@ SIGNATURES = {
     "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
     "pbf_implicit_step": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int,
                           C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _vp],
+    "pbf_newton_work_bytes": [_vp, C.c_int, C.POINTER(C.c_size_t)],
+    "pbf_implicit_step_newton": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                 C.c_double, C.c_int, _vp, C.c_size_t, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_double), _vp],
     "pbf_set_probes": [_vp, C.c_int, _dp, _dp, _vp],
     "pbf_probe": [_vp, _vp, _vp, _vp],
     "pbf_objective": [_vp, _vp, _vp, _vp, _vp],
@@ -294,6 +298,30 @@ class Simulation:
         self._check(self.lib.pbf_stability_lambda(self.ctx, _f64(v0, i["n_dofs"], "v0"), int(iters),
                                                   C.byref(lam), self._stream()))
         return lam.value
+
+    def newton_work(self, restart=30):
+        """Device buffer for implicit_step_newton with the given GMRES restart length."""
+        nb = C.c_size_t()
+        self._check(self.lib.pbf_newton_work_bytes(self.ctx, int(restart), C.byref(nb)))
+        buf, addr = _aligned(nb.value, self.device)
+        return {"buf": buf, "addr": addr, "bytes": nb.value, "restart": int(restart)}
+
+    def implicit_step_newton(self, T_n, rc, t, dt, lin_rtol=1e-10, restart=30, lin_max_it=10000, newton_tol=1e-8,
+                             newton_max_it=30, T_out=None, work=None, check=True):
+        i = self.info()
+        if work is None or work["restart"] != restart:
+            work = self.newton_work(restart)
+        if T_out is None:
+            T_out = torch.empty_like(T_n)
+        it, nit, res = C.c_int(0), C.c_int(0), C.c_double(0)
+        st = self.lib.pbf_implicit_step_newton(
+            self.ctx, _f64(T_n, i["n_dofs"], "T_n"), _f64(T_out, i["n_dofs"], "T_out"),
+            _ptr(rc) if i["n_hist_qp"] else None, float(t), float(dt), float(lin_rtol), int(restart),
+            int(lin_max_it), float(newton_tol), int(newton_max_it), C.c_void_p(work["addr"]), work["bytes"],
+            C.byref(it), C.byref(nit), C.byref(res), self._stream())
+        if check:
+            self._check(st)
+        return T_out, dict(status=st, lin_iters=it.value, newton_iters=nit.value, rel_res=res.value)
 
     def implicit_step(self, T_n, rc, t, dt, cg_rtol=1e-10, cg_max_it=10000, picard_tol=1e-8,
                       picard_max_it=30, T_out=None, check=True):
