@@ -87,7 +87,7 @@ def pmc_summary(fetch_dir, write_dir, out_path, workload, kernel="k_cells<2, dou
             rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == name]
         return rows
 
-    run = ("python3 <repo>/bench.py --steps 30 --warmup 5 --no-cpu --no-fp32 --no-adjoint --calib-copy")
+    run = ("python3 <repo>/bench.py --steps 30 --warmup 5 --no-cpu --no-fp32 --no-adjoint --no-implicit --calib-copy")
     res = {"workload": workload, "kernel": kernel, "kernel_source_sha256_16": kernel_source_hash(),
            "commands": ["cd /tmp && export TMPDIR=/tmp",
                         f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/fetch -o run -- {run}",
@@ -182,6 +182,37 @@ def adjoint_timing(reps=1):
             "dJdA": g["dJdA"].item(), "dJdP_norm": float(torch.linalg.norm(g["dJdP"]).item())}
 
 
+def implicit_timing(sim, T, rc, t, dt=1e-4):
+    """One backward-Euler step of dt from the end state of the explicit run,
+    solved by Picard iterations with Jacobi-CG and by Newton's method with
+    restarted GMRES(30) (relative residual 1e-10 per linear system, 1e-8 K on
+    the update); wall time on the library's stream, iteration counts."""
+    import torch
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), out
+
+    work = sim.newton_work(30)
+    res = {"dt": dt}
+    r1 = rc.clone()
+    ms, (Tp, ip) = timed(lambda: sim.implicit_step(T, r1, t, dt, cg_rtol=1e-10, picard_tol=1e-8, picard_max_it=60))
+    res["picard_cg"] = {"ms": ms, "outer": ip["picard_iters"], "krylov": ip["cg_iters"],
+                        "ms_per_krylov": ms / max(1, ip["cg_iters"])}
+    r2 = rc.clone()
+    ms, (Tn, inw) = timed(lambda: sim.implicit_step_newton(T, r2, t, dt, lin_rtol=1e-10, restart=30,
+                                                           newton_tol=1e-8, newton_max_it=60, work=work))
+    res["newton_gmres"] = {"ms": ms, "outer": inw["newton_iters"], "krylov": inw["lin_iters"],
+                           "ms_per_krylov": ms / max(1, inw["lin_iters"]), "work_bytes": work["bytes"]}
+    res["max_abs_diff_K"] = float((Tp - Tn).abs().max().item())
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +222,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-operator timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-step timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -244,6 +276,8 @@ def main():
         finite = bool(torch.isfinite(T).all().item())
         results[prec] = dict(ms=ms, cell_ms=cell_ms, face_ms=face_ms, n=nt, finite=finite,
                              Tmax=float(T.max().item()))
+        if prec == 64:
+            end_state = (T.clone(), rc.clone())
         del T, rc, T_tmp
 
     n = info["n_dofs"]
@@ -297,6 +331,9 @@ def main():
                                 "ms_per_step": r32["ms"] / args.steps,
                                 "speedup_vs_fp64": v32 / value,
                                 "kernel_ms": r32["cell_ms"], "finite": r32["finite"]}
+    if not args.no_implicit:
+        out["implicit"] = implicit_timing(sim, *end_state, (args.warmup + args.steps) * dt)
+    del end_state
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
     if not args.no_cpu:
