@@ -50,6 +50,7 @@ struct pbf_ctx {
     double *d_f = nullptr, *d_C = nullptr, *d_v = nullptr, *d_partials = nullptr, *d_scal = nullptr;
     double *d_cg[8] = {};  // implicit step: y, diag, r, z, p, Ap, x, d
     double *d_tiles = nullptr;  // adjoint: per-tile source sensitivities
+    double *d_coef = nullptr;   // implicit step (boxes): per-point coefficients of the CG applies
     int *d_probe_cell = nullptr;
     double *d_probe_xi = nullptr, *d_probe_target = nullptr;
     bool laws_dirty = true;
@@ -1148,6 +1149,14 @@ pbf_status pbf_set_track_powers(pbf_ctx *c, const double *power, double absorpti
     return PBF_OK;
 }
 
+// doubles of the CG-apply coefficient cache (boxes; octrees apply on the fly)
+size_t picard_coef_count(const pbf_ctx *c)
+{
+    if (c->octree) return 0;
+    const size_t nq = (size_t)(c->degree + 1) * (c->degree + 1) * (c->degree + 1);
+    return (size_t)kCoefPicard * nq * (size_t)c->nx * c->ny * c->nz;
+}
+
 pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "NULL argument");
@@ -1161,6 +1170,7 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     b += align256(64 * sizeof(double));           // device scalars
     b += align256(adjoint_tiles(c) * sizeof(double));  // adjoint tile partials
     b += align256(3 * kMaxProbes * sizeof(int)) + align256(4 * kMaxProbes * sizeof(double));
+    b += align256(picard_coef_count(c) * sizeof(double));  // CG-apply coefficient cache (boxes)
     b += oct_tables(const_cast<pbf_ctx *>(c), nullptr);  // octree tables and element buffer
     *bytes = b;
     return PBF_OK;
@@ -1208,6 +1218,8 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     c->d_probe_xi = (double *)p;
     c->d_probe_target = c->d_probe_xi + 3 * kMaxProbes;
     p += align256(4 * kMaxProbes * sizeof(double));
+    c->d_coef = (double *)p;
+    p += align256(picard_coef_count(c) * sizeof(double));
     c->probes_dirty = !c->probe_target.empty();
     if (c->octree) {
         compute_history_layers(c);  // Dirichlet flags and history leaves for the current setup
@@ -1358,6 +1370,12 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
         if ((st = picard_pass(c, 0, hp, T_n, Ti, d, Ti, y, rc, dt, &bm, s))) return st;
         if (re) PBF_HIP(c, launch_sub(y, y, c->d_f, N, s));
         if ((st = picard_pass(c, 1, hp, T_n, Ti, nullptr, nullptr, diag, rc, dt, nullptr, s))) return st;
+        if (!c->octree) {  // per-point coefficients of this iteration's CG applies
+            PicardParams pc = picard_params(c, ge, T_n, Ti, nullptr, nullptr, nullptr, rc, dt, nullptr);
+            pc.coef = c->d_coef;
+            pc.ncells = (long long)c->nx * c->ny * c->nz;
+            PBF_HIP(c, launch_picard_coef(c->degree, false, pc, s));
+        }
         PBF_HIP(c, launch_cg_start(y, diag, r, z, p, x, c->d_partials, c->d_scal, ge, N, s));
         PBF_HIP(c, hipMemcpyAsync(hs, c->d_scal + CG_RZ0, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
         PBF_HIP(c, hipStreamSynchronize(s));
@@ -1366,7 +1384,14 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
         int k = 0, rz_old = CG_RZ0;
         last_rel = bn > 0 ? std::sqrt(rr) / bn : 0.0;
         while (bn > 0 && std::sqrt(rr) > cg_rtol * bn && k < cg_max_it) {
-            if ((st = picard_pass(c, 0, hp, T_n, Ti, p, p, Ap, rc, dt, nullptr, s))) return st;
+            if (c->octree) {
+                if ((st = picard_pass(c, 0, hp, T_n, Ti, p, p, Ap, rc, dt, nullptr, s))) return st;
+            } else {
+                PicardParams pa = picard_params(c, ge, T_n, Ti, p, p, Ap, rc, dt, nullptr);
+                pa.coef = c->d_coef;
+                pa.ncells = (long long)c->nx * c->ny * c->nz;
+                PBF_HIP(c, launch_picard_capply(c->degree, false, pa, ge, s));
+            }
             PBF_HIP(c, launch_cg_pap(p, Ap, c->d_partials, c->d_scal, N, s));
             PBF_HIP(c, launch_cg_update(x, r, z, p, Ap, diag, c->d_partials, c->d_scal, rz_old, N, s));
             PBF_HIP(c, hipMemcpyAsync(&rr, c->d_scal + CG_RR, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1404,10 +1429,10 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
 // ---- Newton step with restarted GMRES ----------------------------------------
 
 struct NewtonWork {
-    double *V, *partials, *h1, *h2, *hn, *y;
+    double *V, *partials, *h1, *h2, *hn, *y, *coef;
 };
 
-size_t newton_work_layout(long long N, int restart, char *base, NewtonWork *w)
+size_t newton_work_layout(long long N, long long ncoef, int restart, char *base, NewtonWork *w)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1422,8 +1447,15 @@ size_t newton_work_layout(long long N, int restart, char *base, NewtonWork *w)
     t.h2 = take(kGmMax * sizeof(double));
     t.hn = take(kGmMax * sizeof(double));
     t.y = take(kGmMax * sizeof(double));
+    t.coef = take((size_t)ncoef * sizeof(double));
     if (w) *w = t;
     return off;
+}
+
+long long newton_coef_count(const pbf_ctx *c)
+{
+    const long long nq = (long long)(c->degree + 1) * (c->degree + 1) * (c->degree + 1);
+    return c->octree ? 0 : (long long)kCoefNewton * nq * c->nx * c->ny * c->nz;
 }
 
 pbf_status pbf_newton_work_bytes(pbf_ctx *c, int restart, size_t *bytes)
@@ -1431,7 +1463,7 @@ pbf_status pbf_newton_work_bytes(pbf_ctx *c, int restart, size_t *bytes)
     if (!c || !bytes) return fail(c, PBF_EINVAL, "NULL argument");
     if (!c->has_mesh) return fail(c, PBF_ESTATE, "no mesh");
     if (restart < 1 || restart > kGmMax - 1) return fail(c, PBF_EINVAL, "restart must be in [1, %d]", kGmMax - 1);
-    *bytes = newton_work_layout(n_dofs(c), restart, nullptr, nullptr);
+    *bytes = newton_work_layout(n_dofs(c), newton_coef_count(c), restart, nullptr, nullptr);
     return PBF_OK;
 }
 
@@ -1452,7 +1484,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
     if (restart < 1 || restart > kGmMax - 1) return fail(c, PBF_EINVAL, "restart must be in [1, %d]", kGmMax - 1);
     const long long N = n_dofs(c);
     NewtonWork nw{};
-    const size_t need = newton_work_layout(N, restart, (char *)work, &nw);
+    const size_t need = newton_work_layout(N, newton_coef_count(c), restart, (char *)work, &nw);
     if (!work || work_bytes < need || ((uintptr_t)work & 255))
         return fail(c, PBF_EINVAL, "work must be a 256-byte aligned device buffer of pbf_newton_work_bytes");
     hipStream_t s = (hipStream_t)stream;
@@ -1489,6 +1521,17 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
         if (re) PBF_HIP(c, launch_sub(y, y, c->d_f, N, s));
         PBF_HIP(c, launch_neg(b, y, N, s));
         if ((st = picard_pass(c, 1, hp, T_n, Ti, nullptr, nullptr, diag, rc, dt, nullptr, s))) return st;
+        PicardParams pj = picard_params(c, ge, T_n, Ti, nullptr, nullptr, nullptr, rc, dt, nullptr);
+        pj.coef = nw.coef;
+        pj.ncells = (long long)c->nx * c->ny * c->nz;
+        PBF_HIP(c, launch_picard_coef(c->degree, true, pj, s));
+        auto japply = [&](const double *xin, double *yout) -> pbf_status {  // y = J(T^i) x, cached
+            PicardParams pa = pj;
+            pa.x1 = pa.x2 = xin;
+            pa.yout = yout;
+            PBF_HIP(c, launch_picard_capply(c->degree, true, pa, ge, s));
+            return PBF_OK;
+        };
         // GMRES(m) from x = 0 on J(T^i) x = b, Jacobi on the right
         PBF_HIP(c, launch_fill(x, 0.0, N, s));
         PBF_HIP(c, hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1504,7 +1547,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
             for (j = 0; j < m && k < lin_max_it; ++j) {
                 double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N;
                 PBF_HIP(c, launch_div(z, Vj, diag, N, s));
-                if ((st = picard_pass(c, 2, hp, T_n, Ti, z, z, w, rc, dt, nullptr, s))) return st;
+                if ((st = japply(z, w))) return st;
                 // classical Gram-Schmidt, twice
                 PBF_HIP(c, launch_mdot(w, V, N, j + 1, nw.partials, nw.h1, N, s));
                 PBF_HIP(c, launch_maxpy(w, V, N, j + 1, nw.h1, N, s));
@@ -1542,7 +1585,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
             }
             PBF_HIP(c, hipMemcpyAsync(nw.y, yy.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
             PBF_HIP(c, launch_gm_update(x, V, N, j, nw.y, diag, N, s));
-            if ((st = picard_pass(c, 2, hp, T_n, Ti, x, x, w, rc, dt, nullptr, s))) return st;
+            if ((st = japply(x, w))) return st;
             PBF_HIP(c, launch_sub(r, b, w, N, s));
             if ((st = norm2(r, &rn))) return st;
         }

@@ -147,6 +147,11 @@ struct PicardParams {
     int src_on, laser_kind, src_cz0;
     double xb, yb, src_amp, two_over_R2, h_powder;
     const Law<double> *law;
+    // per-point coefficient cache of the Krylov applies, [component][point][cell]:
+    // 0 capacity weight W rho c(Tc)/dt, 1 conductivity weight W k(Tk, r); Newton
+    // also 2 W k_T(Tk, r) and 3..5 the reference gradient of Tk
+    double *coef;
+    long long ncells;
 };
 
 // Parameters of the adjoint cell kernel (reverse of one explicit step).
@@ -226,6 +231,13 @@ hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s, hipEvent_t
 int picard_column_height();
 hipError_t launch_picard(int degree, int mode, const PicardParams &pp, const HaloParams &hp,
                          hipStream_t s);
+// per-point coefficients of the Krylov applies (once per Picard/Newton iteration)
+hipError_t launch_picard_coef(int degree, bool newton, const PicardParams &pp, hipStream_t s);
+// y = C(Tc) x/dt + K(Tk) x (+ L(Tk) x) from the cached coefficients; pp and hp in
+// the explicit-kernel geometry (16 x 16 cell columns)
+hipError_t launch_picard_capply(int degree, bool newton, const PicardParams &pp, const HaloParams &hp,
+                                hipStream_t s);
+constexpr int kCoefPicard = 2, kCoefNewton = 6;  // cached components
 // vector kernels (vec.hip)
 hipError_t launch_fill(double *x, double v, long long n, hipStream_t s);
 hipError_t launch_init_dirichlet(double *T, const HaloParams &geom, double T_D, hipStream_t s);
