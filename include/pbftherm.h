@@ -112,9 +112,33 @@ pbf_status pbf_octree_remesh(pbf_ctx *ctx, void *workspace, size_t bytes, const 
 pbf_status pbf_dof_coords(const pbf_ctx *ctx, double *xyz);
 
 /* Sizes of the current mesh; any output pointer may be NULL.  n_hist_* depend
- * on the powder depth of the material and are 0 before pbf_set_material. */
+ * on the powder depth of the material and are 0 before pbf_set_material.  On a
+ * growing box (pbf_set_active_layers) these are the sizes of the whole box,
+ * i.e. the lengths of the state arrays T and rc. */
 pbf_status pbf_mesh_info(const pbf_ctx *ctx, int64_t *n_dofs, int64_t *n_cells, int64_t *n_qp,
                          int64_t *n_hist_layers, int64_t *n_hist_cells, int64_t *n_hist_qp);
+
+/* ---- growing domain (Section 4.1, layer activation; initial condition of Section 2)
+ * A box of nx x ny x nz cells (pbf_mesh_box) of which the bottom nz_active cell
+ * layers are active: the domain grows layer by layer, the nodes and cells above
+ * the active top carry no DoFs, and the top face of the active cells is the free
+ * surface (laser source, surface losses).  Because z is the slowest index the
+ * active DoFs are a prefix of the state arrays; every stepping, assembly and
+ * diagnostic call works on the active part only.  Call pbf_set_active_layers
+ * after pbf_mesh_box and before pbf_bind_device (workspace and state arrays are
+ * sized for the whole box; nz_active in [1, nz]).  The consolidated fraction is
+ * stored for every cell of the box (point-major, n_hist_cells = nx ny nz), so
+ * buried powder keeps its history.  pbf_activate_layers(nz_new) activates the
+ * layers nz_active .. nz_new-1: their new nodes start at T0 (the initial
+ * condition holds for parts activated later), their Gauss points within the
+ * powder depth of the new top start as powder (r = 0), others at 1; older cells
+ * keep their history.  Errors: PBF_ESTATE on octrees, after binding
+ * (pbf_set_active_layers) or on a box that does not grow (pbf_activate_layers);
+ * PBF_EINVAL for nz_new outside (nz_active, nz].  The adjoint entry points
+ * refuse a growing box. */
+pbf_status pbf_set_active_layers(pbf_ctx *ctx, int nz_active);
+pbf_status pbf_active_info(const pbf_ctx *ctx, int *nz_active, int64_t *n_active_dofs, double *Lz_active);
+pbf_status pbf_activate_layers(pbf_ctx *ctx, int nz_new, double T0, double *T, double *rc, void *stream);
 
 /* ---- boundary conditions (Section 2, eqs. bc_dirichlet, bc_neumann) ---------
  * Bit f of face_mask makes face f Dirichlet at T_D (bits 0..5: x-, x+, y-, y+,

@@ -77,6 +77,7 @@ def lib():
         L.or_surface_loss.restype = C.c_double
         L.or_surface_loss_vector.argtypes = [P, _dp, _dp]
         L.or_jacobian_apply.argtypes = [P, _dp, _dp, _dp, C.c_double, _dp, _dp]
+        L.or_activate_layers.argtypes = [P, C.c_int, C.c_int, C.c_double, _dp, _dp]
         L.or_picard_apply.argtypes = [P, _dp, _dp, _dp, C.c_double, _dp, _dp]
         L.or_implicit_residual.argtypes = [P, _dp, _dp, _dp, C.c_double, C.c_double, _dp]
         L.or_implicit_step_newton.argtypes = [P, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
@@ -219,6 +220,10 @@ class Oracle:
     def explicit_steps(self, T, rc, t0, dt, n):
         self.L.or_explicit_steps(C.byref(self.s), _ptr(T), _ptr(rc), t0, dt, n)
         return T
+
+    def activate_layers(self, nz_old, nz_new, T0, T, rc):
+        """On the whole box: layers nz_old..nz_new-1 become active (T0, new powder), in place."""
+        self.L.or_activate_layers(C.byref(self.s), int(nz_old), int(nz_new), float(T0), _ptr(T), _ptr(rc))
 
     def surface_loss_vector(self, T):
         """f_RE(T): the radiation and evaporation terms alone, assembled."""

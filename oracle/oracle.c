@@ -353,6 +353,33 @@ void or_init_history(const or_problem *P, double *rc)
     free(R);
 }
 
+/* Layer activation (Section 4.1) on a box P whose bottom nz_old cell layers are
+ * active: layers nz_old .. nz_new-1 become active.  Their new nodes (planes
+ * degree*nz_old+1 .. degree*nz_new) start at T0 (Section 2: parts activated
+ * later start at the initial temperature); their Gauss points within
+ * powder_depth of the new top z = nz_new hz start as powder (r = 0), the others
+ * at 1 (eq. consolidated_fraction, initial state).  T and rc cover the whole box
+ * (rc cell-major); older cells keep their history. */
+void or_activate_layers(const or_problem *P, int nz_old, int nz_new, double T0, double *T, double *rc)
+{
+    ref_elem *R = (ref_elem *)malloc(sizeof(ref_elem));
+    or_make_ref(P->degree, R);
+    double hz = P->Lz / P->nz, Lz_new = nz_new * hz;
+    int64_t NXY = NX(P) * NY(P);
+    for (int64_t i = NXY * ((int64_t)P->degree * nz_old + 1); i < NXY * ((int64_t)P->degree * nz_new + 1); ++i)
+        T[i] = T0;
+    for (int cz = nz_old; cz < nz_new; ++cz)
+        for (int cy = 0; cy < P->ny; ++cy)
+            for (int cx = 0; cx < P->nx; ++cx) {
+                int64_t cell = cx + (int64_t)P->nx * (cy + (int64_t)P->ny * cz);
+                for (int q = 0; q < R->nq; ++q) {
+                    double z = (cz + R->xi[q][2]) * hz;
+                    rc[cell * R->nq + q] = (Lz_new - z <= P->powder_depth) ? 0.0 : 1.0;
+                }
+            }
+    free(R);
+}
+
 /* ------------------------------------------------------------------------- */
 /* element evaluation (eq. diffusive_term_evaluation, weak_form)              */
 /* ------------------------------------------------------------------------- */

@@ -54,6 +54,8 @@ double or_capacity(const or_problem *P, double T);
 int or_beam(const or_problem *P, double t, double *xb, double *yb, double *W, int *track);
 double or_volume_source(const or_problem *P, double x, double y, double z, double t);
 double or_surface_source(const or_problem *P, double x, double y, double t);
+/* layer activation on the whole box P: layers nz_old..nz_new-1 (T to T0, new powder) */
+void or_activate_layers(const or_problem *P, int nz_old, int nz_new, double T0, double *T, double *rc);
 /* outward heat flux density q_rad + q_evap through the free surface at T */
 double or_surface_loss(const or_problem *P, double T);
 /* f_RE(T): the surface-loss terms alone, assembled (zero when they are off) */

@@ -58,6 +58,11 @@ struct pbf_ctx {
     std::vector<int> probe_cell;
     std::vector<double> probe_xi, probe_target;
     bool probes_dirty = false;
+    // growing box (layer activation): nz and L[2] are the active cell layers and
+    // height; nz_full and Lz_full the allocated box (state arrays, workspace)
+    bool growing = false;
+    int nz_full = 0;
+    double Lz_full = 0.0;
     // octree mesh (when octree is set, nx, ny, nz are the coarse cells)
     bool octree = false;
     bool oct_flags_dirty = false;  // Dirichlet flags / history leaves changed since the upload
@@ -125,7 +130,18 @@ long long n_cells(const pbf_ctx *c) { return c->octree ? c->oct.n_cells : (long 
 int nq1(const pbf_ctx *c) { return c->degree + 1; }
 long long n_hist_cells(const pbf_ctx *c)
 {
+    if (c->growing) return (long long)c->nx * c->ny * c->nz_full;  // every layer may start as powder
     return c->octree ? c->oct.n_hist_cells : (long long)c->nx * c->ny * c->hist_layers;
+}
+// sizes of the state arrays and workspace: the whole box when it grows
+long long alloc_dofs(const pbf_ctx *c)
+{
+    if (!c->growing) return n_dofs(c);
+    return nodes1(c, 0) * nodes1(c, 1) * ((long long)c->degree * c->nz_full + 1);
+}
+long long alloc_cells(const pbf_ctx *c)
+{
+    return c->growing ? (long long)c->nx * c->ny * c->nz_full : n_cells(c);
 }
 long long n_hist_qp(const pbf_ctx *c)
 {
@@ -149,6 +165,10 @@ void compute_history_layers(pbf_ctx *c)
     c->powder_levels.clear();
     if (c->octree && c->has_mesh) {
         oct_finish(c->oct, c->dmask, c->has_material ? c->powder_depth : -1.0);
+        return;
+    }
+    if (c->growing) {  // history for every layer (point-major over the whole box, from layer 0)
+        c->hist_layers = c->nz;
         return;
     }
     if (!c->has_mesh || !c->has_material) return;
@@ -1015,12 +1035,67 @@ pbf_status pbf_mesh_info(const pbf_ctx *c, int64_t *nd, int64_t *nc, int64_t *nq
     if (!c) return fail(nullptr, PBF_EINVAL, "pbf_mesh_info: ctx is NULL");
     if (!c->has_mesh) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no mesh");
     const long long q = nq1(c);
-    if (nd) *nd = n_dofs(c);
-    if (nc) *nc = n_cells(c);
-    if (nq) *nq = n_cells(c) * q * q * q;
+    if (nd) *nd = alloc_dofs(c);
+    if (nc) *nc = alloc_cells(c);
+    if (nq) *nq = alloc_cells(c) * q * q * q;
     if (nhl) *nhl = c->hist_layers;
     if (nhc) *nhc = n_hist_cells(c);
     if (nhq) *nhq = n_hist_qp(c);
+    return PBF_OK;
+}
+
+pbf_status pbf_set_active_layers(pbf_ctx *c, int nz_active)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->has_mesh || c->octree) return fail(c, PBF_ESTATE, "layer activation needs a box mesh");
+    if (c->bound) return fail(c, PBF_ESTATE, "set the active layers before pbf_bind_device");
+    const int nzf = c->growing ? c->nz_full : c->nz;
+    if (nz_active < 1 || nz_active > nzf) return fail(c, PBF_EINVAL, "nz_active must be in [1, %d]", nzf);
+    if (!c->growing) {
+        c->nz_full = c->nz;
+        c->Lz_full = c->L[2];
+        c->growing = true;
+    }
+    c->nz = nz_active;
+    c->L[2] = c->Lz_full * nz_active / c->nz_full;
+    compute_history_layers(c);
+    return PBF_OK;
+}
+
+pbf_status pbf_active_info(const pbf_ctx *c, int *nz_active, int64_t *n_active_dofs, double *Lz_active)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->has_mesh) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no mesh");
+    if (nz_active) *nz_active = c->nz;
+    if (n_active_dofs) *n_active_dofs = n_dofs(c);
+    if (Lz_active) *Lz_active = c->L[2];
+    return PBF_OK;
+}
+
+pbf_status pbf_activate_layers(pbf_ctx *c, int nz_new, double T0, double *T, double *rc, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (!c->growing) return fail(c, PBF_ESTATE, "not a growing box (pbf_set_active_layers before binding)");
+    if (nz_new <= c->nz || nz_new > c->nz_full)
+        return fail(c, PBF_EINVAL, "nz_new must be in [%d, %d]", c->nz + 1, c->nz_full);
+    if (!T || (n_hist_qp(c) > 0 && !rc)) return fail(c, PBF_EINVAL, "NULL device array");
+    if (!std::isfinite(T0)) return fail(c, PBF_EINVAL, "T0 must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    const long long NXY = nodes1(c, 0) * nodes1(c, 1);
+    const long long k_old = (long long)c->degree * c->nz, k_new = (long long)c->degree * nz_new;
+    // new node planes k_old+1 .. k_new start at T0 (Section 2: activated parts start at T_0)
+    PBF_HIP(c, launch_fill(T + NXY * (k_old + 1), T0, NXY * (k_new - k_old), s));
+    const long long cpl = (long long)c->nx * c->ny;
+    const int nz_old = c->nz;
+    c->nz = nz_new;
+    c->L[2] = c->Lz_full * nz_new / c->nz_full;
+    compute_history_layers(c);
+    // new cells: powder at the Gauss points within powder_depth of the new top
+    if (n_hist_qp(c) > 0)
+        PBF_HIP(c, launch_layer_history(c->degree, rc, n_hist_cells(c), cpl * nz_old, cpl * nz_new, (int)cpl,
+                                        c->L[2] / c->nz, c->L[2], c->powder_depth, s));
     return PBF_OK;
 }
 
@@ -1154,14 +1229,14 @@ size_t picard_coef_count(const pbf_ctx *c)
 {
     if (c->octree) return 0;
     const size_t nq = (size_t)(c->degree + 1) * (c->degree + 1) * (c->degree + 1);
-    return (size_t)kCoefPicard * nq * (size_t)c->nx * c->ny * c->nz;
+    return (size_t)kCoefPicard * nq * (size_t)alloc_cells(c);
 }
 
 pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "NULL argument");
     if (!c->has_mesh) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "no mesh");
-    const size_t N = (size_t)n_dofs(c);
+    const size_t N = (size_t)alloc_dofs(c);
     size_t b = 0;
     b += align256(sizeof(Law<double>)) * 3 + align256(sizeof(Law<float>));
     b += align256((c->octree ? 0 : 8 * N) * sizeof(double));  // parity slots (boxes)
@@ -1185,7 +1260,7 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     if (!workspace) return fail(c, PBF_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(c, PBF_EINVAL, "workspace must be 256-byte aligned");
     if (bytes < need) return fail(c, PBF_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, need);
-    const size_t N = (size_t)n_dofs(c);
+    const size_t N = (size_t)alloc_dofs(c);
     char *p = (char *)workspace;
     c->d_law64 = (Law<double> *)p;
     p += align256(sizeof(Law<double>));
@@ -1248,9 +1323,13 @@ pbf_status pbf_init_state(pbf_ctx *c, double T0, double *T, double *rc, void *st
         c->laws_dirty = true;
     }
     if ((st = upload_laws(c, s))) return st;
-    PBF_HIP(c, launch_fill(T, T0, n_dofs(c), s));
+    PBF_HIP(c, launch_fill(T, T0, alloc_dofs(c), s));
     PBF_HIP(c, launch_init_dirichlet(T, geometry(c), c->T_D, s));
-    if (n_hist_qp(c) > 0) {
+    if (c->growing) {
+        if (n_hist_qp(c) > 0)
+            PBF_HIP(c, launch_layer_history(c->degree, rc, n_hist_cells(c), 0, alloc_cells(c), c->nx * c->ny,
+                                            c->L[2] / c->nz, c->L[2], c->powder_depth, s));
+    } else if (n_hist_qp(c) > 0) {
         if (c->octree)
             PBF_HIP(c, launch_oct_init_history(c->od, c->degree, c->powder_depth, rc, s));
         else
@@ -1455,7 +1534,7 @@ size_t newton_work_layout(long long N, long long ncoef, int restart, char *base,
 long long newton_coef_count(const pbf_ctx *c)
 {
     const long long nq = (long long)(c->degree + 1) * (c->degree + 1) * (c->degree + 1);
-    return c->octree ? 0 : (long long)kCoefNewton * nq * c->nx * c->ny * c->nz;
+    return c->octree ? 0 : (long long)kCoefNewton * nq * alloc_cells(c);
 }
 
 pbf_status pbf_newton_work_bytes(pbf_ctx *c, int restart, size_t *bytes)
@@ -1678,6 +1757,7 @@ pbf_status pbf_adjoint_step(pbf_ctx *c, const double *T_n, const double *T_next,
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
     if (c->re.on) return fail(c, PBF_ESTATE, "the adjoint does not cover surface losses (pbf_set_surface_loss)");
+    if (c->growing) return fail(c, PBF_ESTATE, "the adjoint needs a fixed mesh (no layer activation)");
     if (c->octree) return fail(const_cast<pbf_ctx *>(c), PBF_ESTATE, "probes and the adjoint need a box mesh");
     pbf_status st = check_bound(c);
     if (st) return st;
@@ -1741,6 +1821,7 @@ pbf_status pbf_gradient_forward(pbf_ctx *c, const double *T0, const double *rc0,
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
     if (c->re.on) return fail(c, PBF_ESTATE, "the adjoint does not cover surface losses (pbf_set_surface_loss)");
+    if (c->growing) return fail(c, PBF_ESTATE, "the adjoint needs a fixed mesh (no layer activation)");
     pbf_status st = check_grad_args(c, dt, n_steps, n_snaps, work, work_bytes);
     if (st) return st;
     if (!T0 || (n_hist_qp(c) > 0 && !rc0)) return fail(c, PBF_EINVAL, "NULL initial state");
@@ -1793,6 +1874,7 @@ pbf_status pbf_gradient_backward(pbf_ctx *c, double t0, double dt, int n_steps, 
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
     if (c->re.on) return fail(c, PBF_ESTATE, "the adjoint does not cover surface losses (pbf_set_surface_loss)");
+    if (c->growing) return fail(c, PBF_ESTATE, "the adjoint needs a fixed mesh (no layer activation)");
     pbf_status st = check_grad_args(c, dt, n_steps, n_snaps, work, work_bytes);
     if (st) return st;
     if (!c->grad.valid || c->grad.work != work || c->grad.n_steps != n_steps || c->grad.n_snaps != n_snaps ||

@@ -272,6 +272,10 @@ hipError_t launch_cg_direction(double *p, const double *z, const double *scal, i
 hipError_t launch_picard_update(double *Ti, const double *x, double *partials, double *scal,
                                 const HaloParams &geom, long long n, hipStream_t s);
 hipError_t launch_sub(double *d, const double *a, const double *b, long long n, hipStream_t s);
+// history of cells [c0, c1) of a growing box (point-major, stride n_hist_cells):
+// 0 (powder) at Gauss levels within depth of the top Lz, else 1
+hipError_t launch_layer_history(int degree, double *rc, long long stride, long long c0, long long c1,
+                                int cells_per_layer, double hz, double Lz, double depth, hipStream_t s);
 // GMRES vector kernels (deterministic reductions); at most kGmMax Krylov vectors
 constexpr int kGmMax = 64;
 hipError_t launch_mdot(const double *w, const double *V, long long ldv, int k, double *partials, double *out,

@@ -335,9 +335,40 @@ __global__ void k_neg(double *b, const double *y, long long n)
     if (j < n) b[j] = -y[j];
 }
 
+template <int P>
+__global__ void k_layer_history(double *rc, long long stride, long long c0, long long c1, int cells_per_layer,
+                                double hz, double Lz, double depth)
+{
+    constexpr int N = P + 1, NQ = N * N * N;
+    const long long nc = c1 - c0;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc * NQ) return;
+    const int q = int(i / nc);
+    const long long c = c0 + i % nc;
+    const int qz = q / (N * N);
+    constexpr double g0 = Tables<P>::gp(0), g1 = Tables<P>::gp(1), g2 = Tables<P>::gp(P);
+    const double zeta = qz == 0 ? g0 : (qz == 1 ? g1 : g2);
+    const double z = (double(c / cells_per_layer) + zeta) * hz;
+    rc[(long long)q * stride + c] = (Lz - z <= depth) ? 0.0 : 1.0;
+}
+
 inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+hipError_t launch_layer_history(int degree, double *rc, long long stride, long long c0, long long c1,
+                                int cells_per_layer, double hz, double Lz, double depth, hipStream_t s)
+{
+    const long long n = (c1 - c0) * (degree + 1) * (degree + 1) * (degree + 1);
+    if (n <= 0) return hipSuccess;
+    if (degree == 1)
+        hipLaunchKernelGGL(k_layer_history<1>, dim3(blocks_for(n, 256)), dim3(256), 0, s, rc, stride, c0, c1,
+                           cells_per_layer, hz, Lz, depth);
+    else
+        hipLaunchKernelGGL(k_layer_history<2>, dim3(blocks_for(n, 256)), dim3(256), 0, s, rc, stride, c0, c1,
+                           cells_per_layer, hz, Lz, depth);
+    return hipGetLastError();
+}
 
 hipError_t launch_mdot(const double *w, const double *V, long long ldv, int k, double *partials, double *out,
                        long long n, hipStream_t s)

@@ -74,6 +74,9 @@ SIGNATURES = {
     "pbf_set_material": [_vp, C.POINTER(_Material)],
     "pbf_set_laser": [_vp, C.POINTER(_Laser)],
     "pbf_set_surface_loss": [_vp, C.POINTER(_SurfaceLoss)],
+    "pbf_set_active_layers": [_vp, C.c_int],
+    "pbf_active_info": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int64), _dp],
+    "pbf_activate_layers": [_vp, C.c_int, C.c_double, _vp, _vp, _vp],
     "pbf_set_track_powers": [_vp, _dp, C.c_double],
     "pbf_workspace_bytes": [_vp, C.POINTER(C.c_size_t)],
     "pbf_bind_device": [_vp, _vp, C.c_size_t, _vp],
@@ -244,6 +247,21 @@ class Simulation:
         r = _SurfaceLoss(float(emissivity), float(T_inf), 1 if evap_on else 0, float(T_v), float(C_P),
                          float(C_T), float(C_M), float(h_v), float(T_h0), float(dT_max))
         self._check(self.lib.pbf_set_surface_loss(self.ctx, C.byref(r)))
+
+    def set_active_layers(self, nz_active):
+        """Growing box: only the bottom nz_active cell layers are active (before bind)."""
+        self._check(self.lib.pbf_set_active_layers(self.ctx, int(nz_active)))
+
+    def active_info(self):
+        nz, nd, lz = C.c_int(0), C.c_int64(0), C.c_double(0)
+        self._check(self.lib.pbf_active_info(self.ctx, C.byref(nz), C.byref(nd), C.byref(lz)))
+        return {"nz_active": nz.value, "n_active_dofs": nd.value, "Lz_active": lz.value}
+
+    def activate_layers(self, nz_new, T0, T, rc):
+        """Activate cell layers up to nz_new: new nodes start at T0, new cells as powder."""
+        i = self.info()
+        self._check(self.lib.pbf_activate_layers(self.ctx, int(nz_new), float(T0), _f64(T, i["n_dofs"], "T"),
+                                                 _ptr(rc) if i["n_hist_qp"] else None, self._stream()))
 
     def set_track_powers(self, powers, absorptivity):
         p = np.ascontiguousarray(powers, dtype=np.float64)
@@ -467,10 +485,11 @@ class Simulation:
         return a.value, b.value, n.value
 
 
-def from_problem(prob, device="cuda:0", leaves=None):
+def from_problem(prob, device="cuda:0", leaves=None, active_layers=None):
     """Simulation set up from a problem description object with the attributes
     of pbf_workloads.Problem (argument marshalling only); an octree mesh when the
-    problem (or the `leaves` argument) holds leaves."""
+    problem (or the `leaves` argument) holds leaves; a growing box with the bottom
+    active_layers cell layers active when given."""
     lv = leaves if leaves is not None else getattr(prob, "leaves", None)
     s = Simulation(prob.degree, prob.nx, prob.ny, prob.nz, prob.L, device=device,
                    max_level=getattr(prob, "max_level", 0), leaves=lv)
@@ -483,5 +502,7 @@ def from_problem(prob, device="cuda:0", leaves=None):
         t_inf = getattr(prob, "T_inf", None)
         s.set_surface_loss(prob.emissivity, prob.T_D if t_inf is None else t_inf, prob.evap_on, prob.T_v,
                            prob.C_P, prob.C_T, prob.C_M, prob.h_v, prob.T_h0, prob.dT_max)
+    if active_layers is not None:
+        s.set_active_layers(active_layers)
     s.bind()
     return s

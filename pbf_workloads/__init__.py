@@ -214,6 +214,13 @@ def small_nonlinear(nx=20, ny=18, nz=10, steps=200, seed=2302, h=31.25e-6, track
                            track_length=track_length, n_tracks=n_tracks, hatch=hatch)
 
 
+def active_part(p: Problem, nz_active: int) -> Problem:
+    """The bottom nz_active cell layers of a box as a problem of their own (the
+    active part of a growing box: same cells, top face at nz_active hz)."""
+    hz = p.L[2] / p.nz
+    return p.replace(nz=nz_active, L=(p.L[0], p.L[1], nz_active * hz))
+
+
 def with_surface_losses(p: Problem, emissivity=0.7, evap=True) -> Problem:
     """The same problem with radiation (emissivity of the paper's Table 2) and
     evaporation on the top surface."""
