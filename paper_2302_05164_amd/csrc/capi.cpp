@@ -1704,8 +1704,10 @@ pbf_status pbf_set_probes(pbf_ctx *c, int n, const double *pts, const double *ta
     const int nc[3] = {c->nx, c->ny, c->nz};
     for (int p = 0; p < n; ++p) {
         for (int d = 0; d < 3; ++d) {
-            const double x = pts[3 * p + d];
-            if (!(x >= 0.0 && x <= c->L[d])) return fail(c, PBF_EINVAL, "probe %d lies outside the box", p);
+            const double tol = 1e-12 * c->L[d];  // points on a face up to rounding
+            if (!(pts[3 * p + d] >= -tol && pts[3 * p + d] <= c->L[d] + tol))
+                return fail(c, PBF_EINVAL, "probe %d lies outside the box", p);
+            const double x = std::min(std::max(pts[3 * p + d], 0.0), c->L[d]);
             const double h = c->L[d] / nc[d];
             const double sx = x / h;
             int ci = (int)std::floor(sx);

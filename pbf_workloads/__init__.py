@@ -227,6 +227,30 @@ def with_surface_losses(p: Problem, emissivity=0.7, evap=True) -> Problem:
     return p.replace(name=p.name + "_re", emissivity=emissivity, evap_on=evap)
 
 
+def convergence_box(degree=2, h=40e-6, power=200.0, absorptivity=0.35) -> Problem:
+    """The two-layer example of the paper's temporal-convergence appendix: a
+    1.0 x 0.2 x 0.2 mm base plate with two 40 um powder layers on top (cells of h,
+    the top two cell layers are the powder layers when h = 40 um), the material of
+    Table 2 (k = 20 W/mK in melt and solid, 0.2 in powder, rho = 7430, c = 965,
+    T_s = 1500 K, T_l = 1900 K, T_0 = 303 K, no latent heat, radiation and
+    evaporation on), the scan of Table 4 (v = 0.96 m/s, R = 60 um); one track per
+    layer along +x from (0, 0) at the top of that layer.  The laser power is not
+    given in the paper: 200 W with absorptivity 0.35 as in the other workloads.
+    `tracks` holds both tracks (layer 1, layer 2); a run scans them one per layer."""
+    L = (1.0e-3, 0.2e-3, 0.28e-3)
+    nx, ny, nz = round(L[0] / h), round(L[1] / h), round(L[2] / h)
+    tracks = np.array([[0.0, 0.0, 0.24e-3, 1.0e-3, 0.0, 0.24e-3, 0.96, power],
+                       [0.0, 0.0, 0.28e-3, 1.0e-3, 0.0, 0.28e-3, 0.96, power]])
+    p = Problem(
+        name=f"convergence_q{degree}_{nx}x{ny}x{nz}", degree=degree, nx=nx, ny=ny, nz=nz, L=L,
+        dirichlet_mask=FACE_ZM, T_D=303.0, T0=303.0,
+        T_bp=np.array([303.0, 3000.0]), k_bp=np.array([20.0, 20.0]), cp_bp=np.array([965.0, 965.0]),
+        rho=7430.0, T_s=1500.0, T_l=1900.0, latent=0.0, powder_k_factor=0.01, powder_depth=40e-6,
+        laser_kind=LASER_VOLUME, radius=60e-6, absorptivity=absorptivity, h_powder=40e-6,
+        t_start=0.0, tracks=tracks, steps=0, dt_factor=0.5, seed=0)
+    return with_surface_losses(p)
+
+
 def sine_mode(degree: int, n: int, k=20.0, rho=7900.0, cp=500.0) -> Problem:
     """Unit cube, all faces Dirichlet, constant coefficients, laser off: the setting of
     the decaying eigenmode T = T_D + A sin(pi x) sin(pi y) sin(pi z)."""
