@@ -68,7 +68,7 @@ k_adjoint(const AdjointParams p)
     const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
-    const long long NXY = (long long)p.NX * p.NY, NT = NXY * p.NZ;
+    const long long NXY = (long long)p.NX * p.NY;
     double src_acc = 0.0;  // this lane's share of sum_q W a_h s_q / W
 
 #pragma clang loop unroll(disable)
@@ -217,7 +217,7 @@ k_adjoint(const AdjointParams p)
         __syncthreads();
         if (active) {
             owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
-                                q.NX, q.NY, q.NZ, q.slots + tpar * NT, NXY,
+                                q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
                                 [&](long long g, int gi, int gj, int gk, int ax, int ay, int az, double fs) {
                 const int li = (az * BY + P * ly + ay) * BX + P * lx + ax;
                 double base = 0.0;
@@ -239,13 +239,12 @@ __global__ void __launch_bounds__(256) k_adjoint_halo(const AdjointHalo ah)
 {
     const HaloParams &h = ah.h;
     FaceNode fn;
-    if (!face_node((long long)blockIdx.x * blockDim.x + threadIdx.x, h, fn)) return;
-    const long long NT = (long long)h.NX * h.NY * h.NZ;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!face_node(t, h, fn)) return;
     const long long g = (long long)fn.gi + (long long)h.NX * fn.gj + (long long)h.NX * h.NY * fn.gk;
-    double fs = 0.0;
-    for (int a = 0; a < fn.n; ++a) fs += h.slots[fn.par[a] * NT + g];
+    const double fs = face_sum(h.slots, h.GX + h.GY + h.GZ, t, fn);
     double base = 0.0;
-    if (!on_dirichlet(h.dmask, fn.gi, fn.gj, fn.gk, h.NX, h.NY, h.NZ)) {
+    if (!on_dirichlet(h.dmask, int(fn.gi), int(fn.gj), int(fn.gk), h.NX, h.NY, h.NZ)) {
         const double lam = ah.lam[g], Tn = h.Tin[g];
         base = lam - lam * (ah.Tn1[g] - Tn) * capacity_log_slope(const_law(h.nlaw), Tn);
     }

@@ -274,14 +274,14 @@ Beam beam_at(const pbf_ctx *c, double t)
 // Cell layers per z-segment of a column workgroup: minimizes the makespan
 // (rounds of resident workgroups x layers per workgroup), two workgroups per CU
 // on 256 CUs, preferring longer segments (fewer segment faces) on ties.
-int segment_length(const pbf_ctx *c, int ty, int resident_per_cu)
+int segment_length(int nx, int ny, int nz, int ty, int resident_per_cu)
 {
-    const long long cols = (long long)ceil_div(c->nx, kTX) * ceil_div(c->ny, ty);
+    const long long cols = (long long)ceil_div(nx, kTX) * ceil_div(ny, ty);
     const long long slots = 256LL * resident_per_cu;
-    int best = c->nz;
+    int best = nz;
     long long best_cost = -1;
-    for (int S = std::min(c->nz, 32); S >= 1; --S) {
-        const long long blocks = cols * ceil_div(c->nz, S);
+    for (int S = std::min(nz, 32); S >= 1; --S) {
+        const long long blocks = cols * ceil_div(nz, S);
         const long long cost = ((blocks + slots - 1) / slots) * S;
         if (best_cost < 0 || cost < best_cost) {
             best_cost = cost;
@@ -310,7 +310,7 @@ HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
     }
     HaloParams h{};
     const int P = c->degree;
-    const int S = segment_length(c, ty, resident);
+    const int S = segment_length(c->nx, c->ny, c->nz, ty, resident);
     h.NX = (int)nodes1(c, 0);
     h.NY = (int)nodes1(c, 1);
     h.NZ = (int)nodes1(c, 2);
@@ -323,6 +323,12 @@ HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
     h.GX = (long long)(h.MX - 1) * h.NY * h.NZ;
     h.GY = (long long)h.NX * (h.MY - 1) * h.NZ;
     h.GZ = (long long)h.NX * h.NY * (h.MZ - 1);
+    h.fNX = fast_div(h.NX);
+    h.fNY = fast_div(h.NY);
+    h.fNZ = fast_div(h.NZ);
+    h.fSX = fast_div(h.SX);
+    h.fSY = fast_div(h.SY);
+    h.fSZ = fast_div(h.SZ);
     h.T_D = c->T_D;
     h.dmask = c->dmask;
     h.slots = c->d_slots;
@@ -332,6 +338,40 @@ HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
     h.hy = c->L[1] / c->ny;
     h.hz = c->L[2] / c->nz;
     return h;
+}
+
+// Resident workgroups per CU assumed by the Picard-operator column geometry.
+constexpr int kPicardResident = 3;
+
+FaceMap face_map(const HaloParams &h)
+{
+    return FaceMap{h.SZ, h.GX, h.GY, h.GX + h.GY + h.GZ};
+}
+
+// Column-face nodes of a box of nx x ny x nz cells of degree P under columns of
+// 16 x ty cells with the given residency (entries per parity slot).
+long long face_nodes(int P, int nx, int ny, int nz, int ty, int resident)
+{
+    const long long NX = (long long)P * nx + 1, NY = (long long)P * ny + 1, NZ = (long long)P * nz + 1;
+    const int S = segment_length(nx, ny, nz, ty, resident);
+    return (ceil_div(nx, kTX) - 1) * NY * NZ + NX * (ceil_div(ny, ty) - 1) * NZ +
+           NX * NY * (ceil_div(nz, S) - 1);
+}
+
+// Entries per parity slot: the largest face-node count of the column kernels
+// (explicit, Picard, adjoint) over every box the context can take (every
+// active height of a growing box).
+long long slot_entries(const pbf_ctx *c)
+{
+    if (c->octree) return 0;
+    const int tys[3] = {column_height(), picard_column_height(), adjoint_column_height()};
+    const int res[3] = {resident_columns_per_cu(column_height()), kPicardResident,
+                         adjoint_resident_columns_per_cu()};
+    long long m = 1;
+    const int z1 = c->growing ? c->nz_full : c->nz;
+    for (int nz = c->growing ? 1 : c->nz; nz <= z1; ++nz)
+        for (int g = 0; g < 3; ++g) m = std::max(m, face_nodes(c->degree, c->nx, c->ny, nz, tys[g], res[g]));
+    return m;
 }
 
 HaloParams adjoint_geometry(const pbf_ctx *c)
@@ -377,6 +417,7 @@ CellParams<R> cell_params(const pbf_ctx *c, const Law<R> *law, bool history)
     p.Tref = std::is_same<R, double>::value ? 0.0 : c->Tref;
     p.dmask = c->dmask;
     p.slots = c->d_slots;
+    p.fm = face_map(h);
     p.law = law;
     p.nlaw = c->d_law64;
     p.laser_on = 0;
@@ -572,6 +613,7 @@ PicardParams picard_params(const pbf_ctx *c, const HaloParams &h, const double *
     q.yout = y;
     q.hist = rc;
     q.slots = c->d_slots;
+    q.fm = face_map(h);
     q.nx = c->nx;
     q.ny = c->ny;
     q.nz = c->nz;
@@ -685,6 +727,7 @@ AdjointParams adjoint_params(const pbf_ctx *c, const HaloParams &h, const double
     a.hist = rc;
     a.mu = mu;
     a.slots = c->d_slots;
+    a.fm = face_map(h);
     a.partials = c->d_tiles;
     a.nx = c->nx;
     a.ny = c->ny;
@@ -1239,7 +1282,10 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     const size_t N = (size_t)alloc_dofs(c);
     size_t b = 0;
     b += align256(sizeof(Law<double>)) * 3 + align256(sizeof(Law<float>));
-    b += align256((c->octree ? 0 : 8 * N) * sizeof(double));  // parity slots (boxes)
+    const long long faces = slot_entries(c);
+    if (faces > 0x7FFFFFFFLL)  // face nodes are indexed with 32-bit thread indices
+        return fail(const_cast<pbf_ctx *>(c), PBF_EINVAL, "box too large: %lld column-face nodes", faces);
+    b += align256(8 * (size_t)faces * sizeof(double));  // parity slots (boxes)
     b += 11 * align256(N * sizeof(double));       // f, C, v; implicit: y, diag, r, z, p, Ap, x, d
     b += align256(kRedBlocks * 4 * sizeof(double)); // reduction partials
     b += align256(64 * sizeof(double));           // device scalars
@@ -1271,7 +1317,7 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     c->d_law32 = (Law<float> *)p;
     p += align256(sizeof(Law<float>));
     c->d_slots = (double *)p;
-    p += align256((c->octree ? 0 : 8 * N) * sizeof(double));
+    p += align256(8 * (size_t)slot_entries(c) * sizeof(double));
     c->d_f = (double *)p;
     p += align256(N * sizeof(double));
     c->d_C = (double *)p;
@@ -1427,7 +1473,7 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
     if ((st = upload_laws(c, s))) return st;
     const long long N = n_dofs(c);
     const HaloParams ge = geometry(c);  // explicit-kernel geometry (history commit)
-    const HaloParams hp = geometry(c, picard_column_height(), 3);
+    const HaloParams hp = geometry(c, picard_column_height(), kPicardResident);
     double *y = c->d_cg[0], *diag = c->d_cg[1], *r = c->d_cg[2], *z = c->d_cg[3], *p = c->d_cg[4],
            *Ap = c->d_cg[5], *x = c->d_cg[6], *d = c->d_cg[7];
     double *Ti = T_out;
@@ -1569,7 +1615,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_laws(c, s))) return st;
     const HaloParams ge = geometry(c);
-    const HaloParams hp = geometry(c, picard_column_height(), 3);
+    const HaloParams hp = geometry(c, picard_column_height(), kPicardResident);
     double *y = c->d_cg[0], *diag = c->d_cg[1], *r = c->d_cg[2], *z = c->d_cg[3], *b = c->d_cg[4],
            *w = c->d_cg[5], *x = c->d_cg[6], *d = c->d_cg[7];
     double *Ti = T_out, *V = nw.V;

@@ -121,6 +121,26 @@ __device__ __forceinline__ bool is_face(int g, int S, int n)  // interior tile f
     return g > 0 && g < n - 1 && (g % S) == 0;
 }
 
+// Copy of the face map of a parameter block (which may live in the kernel
+// argument segment).
+template <typename Q>
+__device__ __forceinline__ FaceMap face_map_of(Q &q)
+{
+    return FaceMap{q.fm.SZ, q.fm.GX, q.fm.GY, q.fm.GT};
+}
+
+// Index of a column-face node in the compact slot layout: x-face planes
+// [plane][k][j], then y-face planes [plane][k][i] (nodes not on an x face),
+// then z-segment ends [end][j][i] (nodes on neither).  SX, SY: node planes per
+// column in x and y.
+__device__ __forceinline__ long long face_slot(int gi, int gj, int gk, int SX, int SY, int NX, int NY,
+                                               int NZ, FaceMap m)
+{
+    if (is_face(gi, SX, NX)) return ((long long)(gi / SX - 1) * NZ + gk) * NY + gj;
+    if (is_face(gj, SY, NY)) return m.GX + ((long long)(gj / SY - 1) * NZ + gk) * NX + gi;
+    return m.GX + m.GY + ((long long)(gk / m.SZ - 1) * NY + gj) * NX + gi;
+}
+
 // lumped capacity C~_i = rho c(T_i) M~_i at node (i,j,k), in double precision;
 // hinges of the law that no active lane of the wave exceeds are skipped
 __device__ __forceinline__ double node_capacity(ConstLaw<double> &L, double T, int i, int j, int k,
@@ -217,13 +237,13 @@ __device__ __forceinline__ void stage_shared(double *sS, const R *fe, int tid)
 // (plus 0 on the column's low faces).  The sum order of every node is fixed:
 // carry (cells below), own, right, upper, diagonal neighbour.  Top-plane sums
 // are carried in sC to the next layer; nodes on column faces and segment ends
-// go to the slot array `slots` (already offset by the column parity); complete
+// go to the compact slot array `slots` (already offset by the column parity); complete
 // nodes are handed to done(g, gi, gj, gk, ax, ay, az, f).
 template <int P, int kTY, typename R, typename Done>
 __device__ __forceinline__ void owner_nodes(const R *fe, const double *sS, double *sC, int tid, int lx,
                                             int ly, int cx, int cy, int nx, int ny, int k0, bool first,
                                             bool last, int NX, int NY, int NZ, double *slots,
-                                            long long NXY, Done &&done)
+                                            FaceMap fm, long long NXY, Done &&done)
 {
     constexpr int N = P + 1, kTPB = kTX * kTY;
     const bool hasR = lx < kTX - 1 && cx + 1 < nx;
@@ -252,7 +272,7 @@ __device__ __forceinline__ void owner_nodes(const R *fe, const double *sS, doubl
                 const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1) ||
                                   is_face(gi, P * kTX, NX) || is_face(gj, P * kTY, NY);
                 if (face) {
-                    slots[g] = f;
+                    slots[face_slot(gi, gj, gk, P * kTX, P * kTY, NX, NY, NZ, fm)] = f;
                     continue;
                 }
                 done(g, gi, gj, gk, ax, ay, az, f);
@@ -261,58 +281,80 @@ __device__ __forceinline__ void owner_nodes(const R *fe, const double *sS, doubl
     }
 }
 
-// Decode the index t of a column-face node (x-faces, then y-faces without
-// x-face nodes, then z segment ends without either) and list the columns and
-// segments that contain it.  Returns false for threads without a node.
-struct FaceNode {
-    int gi, gj, gk, n;  // node and number of containing columns/segments
-    int par[8];         // their parity slots, in a fixed order
-};
-__device__ __forceinline__ bool face_node(long long t, const HaloParams &h, FaceNode &fn)
+// Quotient and remainder of n / f.d (see FastDiv).
+__device__ __forceinline__ unsigned div_rem(unsigned n, FastDiv f, unsigned &r)
 {
-    long long r = t;
-    int gi, gj, gk, grp;
-    if (r < h.GX) {
+    unsigned q = __umulhi(n, f.m);
+    r = n - q * f.d;
+    if (r >= f.d) {
+        ++q;
+        r -= f.d;
+    }
+    return q;
+}
+
+// A column-face node and the columns/segments that contain it: cx x cy x cz of
+// them (1 or 2 per direction) starting at the tile (x0, y0, z0) whose parity
+// bits are p0; the others follow with the parity bit of their direction flipped.
+struct FaceNode {
+    unsigned gi, gj, gk;
+    unsigned p0, cx, cy, cz;
+};
+
+// Decode the index t of a column-face node (x-faces, then y-faces without
+// x-face nodes, then z segment ends without either; the compact slot order).
+// Returns false for threads without a node.
+__device__ __forceinline__ bool face_node(unsigned t, const HaloParams &h, FaceNode &fn)
+{
+    unsigned r = t, gi, gj, gk, plane;
+    int grp;
+    if (r < unsigned(h.GX)) {
         grp = 0;
-        gj = int(r % h.NY);
-        r /= h.NY;
-        gk = int(r % h.NZ);
-        gi = int(r / h.NZ + 1) * h.SX;
-    } else if ((r -= h.GX) < h.GY) {
+        plane = div_rem(div_rem(r, h.fNY, gj), h.fNZ, gk);
+        gi = (plane + 1) * unsigned(h.SX);
+    } else if ((r -= unsigned(h.GX)) < unsigned(h.GY)) {
         grp = 1;
-        gi = int(r % h.NX);
-        r /= h.NX;
-        gk = int(r % h.NZ);
-        gj = int(r / h.NZ + 1) * h.SY;
-    } else if ((r -= h.GY) < h.GZ) {
+        plane = div_rem(div_rem(r, h.fNX, gi), h.fNZ, gk);
+        gj = (plane + 1) * unsigned(h.SY);
+    } else if ((r -= unsigned(h.GY)) < unsigned(h.GZ)) {
         grp = 2;
-        gi = int(r % h.NX);
-        r /= h.NX;
-        gj = int(r % h.NY);
-        gk = int(r / h.NY + 1) * h.SZ;
+        plane = div_rem(div_rem(r, h.fNX, gi), h.fNY, gj);
+        gk = (plane + 1) * unsigned(h.SZ);
     } else {
         return false;
     }
-    const bool fx = is_face(gi, h.SX, h.NX), fy = is_face(gj, h.SY, h.NY), fz = is_face(gk, h.SZ, h.NZ);
+    unsigned rx, ry, rz;
+    const unsigned tx = div_rem(gi, h.fSX, rx), ty = div_rem(gj, h.fSY, ry), tz = div_rem(gk, h.fSZ, rz);
+    const bool fx = rx == 0 && gi > 0 && gi < unsigned(h.NX - 1);
+    const bool fy = ry == 0 && gj > 0 && gj < unsigned(h.NY - 1);
+    const bool fz = rz == 0 && gk > 0 && gk < unsigned(h.NZ - 1);
     if (grp == 0 && !fx) return false;
     if (grp >= 1 && fx) return false;
     if (grp == 1 && !fy) return false;
     if (grp == 2 && (fy || !fz)) return false;
-    int xs[2], ys[2], zs[2];
-    int nxs, nys, nzs;
-    if (fx) { xs[0] = gi / h.SX - 1; xs[1] = gi / h.SX; nxs = 2; } else { xs[0] = min(gi / h.SX, h.MX - 1); nxs = 1; }
-    if (fy) { ys[0] = gj / h.SY - 1; ys[1] = gj / h.SY; nys = 2; } else { ys[0] = min(gj / h.SY, h.MY - 1); nys = 1; }
-    if (fz) { zs[0] = gk / h.SZ - 1; zs[1] = gk / h.SZ; nzs = 2; } else { zs[0] = min(gk / h.SZ, h.MZ - 1); nzs = 1; }
-    int n = 0;
-    for (int a = 0; a < nzs; ++a)
-        for (int bb = 0; bb < nys; ++bb)
-            for (int e = 0; e < nxs; ++e)
-                fn.par[n++] = (xs[e] & 1) | ((ys[bb] & 1) << 1) | ((zs[a] & 1) << 2);
+    // lowest containing tile per direction (the last tile also holds the far boundary)
+    const unsigned x0 = fx ? tx - 1 : min(tx, unsigned(h.MX - 1));
+    const unsigned y0 = fy ? ty - 1 : min(ty, unsigned(h.MY - 1));
+    const unsigned z0 = fz ? tz - 1 : min(tz, unsigned(h.MZ - 1));
     fn.gi = gi;
     fn.gj = gj;
     fn.gk = gk;
-    fn.n = n;
+    fn.p0 = (x0 & 1) | ((y0 & 1) << 1) | ((z0 & 1) << 2);
+    fn.cx = fx ? 2 : 1;
+    fn.cy = fy ? 2 : 1;
+    fn.cz = fz ? 2 : 1;
     return true;
+}
+
+// Sum of the parity slots of face node t in a fixed order (z outer, x inner).
+__device__ __forceinline__ double face_sum(const double *slots, long long GT, unsigned t, const FaceNode &fn)
+{
+    double f = 0.0;
+    for (unsigned a = 0; a < fn.cz; ++a)
+        for (unsigned b = 0; b < fn.cy; ++b)
+            for (unsigned e = 0; e < fn.cx; ++e)
+                f += slots[(long long)(fn.p0 ^ (e | (b << 1) | (a << 2))) * GT + t];
+    return f;
 }
 
 // ---- Picard operator helpers (implicit step) ----

@@ -262,6 +262,7 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
     const int NX = q.NX, NY = q.NY, NZ = q.NZ;
     const unsigned dmask = q.dmask;
     const double hx = q.hx, hy = q.hy, hz = q.hz, dt = q.dt, T_D = q.T_D;
+    const FaceMap fm = face_map_of(q);
 #pragma unroll
     for (int az = 0; az < N; ++az) {
 #pragma unroll
@@ -300,13 +301,20 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
                 const double m = lumped_mass_1d(gi, NX, P, hx) * lumped_mass_1d(gj, NY, P, hy) *
                                  lumped_mass_1d(gk, NZ, P, hz);
                 const double C = rho * c * m;
+                const long long t = face_slot(gi, gj, gk, P * kTX, P * kTY, NX, NY, NZ, fm);
                 if (MODE == 0) {
-                    const double upd = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ) ? T_D : T + dt * f / C;
-                    double *dst = face ? slots + g : q.Tout + g;
-                    const double val = face ? f : upd;
+                    // face nodes: the lowest containing column (the first term of the face
+                    // kernel's fixed-order sum) stores its complete update, the others only
+                    // their increment, so the face kernel needs neither T_n nor C~
+                    const bool dir = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ);
+                    const double inc = dt * f / C;
+                    const bool later = (ax == 0 && is_face(gi, P * kTX, NX)) ||
+                                       (ay == 0 && is_face(gj, P * kTY, NY)) || (az == 0 && first && gk > 0);
+                    const double val = dir ? ((face && later) ? 0.0 : T_D) : ((face && later) ? inc : T + inc);
+                    double *dst = face ? slots + t : q.Tout + g;
                     if (own) *dst = val;
                 } else {
-                    double *dst = face ? slots + g : q.fout + g;
+                    double *dst = face ? slots + t : q.fout + g;
                     if (own) *dst = f;
                     if (own && !face) q.Cout[g] = C;
                 }
@@ -361,7 +369,7 @@ k_cells(const CellParams<R> p)
     const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
-    const long long NXY = (long long)p.NX * p.NY, NT = NXY * p.NZ;
+    const long long NXY = (long long)p.NX * p.NY;
 
     // the N node planes of the first layer
     for (unsigned idx = threadIdx.x; idx < unsigned(NB); idx += kTPB) {
@@ -429,7 +437,7 @@ k_cells(const CellParams<R> p)
         // 3. owned nodes: sum, carry, completion
         if (active) {
             owner_update<P, kTY, MODE>(q, fe, sS, sC, sTl, r0, tid, lx, ly, cx, cy, k0, cz == z0,
-                                       cz == z1 - 1, q.slots + tpar * NT, NXY);
+                                       cz == z1 - 1, q.slots + tpar * q.fm.GT, NXY);
         }
         __syncthreads();
         // 4. the new planes replace planes k0 .. k0+P-1 (slots r0 .. r0+P-1 mod N)
@@ -454,20 +462,16 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_halo(const HaloParams h)
 {
     FaceNode fn;
-    if (!face_node((long long)blockIdx.x * blockDim.x + threadIdx.x, h, fn)) return;
-    const long long NT = (long long)h.NX * h.NY * h.NZ;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!face_node(t, h, fn)) return;
     const long long g = (long long)fn.gi + (long long)h.NX * fn.gj + (long long)h.NX * h.NY * fn.gk;
-    double f = 0.0;
-    for (int a = 0; a < fn.n; ++a) f += h.slots[fn.par[a] * NT + g];
-    const double T = h.Tin[g];
-    const double C = node_capacity(const_law(h.nlaw), T, fn.gi, fn.gj, fn.gk, h.P, h.NX, h.NY, h.NZ,
-                                   h.hx, h.hy, h.hz);
-    if (MODE == 0) {
-        h.Tout[g] = on_dirichlet(h.dmask, fn.gi, fn.gj, fn.gk, h.NX, h.NY, h.NZ) ? h.T_D
-                                                                                : T + h.dt * f / C;
+    const double f = face_sum(h.slots, h.GX + h.GY + h.GZ, t, fn);
+    if (MODE == 0) {  // the slots hold T_n + dt f_0 / C~ and the other columns' increments
+        h.Tout[g] = f;
     } else {
         h.fout[g] = f;
-        h.Cout[g] = C;
+        h.Cout[g] = node_capacity(const_law(h.nlaw), h.Tin[g], int(fn.gi), int(fn.gj), int(fn.gk), h.P, h.NX,
+                                  h.NY, h.NZ, h.hx, h.hy, h.hz);
     }
 }
 

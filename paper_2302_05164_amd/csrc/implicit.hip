@@ -47,7 +47,7 @@ k_picard(const PicardParams p)
     const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
-    const long long NXY = (long long)p.NX * p.NY, NT = NXY * p.NZ;
+    const long long NXY = (long long)p.NX * p.NY;
 
 #pragma clang loop unroll(disable)
     for (int cz = z0; cz < z1; ++cz) {
@@ -188,7 +188,7 @@ k_picard(const PicardParams p)
         __syncthreads();
         if (active) {
             owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
-                                q.NX, q.NY, q.NZ, q.slots + tpar * NT, NXY,
+                                q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
                                 [&](long long g, int gi, int gj, int gk, int, int, int, double f) {
                 const bool dir = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ);
                 q.yout[g] = dir ? (MODE == 0 ? 0.0 : 1.0) : f;
@@ -276,7 +276,7 @@ k_picard_capply(const PicardParams p)
     const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
-    const long long NXY = (long long)p.NX * p.NY, NT = NXY * p.NZ;
+    const long long NXY = (long long)p.NX * p.NY;
 
 #pragma clang loop unroll(disable)
     for (int cz = z0; cz < z1; ++cz) {
@@ -350,7 +350,7 @@ k_picard_capply(const PicardParams p)
         __syncthreads();
         if (active) {
             owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
-                                q.NX, q.NY, q.NZ, q.slots + tpar * NT, NXY,
+                                q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
                                 [&](long long g, int gi, int gj, int gk, int, int, int, double f) {
                 q.yout[g] = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ) ? 0.0 : f;
             });
@@ -363,12 +363,11 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_picard_halo(const HaloParams h, double *y)
 {
     FaceNode fn;
-    if (!face_node((long long)blockIdx.x * blockDim.x + threadIdx.x, h, fn)) return;
-    const long long NT = (long long)h.NX * h.NY * h.NZ;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!face_node(t, h, fn)) return;
     const long long g = (long long)fn.gi + (long long)h.NX * fn.gj + (long long)h.NX * h.NY * fn.gk;
-    double f = 0.0;
-    for (int a = 0; a < fn.n; ++a) f += h.slots[fn.par[a] * NT + g];
-    const bool dir = on_dirichlet(h.dmask, fn.gi, fn.gj, fn.gk, h.NX, h.NY, h.NZ);
+    const double f = face_sum(h.slots, h.GX + h.GY + h.GZ, t, fn);
+    const bool dir = on_dirichlet(h.dmask, int(fn.gi), int(fn.gj), int(fn.gk), h.NX, h.NY, h.NZ);
     y[g] = dir ? (MODE == 0 ? 0.0 : 1.0) : f;
 }
 

@@ -108,6 +108,16 @@ struct SurfaceLoss {
     const Law<double> *law;    // material law (specific heat of the enthalpy term)
 };
 
+// Compact storage of the partial sums at column faces: one entry per face node
+// and column parity, in the order in which the face kernels enumerate their
+// threads (x-face planes, then y-face planes without x-face nodes, then
+// z-segment ends without either), so that those kernels read it coalesced.
+// Parity slot s of face node t lives at slots[s * GT + t].
+struct FaceMap {
+    int SZ;                // node planes per z-segment
+    long long GX, GY, GT;  // x-face nodes, y-face nodes, all face nodes
+};
+
 // Parameters of one cell-kernel launch (passed by value).
 template <typename R>
 struct CellParams {
@@ -116,6 +126,7 @@ struct CellParams {
     double *fout, *Cout;  // assembled vectors (assemble mode)
     double *hist;       // consolidated fraction of the history layers
     double *slots;      // 8 parity slots of partial sums of f at tile faces
+    FaceMap fm;
     int nx, ny, nz, NX, NY, NZ;
     int MX, MY, MZ, ntiles, tiles_per_xcd;  // columns in x, y; z-segments; MX*MY*MZ
     int seg_len;                            // cell layers per z-segment
@@ -138,6 +149,7 @@ struct PicardParams {
     double *yout;
     const double *hist;  // consolidated fraction, lagged (read only)
     double *slots;
+    FaceMap fm;
     int nx, ny, nz, NX, NY, NZ;
     int MX, MY, MZ, ntiles, tiles_per_xcd, seg_len;
     int hist_cz0, n_hist_cells;
@@ -163,6 +175,7 @@ struct AdjointParams {
     const double *hist;  // r^{n-1} (read only)
     double *mu;          // history adjoint: mu_n in, mu_{n-1} out
     double *slots;
+    FaceMap fm;
     double *partials;    // per column tile: source sensitivity of the step
     int nx, ny, nz, NX, NY, NZ;
     int MX, MY, MZ, ntiles, tiles_per_xcd, seg_len;
@@ -185,6 +198,15 @@ struct ProbeSet {
 };
 
 // Parameters of the tile-face completion kernel.
+// Division of 32-bit unsigned numerators n by a fixed divisor d >= 1 with a
+// multiply-high: m = floor((2^32 - 1) / d) gives n m / 2^32 > n / d - 1 for
+// every n < 2^32, so the estimate is the quotient or one less, and a single
+// remainder test corrects it.
+struct FastDiv {
+    unsigned d, m;
+};
+inline FastDiv fast_div(unsigned d) { return FastDiv{d, 0xFFFFFFFFu / d}; }
+
 struct HaloParams {
     const double *Tin;
     double *Tout, *fout, *Cout;
@@ -192,6 +214,7 @@ struct HaloParams {
     const Law<double> *nlaw;
     int P, NX, NY, NZ, SX, SY, SZ, MX, MY, MZ;
     long long GX, GY, GZ;  // sizes of the x-, y- and z-face groups
+    FastDiv fNX, fNY, fNZ, fSX, fSY, fSZ;  // divisions of the face-node decode
     double hx, hy, hz, dt, T_D;
     unsigned dmask;
     const unsigned char *dflag;  // per-dof Dirichlet flags (octree meshes), else NULL
