@@ -65,7 +65,7 @@ k_adjoint(const AdjointParams p)
     if (id >= p.ntiles) return;
     const int seg = id % p.MZ, col = id / p.MZ;
     const int tx = col % p.MX, ty = col / p.MX;
-    const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
+    const int z0 = p.zb[seg], z1 = p.zb[seg + 1];
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
     const long long NXY = (long long)p.NX * p.NY;
@@ -216,7 +216,7 @@ k_adjoint(const AdjointParams p)
         }
         __syncthreads();
         if (active) {
-            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
+            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, seg, cz == z0, cz == z1 - 1,
                                 q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
                                 [&](long long g, int gi, int gj, int gk, int ax, int ay, int az, double fs) {
                 const int li = (az * BY + P * ly + ay) * BX + P * lx + ax;

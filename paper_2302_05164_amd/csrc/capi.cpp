@@ -278,9 +278,10 @@ int segment_length(int nx, int ny, int nz, int ty, int resident_per_cu)
 {
     const long long cols = (long long)ceil_div(nx, kTX) * ceil_div(ny, ty);
     const long long slots = 256LL * resident_per_cu;
-    int best = nz;
+    const int smin = ceil_div(nz, kMaxSeg);  // at most kMaxSeg segments
+    int best = std::max(std::min(nz, 32), smin);
     long long best_cost = -1;
-    for (int S = std::min(nz, 32); S >= 1; --S) {
+    for (int S = best; S >= smin; --S) {
         const long long blocks = cols * ceil_div(nz, S);
         const long long cost = ((blocks + slots - 1) / slots) * S;
         if (best_cost < 0 || cost < best_cost) {
@@ -291,8 +292,29 @@ int segment_length(int nx, int ny, int nz, int ty, int resident_per_cu)
     return best;
 }
 
+// Boundaries of MZ = ceil(nz / S) z-segments.  Uniform: S layers each (the
+// top one takes the remainder).  top_short: the top segment takes S/2 layers
+// and the lower ones share the rest evenly (longer ones at the bottom).  The
+// top layers of a scan are the costliest (beam, melt pool, powder history),
+// and a column's top segment sets the launch time when it is as long as the
+// others.
+int segment_bounds(int nz, int S, bool top_short, int *zb)
+{
+    const int MZ = ceil_div(nz, S);
+    zb[0] = 0;
+    if (!top_short || MZ < 2 || S < 2) {
+        for (int s = 1; s <= MZ; ++s) zb[s] = std::min(s * S, nz);
+        return MZ;
+    }
+    const int lower = MZ - 1, rest = nz - S / 2;  // rest >= lower: nz > (MZ - 1) S
+    for (int s = 0; s < lower; ++s) zb[s + 1] = zb[s] + rest / lower + (s < rest % lower ? 1 : 0);
+    zb[MZ] = nz;
+    return MZ;
+}
+
 // Column geometry of a cell kernel with columns of 16 x ty cells and the given
-// number of resident workgroups per CU (explicit kernels by default).
+// number of resident workgroups per CU (explicit kernels by default, which
+// also shorten the top segment).
 HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
 {
     if (c->octree) {  // dof vectors with per-dof Dirichlet flags
@@ -304,6 +326,7 @@ HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
         h.nlaw = c->d_law64;
         return h;
     }
+    const bool top_short = ty < 0;
     if (ty < 0) {
         ty = column_height();
         resident = resident_columns_per_cu(ty);
@@ -316,10 +339,9 @@ HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
     h.NZ = (int)nodes1(c, 2);
     h.SX = P * kTX;
     h.SY = P * ty;
-    h.SZ = P * S;
     h.MX = ceil_div(c->nx, kTX);
     h.MY = ceil_div(c->ny, ty);
-    h.MZ = ceil_div(c->nz, S);
+    h.MZ = segment_bounds(c->nz, S, top_short, h.zb);
     h.GX = (long long)(h.MX - 1) * h.NY * h.NZ;
     h.GY = (long long)h.NX * (h.MY - 1) * h.NZ;
     h.GZ = (long long)h.NX * h.NY * (h.MZ - 1);
@@ -328,7 +350,6 @@ HaloParams geometry(const pbf_ctx *c, int ty = -1, int resident = -1)
     h.fNZ = fast_div(h.NZ);
     h.fSX = fast_div(h.SX);
     h.fSY = fast_div(h.SY);
-    h.fSZ = fast_div(h.SZ);
     h.T_D = c->T_D;
     h.dmask = c->dmask;
     h.slots = c->d_slots;
@@ -345,7 +366,7 @@ constexpr int kPicardResident = 3;
 
 FaceMap face_map(const HaloParams &h)
 {
-    return FaceMap{h.SZ, h.GX, h.GY, h.GX + h.GY + h.GZ};
+    return FaceMap{h.GX, h.GY, h.GX + h.GY + h.GZ};
 }
 
 // Column-face nodes of a box of nx x ny x nz cells of degree P under columns of
@@ -401,7 +422,7 @@ CellParams<R> cell_params(const pbf_ctx *c, const Law<R> *law, bool history)
     p.MZ = h.MZ;
     p.ntiles = h.MX * h.MY * h.MZ;
     p.tiles_per_xcd = ceil_div(p.ntiles, 8);
-    p.seg_len = h.SZ / c->degree;
+    std::copy(h.zb, h.zb + h.MZ + 1, p.zb);
     p.hist_cz0 = history ? c->nz - c->hist_layers : c->nz;
     p.hist_write = 1;
     p.n_hist_cells = (int)n_hist_cells(c);
@@ -625,7 +646,7 @@ PicardParams picard_params(const pbf_ctx *c, const HaloParams &h, const double *
     q.MZ = h.MZ;
     q.ntiles = h.MX * h.MY * h.MZ;
     q.tiles_per_xcd = ceil_div(q.ntiles, 8);
-    q.seg_len = h.SZ / c->degree;
+    std::copy(h.zb, h.zb + h.MZ + 1, q.zb);
     q.hist_cz0 = c->nz - c->hist_layers;
     q.n_hist_cells = (int)n_hist_cells(c);
     q.hx = c->L[0] / c->nx;
@@ -740,7 +761,7 @@ AdjointParams adjoint_params(const pbf_ctx *c, const HaloParams &h, const double
     a.MZ = h.MZ;
     a.ntiles = h.MX * h.MY * h.MZ;
     a.tiles_per_xcd = ceil_div(a.ntiles, 8);
-    a.seg_len = h.SZ / c->degree;
+    std::copy(h.zb, h.zb + h.MZ + 1, a.zb);
     a.hist_cz0 = c->nz - c->hist_layers;
     a.n_hist_cells = (int)n_hist_cells(c);
     a.hx = c->L[0] / c->nx;

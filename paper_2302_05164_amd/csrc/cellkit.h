@@ -126,19 +126,19 @@ __device__ __forceinline__ bool is_face(int g, int S, int n)  // interior tile f
 template <typename Q>
 __device__ __forceinline__ FaceMap face_map_of(Q &q)
 {
-    return FaceMap{q.fm.SZ, q.fm.GX, q.fm.GY, q.fm.GT};
+    return FaceMap{q.fm.GX, q.fm.GY, q.fm.GT};
 }
 
 // Index of a column-face node in the compact slot layout: x-face planes
 // [plane][k][j], then y-face planes [plane][k][i] (nodes not on an x face),
-// then z-segment ends [end][j][i] (nodes on neither).  SX, SY: node planes per
-// column in x and y.
-__device__ __forceinline__ long long face_slot(int gi, int gj, int gk, int SX, int SY, int NX, int NY,
-                                               int NZ, FaceMap m)
+// then interior z-segment ends [end][j][i] (nodes on neither; zf: the end's
+// index, segment s ending at zf = s).  SX, SY: node planes per column in x, y.
+__device__ __forceinline__ long long face_slot(int gi, int gj, int gk, int zf, int SX, int SY, int NX,
+                                               int NY, int NZ, FaceMap m)
 {
     if (is_face(gi, SX, NX)) return ((long long)(gi / SX - 1) * NZ + gk) * NY + gj;
     if (is_face(gj, SY, NY)) return m.GX + ((long long)(gj / SY - 1) * NZ + gk) * NX + gi;
-    return m.GX + m.GY + ((long long)(gk / m.SZ - 1) * NY + gj) * NX + gi;
+    return m.GX + m.GY + ((long long)zf * NY + gj) * NX + gi;
 }
 
 // lumped capacity C~_i = rho c(T_i) M~_i at node (i,j,k), in double precision;
@@ -241,8 +241,8 @@ __device__ __forceinline__ void stage_shared(double *sS, const R *fe, int tid)
 // nodes are handed to done(g, gi, gj, gk, ax, ay, az, f).
 template <int P, int kTY, typename R, typename Done>
 __device__ __forceinline__ void owner_nodes(const R *fe, const double *sS, double *sC, int tid, int lx,
-                                            int ly, int cx, int cy, int nx, int ny, int k0, bool first,
-                                            bool last, int NX, int NY, int NZ, double *slots,
+                                            int ly, int cx, int cy, int nx, int ny, int k0, int seg,
+                                            bool first, bool last, int NX, int NY, int NZ, double *slots,
                                             FaceMap fm, long long NXY, Done &&done)
 {
     constexpr int N = P + 1, kTPB = kTX * kTY;
@@ -272,7 +272,7 @@ __device__ __forceinline__ void owner_nodes(const R *fe, const double *sS, doubl
                 const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1) ||
                                   is_face(gi, P * kTX, NX) || is_face(gj, P * kTY, NY);
                 if (face) {
-                    slots[face_slot(gi, gj, gk, P * kTX, P * kTY, NX, NY, NZ, fm)] = f;
+                    slots[face_slot(gi, gj, gk, az == 0 ? seg - 1 : seg, P * kTX, P * kTY, NX, NY, NZ, fm)] = f;
                     continue;
                 }
                 done(g, gi, gj, gk, ax, ay, az, f);
@@ -319,15 +319,23 @@ __device__ __forceinline__ bool face_node(unsigned t, const HaloParams &h, FaceN
     } else if ((r -= unsigned(h.GY)) < unsigned(h.GZ)) {
         grp = 2;
         plane = div_rem(div_rem(r, h.fNX, gi), h.fNY, gj);
-        gk = (plane + 1) * unsigned(h.SZ);
+        gk = 0;
+        for (int b = 1; b < h.MZ; ++b) gk = plane + 1 == unsigned(b) ? unsigned(h.P * h.zb[b]) : gk;
     } else {
         return false;
     }
-    unsigned rx, ry, rz;
-    const unsigned tx = div_rem(gi, h.fSX, rx), ty = div_rem(gj, h.fSY, ry), tz = div_rem(gk, h.fSZ, rz);
+    unsigned rx, ry;
+    const unsigned tx = div_rem(gi, h.fSX, rx), ty = div_rem(gj, h.fSY, ry);
     const bool fx = rx == 0 && gi > 0 && gi < unsigned(h.NX - 1);
     const bool fy = ry == 0 && gj > 0 && gj < unsigned(h.NY - 1);
-    const bool fz = rz == 0 && gk > 0 && gk < unsigned(h.NZ - 1);
+    // z: interior segment ends below the node plane, and whether it is one
+    unsigned below = 0;
+    bool fz = false;
+    for (int b = 1; b < h.MZ; ++b) {
+        const unsigned e = unsigned(h.P * h.zb[b]);
+        below += e < gk ? 1u : 0u;
+        fz = fz || e == gk;
+    }
     if (grp == 0 && !fx) return false;
     if (grp >= 1 && fx) return false;
     if (grp == 1 && !fy) return false;
@@ -335,7 +343,7 @@ __device__ __forceinline__ bool face_node(unsigned t, const HaloParams &h, FaceN
     // lowest containing tile per direction (the last tile also holds the far boundary)
     const unsigned x0 = fx ? tx - 1 : min(tx, unsigned(h.MX - 1));
     const unsigned y0 = fy ? ty - 1 : min(ty, unsigned(h.MY - 1));
-    const unsigned z0 = fz ? tz - 1 : min(tz, unsigned(h.MZ - 1));
+    const unsigned z0 = below;
     fn.gi = gi;
     fn.gj = gj;
     fn.gk = gk;

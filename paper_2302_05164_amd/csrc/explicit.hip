@@ -39,6 +39,9 @@
 namespace pbf {
 namespace {
 
+// Exponent beyond which the volume source is skipped in a cell (e^-56 < 2^-80).
+constexpr double kSourceCut = 56.0;
+
 // Flux and source at the Gauss points of one cell, accumulated into the
 // collocation-space integrand w.  FAST: at most one hinge of the law active, no
 // source and no history update in the wave (uniform branch-free straight-line
@@ -169,12 +172,14 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
     const long long hc = has_hist ? (long long)cx + (long long)p.nx * (cy + (long long)p.ny * (cz - p.hist_cz0)) : 0;
     bool src_cell = p.laser_on && p.laser_kind == 1 && cz >= p.src_cz0;
     if (src_cell) {
-        // Gauss points at least as far from the beam axis as the cell's box:
-        // where the Gaussian's exponent is below -750 it underflows to exactly
-        // zero in double precision, so the source adds exactly nothing there
+        // Gauss points at least as far from the beam axis as the cell's box.
+        // Where the Gaussian's exponent is below -kSourceCut the source is
+        // below e^-56 (< 2^-80) of its peak at every point of the cell: the
+        // temperature increment it would add in a step is that fraction of the
+        // peak increment, far below the rounding unit of any temperature
         const double ex = fmax(0.0, fmax(cx * p.hx - p.xb, p.xb - (cx + 1) * p.hx));
         const double ey = fmax(0.0, fmax(cy * p.hy - p.yb, p.yb - (cy + 1) * p.hy));
-        src_cell = (ex * ex + ey * ey) * p.two_over_R2 < 750.0;
+        src_cell = (ex * ex + ey * ey) * p.two_over_R2 < kSourceCut;
     }
 
     R w[NN];  // collocation-space integrand of f
@@ -240,7 +245,7 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
 template <int P, int kTY, int MODE, typename Q, typename R>
 __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS, double *sC,
                                              const double *sTl, int r0, int tid, int lx, int ly,
-                                             int cx, int cy, int k0, bool first, bool last,
+                                             int cx, int cy, int k0, int seg, bool first, bool last,
                                              double *slots, long long NXY)
 {
     constexpr int N = P + 1, kTPB = kTX * kTY;
@@ -301,7 +306,7 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
                 const double m = lumped_mass_1d(gi, NX, P, hx) * lumped_mass_1d(gj, NY, P, hy) *
                                  lumped_mass_1d(gk, NZ, P, hz);
                 const double C = rho * c * m;
-                const long long t = face_slot(gi, gj, gk, P * kTX, P * kTY, NX, NY, NZ, fm);
+                const long long t = face_slot(gi, gj, gk, az == 0 ? seg - 1 : seg, P * kTX, P * kTY, NX, NY, NZ, fm);
                 if (MODE == 0) {
                     // face nodes: the lowest containing column (the first term of the face
                     // kernel's fixed-order sum) stores its complete update, the others only
@@ -366,7 +371,7 @@ k_cells(const CellParams<R> p)
     if (id >= p.ntiles) return;  // uniform over the workgroup
     const int seg = id % p.MZ, col = id / p.MZ;
     const int tx = col % p.MX, ty = col / p.MX;
-    const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
+    const int z0 = p.zb[seg], z1 = p.zb[seg + 1];
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
     const long long NXY = (long long)p.NX * p.NY;
@@ -436,7 +441,7 @@ k_cells(const CellParams<R> p)
         }
         // 3. owned nodes: sum, carry, completion
         if (active) {
-            owner_update<P, kTY, MODE>(q, fe, sS, sC, sTl, r0, tid, lx, ly, cx, cy, k0, cz == z0,
+            owner_update<P, kTY, MODE>(q, fe, sS, sC, sTl, r0, tid, lx, ly, cx, cy, k0, seg, cz == z0,
                                        cz == z1 - 1, q.slots + tpar * q.fm.GT, NXY);
         }
         __syncthreads();

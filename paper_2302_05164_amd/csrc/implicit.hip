@@ -44,7 +44,7 @@ k_picard(const PicardParams p)
     if (id >= p.ntiles) return;
     const int seg = id % p.MZ, col = id / p.MZ;
     const int tx = col % p.MX, ty = col / p.MX;
-    const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
+    const int z0 = p.zb[seg], z1 = p.zb[seg + 1];
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
     const long long NXY = (long long)p.NX * p.NY;
@@ -187,7 +187,7 @@ k_picard(const PicardParams p)
         }
         __syncthreads();
         if (active) {
-            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
+            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, seg, cz == z0, cz == z1 - 1,
                                 q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
                                 [&](long long g, int gi, int gj, int gk, int, int, int, double f) {
                 const bool dir = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ);
@@ -273,7 +273,7 @@ k_picard_capply(const PicardParams p)
     if (id >= p.ntiles) return;
     const int seg = id % p.MZ, col = id / p.MZ;
     const int tx = col % p.MX, ty = col / p.MX;
-    const int z0 = seg * p.seg_len, z1 = min(z0 + p.seg_len, p.nz);
+    const int z0 = p.zb[seg], z1 = p.zb[seg + 1];
     const int i0 = P * kTX * tx, j0 = P * kTY * ty;
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
     const long long NXY = (long long)p.NX * p.NY;
@@ -349,7 +349,7 @@ k_picard_capply(const PicardParams p)
         }
         __syncthreads();
         if (active) {
-            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, cz == z0, cz == z1 - 1,
+            owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, seg, cz == z0, cz == z1 - 1,
                                 q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
                                 [&](long long g, int gi, int gj, int gk, int, int, int, double f) {
                 q.yout[g] = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ) ? 0.0 : f;

@@ -114,9 +114,12 @@ struct SurfaceLoss {
 // z-segment ends without either), so that those kernels read it coalesced.
 // Parity slot s of face node t lives at slots[s * GT + t].
 struct FaceMap {
-    int SZ;                // node planes per z-segment
     long long GX, GY, GT;  // x-face nodes, y-face nodes, all face nodes
 };
+
+// z-segments of the columns: segment s spans cell layers zb[s] .. zb[s+1]-1
+// (zb[0] = 0, zb[MZ] = nz); lengths need not be equal.
+constexpr int kMaxSeg = 64;
 
 // Parameters of one cell-kernel launch (passed by value).
 template <typename R>
@@ -129,7 +132,7 @@ struct CellParams {
     FaceMap fm;
     int nx, ny, nz, NX, NY, NZ;
     int MX, MY, MZ, ntiles, tiles_per_xcd;  // columns in x, y; z-segments; MX*MY*MZ
-    int seg_len;                            // cell layers per z-segment
+    int zb[kMaxSeg + 1];                    // z-segment boundaries (cell layers)
     int hist_cz0, n_hist_cells;
     int hist_write;  // 0: the updated consolidated fraction is used but not stored
     double hx, hy, hz, Lz;
@@ -151,7 +154,8 @@ struct PicardParams {
     double *slots;
     FaceMap fm;
     int nx, ny, nz, NX, NY, NZ;
-    int MX, MY, MZ, ntiles, tiles_per_xcd, seg_len;
+    int MX, MY, MZ, ntiles, tiles_per_xcd;
+    int zb[kMaxSeg + 1];
     int hist_cz0, n_hist_cells;
     double hx, hy, hz, Lz;
     double detJ, ih2x, ih2y, ih2z, inv_dt;
@@ -178,7 +182,8 @@ struct AdjointParams {
     FaceMap fm;
     double *partials;    // per column tile: source sensitivity of the step
     int nx, ny, nz, NX, NY, NZ;
-    int MX, MY, MZ, ntiles, tiles_per_xcd, seg_len;
+    int MX, MY, MZ, ntiles, tiles_per_xcd;
+    int zb[kMaxSeg + 1];
     int hist_cz0, n_hist_cells;
     double hx, hy, hz, Lz;
     double detJ, ih2x, ih2y, ih2z, dt;
@@ -212,9 +217,10 @@ struct HaloParams {
     double *Tout, *fout, *Cout;
     const double *slots;
     const Law<double> *nlaw;
-    int P, NX, NY, NZ, SX, SY, SZ, MX, MY, MZ;
+    int P, NX, NY, NZ, SX, SY, MX, MY, MZ;
+    int zb[kMaxSeg + 1];  // z-segment boundaries (cell layers)
     long long GX, GY, GZ;  // sizes of the x-, y- and z-face groups
-    FastDiv fNX, fNY, fNZ, fSX, fSY, fSZ;  // divisions of the face-node decode
+    FastDiv fNX, fNY, fNZ, fSX, fSY;  // divisions of the face-node decode
     double hx, hy, hz, dt, T_D;
     unsigned dmask;
     const unsigned char *dflag;  // per-dof Dirichlet flags (octree meshes), else NULL

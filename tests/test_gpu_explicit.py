@@ -72,6 +72,20 @@ def test_q2_run_reaches_melting_and_history():
     assert np.abs(rg - ro).max() <= 1e-9
 
 
+def test_q2_many_columns_segmented_run():
+    """A box with enough columns that the explicit kernel splits each column into
+    z-segments of several layers (a short top segment over longer ones) with ragged
+    x and y tails, run through melting: full-field parity with the oracle."""
+    need_gpu()
+    prob = W.small_nonlinear(nx=33, ny=33, nz=57, steps=20, track_length=0.5e-3, n_tracks=2)
+    Tg, rg, To, ro, info = _run_pair(prob, prob.steps, 2.5e-6)
+    mx, l2 = rel_errors(Tg, To)
+    print(f"33x33x57: max rel {mx:.2e} rel-L2 {l2:.2e} Tmax {To.max():.0f}")
+    assert To.max() > prob.T_l
+    assert mx <= TOL64 and l2 <= TOL64
+    assert np.abs(rg - ro).max() <= 1e-9
+
+
 @pytest.mark.parametrize("degree", [1, 2])
 def test_q1_q2_volume_source_run(degree):
     need_gpu()
@@ -131,6 +145,13 @@ def _sampled_nodes(prob, rng, T, n_random=160):
     # hottest nodes (melt pool) and their neighbourhood
     hot = np.argsort(T)[-48:]
     nodes.update(hot.tolist())
+    # whole node columns through every z-segment end: under the beam, and on an
+    # x and a y column face next to it
+    hi = int(hot[-1])
+    bi, bj = hi % NX, (hi // NX) % NY
+    fi, fj = (bi // 32) * 32 or 32, (bj // 32) * 32 or 32
+    for ci, cj in [(bi, bj), (fi, bj), (bi, fj), (fi, fj)]:
+        nodes.update(ci + NX * (cj + NY * k) for k in range(NZ))
     # tile faces, corners, the Dirichlet bottom and the last node
     for gi, gj, gk in [(16, 16, 8), (16, 5, 3), (5, 16, 3), (5, 5, 8), (0, 0, 0), (NX - 1, NY - 1, NZ - 1),
                        (NX - 1, 3, NZ - 1), (32, 32, 16), (NX // 2, NY // 2, NZ - 1)]:
