@@ -81,18 +81,34 @@ k_adjoint(const AdjointParams p)
         const int lx = tid % kTX, ly = tid / kTX;
         const int cx = kTX * tx + lx, cy = kTY * ty + ly;
         const bool active = cx < q.nx && cy < q.ny;
-        for (int idx = tid; idx < NB; idx += kTPB) {
-            const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
-            const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
-            double Tv = 0.0, av = 0.0;
-            const bool in = gi < q.NX && gj < q.NY;
-            const long long g = (long long)gi + (long long)q.NX * gj + NXY * gk;
-            if (in) Tv = q.T[g];
-            // C~ as in the forward step (nodal capacity, same hinge truncation)
-            const double C = node_capacity(law, Tv, gi, gj, gk, P, q.NX, q.NY, q.NZ, q.hx, q.hy, q.hz);
-            if (in && !on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ)) av = q.dt * q.lam[g] / C;
-            sT[0][idx] = Tv;
-            sT[1][idx] = av;
+        {
+            // all loads of the lane first (their latencies overlap), then the
+            // capacities and the LDS stores
+            constexpr int NL = (NB + kTPB - 1) / kTPB;
+            double Tv[NL], lv[NL];
+#pragma unroll
+            for (int e = 0; e < NL; ++e) {
+                const int idx = tid + e * kTPB;
+                const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
+                const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
+                const bool in = idx < NB && gi < q.NX && gj < q.NY;
+                const long long g = (long long)gi + (long long)q.NX * gj + NXY * gk;
+                Tv[e] = in ? q.T[g] : 0.0;
+                lv[e] = in ? q.lam[g] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < NL; ++e) {
+                const int idx = tid + e * kTPB;
+                if (idx >= NB) continue;
+                const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
+                const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
+                const bool in = gi < q.NX && gj < q.NY;
+                // C~ as in the forward step (nodal capacity, same hinge truncation)
+                const double C = node_capacity(law, Tv[e], gi, gj, gk, P, q.NX, q.NY, q.NZ, q.hx, q.hy, q.hz);
+                const bool unconstrained = in && !on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ);
+                sT[0][idx] = Tv[e];
+                sT[1][idx] = unconstrained ? q.dt * lv[e] / C : 0.0;
+            }
         }
         __syncthreads();
         auto gather = [&](int vec, double *u) {

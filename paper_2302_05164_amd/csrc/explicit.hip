@@ -376,14 +376,27 @@ k_cells(const CellParams<R> p)
     const int tpar = (tx & 1) | ((ty & 1) << 1) | ((seg & 1) << 2);
     const long long NXY = (long long)p.NX * p.NY;
 
-    // the N node planes of the first layer
-    for (unsigned idx = threadIdx.x; idx < unsigned(NB); idx += kTPB) {
-        const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
-        const unsigned li = rem % BX, lj = rem / BX;
-        const int gi = i0 + int(li), gj = j0 + int(lj), gk = P * z0 + int(lp);
-        double val = 0.0;
-        if (gi < p.NX && gj < p.NY) val = p.Tin[(long long)gi + (long long)p.NX * gj + NXY * gk];
-        sT[(gk % N) * PLANE + rem] = val;
+    // the N node planes of the first layer: every load of the lane is issued
+    // before the first store, so the latencies overlap
+    {
+        constexpr int NL = (NB + kTPB - 1) / kTPB;
+        double val[NL];
+#pragma unroll
+        for (int e = 0; e < NL; ++e) {
+            const unsigned idx = threadIdx.x + unsigned(e * kTPB);
+            const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
+            const unsigned li = rem % BX, lj = rem / BX;
+            const int gi = i0 + int(li), gj = j0 + int(lj), gk = P * z0 + int(lp);
+            val[e] = 0.0;
+            if (idx < unsigned(NB) && gi < p.NX && gj < p.NY)
+                val[e] = p.Tin[(long long)gi + (long long)p.NX * gj + NXY * gk];
+        }
+#pragma unroll
+        for (int e = 0; e < NL; ++e) {
+            const unsigned idx = threadIdx.x + unsigned(e * kTPB);
+            const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
+            if (idx < unsigned(NB)) sT[((P * z0 + int(lp)) % N) * PLANE + rem] = val[e];
+        }
     }
     __syncthreads();
 

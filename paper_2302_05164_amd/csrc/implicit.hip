@@ -287,10 +287,21 @@ k_picard_capply(const PicardParams p)
         const int lx = tid % kTX, ly = tid / kTX;
         const int cx = kTX * tx + lx, cy = kTY * ty + ly;
         const bool active = cx < q.nx && cy < q.ny;
-        for (int idx = tid; idx < NB; idx += kTPB) {
-            const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
-            const int gi = i0 + li, gj = j0 + lj;
-            sT[idx] = (gi < q.NX && gj < q.NY) ? q.x2[(long long)gi + (long long)q.NX * gj + NXY * (k0 + lk)] : 0.0;
+        {
+            // all loads of the lane first, so that their latencies overlap
+            constexpr int NL = (NB + kTPB - 1) / kTPB;
+            double xv[NL];
+#pragma unroll
+            for (int e = 0; e < NL; ++e) {
+                const int idx = tid + e * kTPB;
+                const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
+                const int gi = i0 + li, gj = j0 + lj;
+                xv[e] = (idx < NB && gi < q.NX && gj < q.NY)
+                            ? q.x2[(long long)gi + (long long)q.NX * gj + NXY * (k0 + lk)] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < NL; ++e)
+                if (tid + e * kTPB < NB) sT[tid + e * kTPB] = xv[e];
         }
         __syncthreads();
         double fe[NN];
