@@ -56,7 +56,7 @@ k_adjoint(const AdjointParams p)
     constexpr int BX = P * kTX + 1, BY = P * kTY + 1, PLANE = BX * BY, NB = N * PLANE;
     constexpr int NSH = N * N + P * N;
     using TB = Tables<P>;
-    __shared__ double sT[2][NB];  // T_n, a
+    __shared__ double sT[3][NB];  // T_n, a, node term of lambda_n (below)
     __shared__ double sS[NSH * kTPB];
     __shared__ double sC[N * N * kTPB];
 
@@ -82,10 +82,13 @@ k_adjoint(const AdjointParams p)
         const int cx = kTX * tx + lx, cy = kTY * ty + ly;
         const bool active = cx < q.nx && cy < q.ny;
         {
-            // all loads of the lane first (their latencies overlap), then the
-            // capacities and the LDS stores
+            // all loads of the lane first (their latencies overlap); then, per
+            // node of the block, the capacity c(T_n) and its slope (hinge sums one
+            // hinge at a time, each coefficient read once), a = dt lambda / C~ and
+            // the node term lambda - lambda (T_{n+1} - T_n) c'(T_n) / c(T_n) of
+            // lambda_n (zero at Dirichlet nodes)
             constexpr int NL = (NB + kTPB - 1) / kTPB;
-            double Tv[NL], lv[NL];
+            double Tv[NL], lv[NL], t1v[NL];
 #pragma unroll
             for (int e = 0; e < NL; ++e) {
                 const int idx = tid + e * kTPB;
@@ -95,7 +98,25 @@ k_adjoint(const AdjointParams p)
                 const long long g = (long long)gi + (long long)q.NX * gj + NXY * gk;
                 Tv[e] = in ? q.T[g] : 0.0;
                 lv[e] = in ? q.lam[g] : 0.0;
+                t1v[e] = in ? q.Tn1[g] : 0.0;
             }
+            double c[NL], cs[NL];
+#pragma unroll
+            for (int e = 0; e < NL; ++e) {
+                c[e] = law.c0;
+                cs[e] = 0.0;
+            }
+            for (int i = 0; i < law.n_hinge; ++i) {
+                const double bi = law.b[i], dci = law.dc[i];
+#pragma unroll
+                for (int e = 0; e < NL; ++e) {
+                    const double x = Tv[e] - bi;
+                    c[e] = __builtin_fma(dci, fmax0(x, 0.0), c[e]);
+                    cs[e] += x >= 0.0 ? dci : 0.0;
+                }
+            }
+            const double b_lo = law.n_hinge > 0 ? double(law.b[0]) : 0.0;
+            const double b_hi = law.n_hinge > 0 ? double(law.b[law.n_hinge - 1]) : 0.0;
 #pragma unroll
             for (int e = 0; e < NL; ++e) {
                 const int idx = tid + e * kTPB;
@@ -103,11 +124,18 @@ k_adjoint(const AdjointParams p)
                 const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
                 const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
                 const bool in = gi < q.NX && gj < q.NY;
-                // C~ as in the forward step (nodal capacity, same hinge truncation)
-                const double C = node_capacity(law, Tv[e], gi, gj, gk, P, q.NX, q.NY, q.NZ, q.hx, q.hy, q.hz);
+                const double T = Tv[e];
+                if (law.n_hinge == 0 || !(T > b_lo) || T >= b_hi) cs[e] = 0.0;
+                if (T >= law.Ts && T <= law.Tl) c[e] += law.lat;
+                // C~ as in the forward step (nodal capacity)
+                const double m = lumped_mass_1d(gi, q.NX, P, q.hx) * lumped_mass_1d(gj, q.NY, P, q.hy) *
+                                 lumped_mass_1d(gk, q.NZ, P, q.hz);
+                const double C = law.rho * c[e] * m;
                 const bool unconstrained = in && !on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ);
-                sT[0][idx] = Tv[e];
-                sT[1][idx] = unconstrained ? q.dt * lv[e] / C : 0.0;
+                const double lam = lv[e];
+                sT[0][idx] = T;
+                sT[1][idx] = unconstrained ? q.dt * lam / C : 0.0;
+                sT[2][idx] = unconstrained ? lam - lam * (t1v[e] - T) * (cs[e] / c[e]) : 0.0;
             }
         }
         __syncthreads();
@@ -141,11 +169,52 @@ k_adjoint(const AdjointParams p)
             while (nh < law.n_hinge && __any(tmax >= law.b[nh])) ++nh;
             const double b_first = law.n_hinge > 0 ? double(law.b[0]) : 0.0;
             const double b_last = law.n_hinge > 0 ? double(law.b[law.n_hinge - 1]) : 0.0;
+            // hinge sums of every point, one hinge at a time (each coefficient
+            // read once per cell; every point adds its hinges in increasing order)
+            double kq[NN], ksq[NN];
+#pragma unroll
+            for (int a = 0; a < NN; ++a) {
+                kq[a] = law.k0;
+                ksq[a] = 0.0;
+            }
+            for (int i = 0; i < nh; ++i) {
+                const double bi = law.b[i], dki = law.dk[i];
+#pragma unroll
+                for (int a = 0; a < NN; ++a) {
+                    const double x = vT[a] - bi;
+                    kq[a] = __builtin_fma(dki, fmax0(x, 0.0), kq[a]);
+                    ksq[a] += x >= 0.0 ? dki : 0.0;
+                }
+            }
+            // the Gaussian once per (x, y) column of points (its exponent does not depend on z)
+            double sq[N * N];
+            if (src_cell) {
+                sfor<0, N * N>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value % N, j = decltype(ic)::value / N;
+                    constexpr double xi = TB::gp(i), et = TB::gp(j);
+                    const double dxb = (cx + xi) * q.hx - q.xb, dyb = (cy + et) * q.hy - q.yb;
+                    sq[decltype(ic)::value] = exp(-(dxb * dxb + dyb * dyb) * q.two_over_R2);
+                });
+            }
 #pragma unroll
             for (int a = 0; a < NN; ++a) w[a] = 0.0;
+            // history r and its adjoint mu of a z-plane of points, loaded together
+            // before the plane (the mu stores would otherwise order each point's
+            // loads behind the previous point's store)
+            double rpl[N * N], mul[N * N];
             sfor<0, NN>([&](auto qc) {
                 constexpr int qq = decltype(qc)::value;
                 constexpr int qx = qq % N, qy = (qq / N) % N, qz = qq / (N * N);
+                if constexpr (qx == 0 && qy == 0) {
+                    if (has_hist) {
+#pragma unroll
+                        for (int j = 0; j < N * N; ++j) {
+                            const long long hj = (long long)(qz * N * N + j) * q.n_hist_cells + hc;
+                            rpl[j] = q.hist[hj];
+                            mul[j] = q.mu[hj];
+                        }
+                    }
+                }
                 auto tx_ = [&](auto rc) { return vT[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
                 auto ty_ = [&](auto rc) { return vT[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
                 auto tz_ = [&](auto rc) { return vT[tidx<N, 2>(decltype(rc)::value, qx, qy)]; };
@@ -159,20 +228,15 @@ k_adjoint(const AdjointParams p)
                 const double gay = rowdot<TagD<P>, qy, 0, N, false>(ay_, 0.0);
                 const double gaz = rowdot<TagD<P>, qz, 0, N, false>(az_, 0.0);
                 const double T = vT[qq];
-                double kpl = law.k0, ks = 0.0;
-                for (int i = 0; i < nh; ++i) {
-                    const double x = T - law.b[i];
-                    kpl = __builtin_fma(law.dk[i], fmax0(x, 0.0), kpl);
-                    ks += x >= 0.0 ? double(law.dk[i]) : 0.0;
-                }
-                if (!(T > b_first) || T >= b_last) ks = 0.0;
+                const double kpl = kq[qq];
+                const double ks = (!(T > b_first) || T >= b_last) ? 0.0 : ksq[qq];
                 constexpr double wq = TB::gw(qx) * TB::gw(qy) * TB::gw(qz);
                 const double W = wq * q.detJ;
                 double rn = 1.0, rp = 1.0, gl = 0.0;
                 long long hi = 0;
                 if (has_hist) {
                     hi = (long long)qq * q.n_hist_cells + hc;
-                    rp = q.hist[hi];
+                    rp = rpl[qy * N + qx];
                     gl = fmin0(fmax0((T - law.Ts) * law.inv_dT, 0.0), 1.0);
                     rn = gl > rp ? gl : rp;
                 }
@@ -181,7 +245,7 @@ k_adjoint(const AdjointParams p)
                 const double kbar = -W * (q.ih2x * gTx * gax + q.ih2y * gTy * gay + q.ih2z * gTz * gaz);
                 double Tbar = kbar * (ks * phase);
                 if (has_hist) {
-                    const double rbar = __builtin_fma(kbar, kpl * (1.0 - law.phi), q.mu[hi]);
+                    const double rbar = __builtin_fma(kbar, kpl * (1.0 - law.phi), mul[qy * N + qx]);
                     if (gl > rp) {  // the max took g: the adjoint flows to T
                         const double gp = T < law.Tl ? double(law.inv_dT) : 0.0;
                         Tbar = __builtin_fma(rbar, gp, Tbar);
@@ -201,12 +265,9 @@ k_adjoint(const AdjointParams p)
                     if constexpr (dz != 0.0) w[tidx<N, 2>(r, qx, qy)] = __builtin_fma(dz, Fz, w[tidx<N, 2>(r, qx, qy)]);
                 });
                 if (src_cell) {
-                    constexpr double xi = TB::gp(qx), et = TB::gp(qy), ze = TB::gp(qz);
+                    constexpr double ze = TB::gp(qz);
                     const double depth = q.Lz - (cz + ze) * q.hz;
-                    if (depth >= 0.0 && depth <= q.h_powder) {
-                        const double dxb = (cx + xi) * q.hx - q.xb, dyb = (cy + et) * q.hy - q.yb;
-                        src_acc += W * va[qq] * q.src_unit * exp(-(dxb * dxb + dyb * dyb) * q.two_over_R2);
-                    }
+                    if (depth >= 0.0 && depth <= q.h_powder) src_acc += W * va[qq] * q.src_unit * sq[qy * N + qx];
                 }
             });
             sweep<TagSt<P>, N, 0>(w, t1);
@@ -235,13 +296,7 @@ k_adjoint(const AdjointParams p)
             owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, seg, cz == z0, cz == z1 - 1,
                                 q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
                                 [&](long long g, int gi, int gj, int gk, int ax, int ay, int az, double fs) {
-                const int li = (az * BY + P * ly + ay) * BX + P * lx + ax;
-                double base = 0.0;
-                if (!on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ)) {
-                    const double lam = q.lam[g], Tn = sT[0][li];
-                    base = lam - lam * (q.Tn1[g] - Tn) * capacity_log_slope(law, Tn);
-                }
-                q.lam_out[g] = base + fs;
+                q.lam_out[g] = sT[2][(az * BY + P * ly + ay) * BX + P * lx + ax] + fs;
             });
         }
         __syncthreads();
