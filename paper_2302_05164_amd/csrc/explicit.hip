@@ -81,9 +81,19 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
             });
         }
     }
+    // general cells: the history of a z-plane of points, loaded together before
+    // the plane (the updates would otherwise order each point's load behind the
+    // previous point's store)
+    R rpl[FAST ? 1 : N * N];
     sfor<0, NN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+        if constexpr (!FAST && qx == 0 && qy == 0) {
+            if (has_hist) {
+#pragma unroll
+                for (int j = 0; j < N * N; ++j) rpl[j] = R(p.hist[(long long)(qz * N * N + j) * p.n_hist_cells + hc]);
+            }
+        }
         // reference gradient by Gauss-point collocation
         auto gxf = [&](auto rc) { return v[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
         auto gyf = [&](auto rc) { return v[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
@@ -106,7 +116,7 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
             k = kpl;
             if (has_hist) {
                 const long long hi = (long long)q * p.n_hist_cells + hc;
-                R r = R(p.hist[hi]);
+                R r = rpl[qy * N + qx];
                 if (melt) {
                     const R g = fmin0(fmax0((T - law.Ts) * law.inv_dT, R(0)), R(1));
                     if (g > r) {  // r_c = max(r_c, g): update before use
