@@ -287,6 +287,13 @@ k_picard_capply(const PicardParams p)
         const int lx = tid % kTX, ly = tid / kTX;
         const int cx = kTX * tx + lx, cy = kTY * ty + ly;
         const bool active = cx < q.nx && cy < q.ny;
+        // the cell's conductivity weights, in flight with the block load below
+        const long long cell = (long long)cx + (long long)q.nx * (cy + (long long)q.ny * cz);
+        const double *cf = q.coef + cell;
+        const long long nc = q.ncells;
+        double kwq[NN];
+#pragma unroll
+        for (int a = 0; a < NN; ++a) kwq[a] = active ? cf[(long long)(NN + a) * nc] : 0.0;
         {
             // all loads of the lane first, so that their latencies overlap
             constexpr int NL = (NB + kTPB - 1) / kTPB;
@@ -306,10 +313,9 @@ k_picard_capply(const PicardParams p)
         __syncthreads();
         double fe[NN];
         if (active) {
-            const long long cell = (long long)cx + (long long)q.nx * (cy + (long long)q.ny * cz);
-            const double *cf = q.coef + cell;
-            const long long nc = q.ncells;
             double u[NN], t1[NN], t2[NN], m[NN];
+#pragma unroll
+            for (int a = 0; a < NN; ++a) m[a] = cf[(long long)a * nc];  // capacity weights, before the sweeps
 #pragma unroll
             for (int a = 0; a < NN; ++a) {
                 const int ax = a % N, ay = (a / N) % N, az = a / (N * N);
@@ -319,11 +325,11 @@ k_picard_capply(const PicardParams p)
             sweep<TagS<P>, N, 1>(t1, t2);
             sweep<TagS<P>, N, 2>(t2, u);
 #pragma unroll
-            for (int a = 0; a < NN; ++a) m[a] = cf[(long long)a * nc] * u[a];
+            for (int a = 0; a < NN; ++a) m[a] = m[a] * u[a];
             sfor<0, NN>([&](auto qc) {
                 constexpr int qq = decltype(qc)::value;
                 constexpr int qx = qq % N, qy = (qq / N) % N, qz = qq / (N * N);
-                const double kw = cf[(long long)(NN + qq) * nc];
+                const double kw = kwq[qq];
                 auto gxf = [&](auto rc) { return u[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
                 auto gyf = [&](auto rc) { return u[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
                 auto gzf = [&](auto rc) { return u[tidx<N, 2>(decltype(rc)::value, qx, qy)]; };
@@ -339,13 +345,26 @@ k_picard_capply(const PicardParams p)
                 });
             });
             if constexpr (NEWTON) {
+                // the Newton coefficients of a z-plane of points, loaded together
+                double nk[N * N], ngx[N * N], ngy[N * N], ngz[N * N];
                 sfor<0, NN>([&](auto qc) {
                     constexpr int qq = decltype(qc)::value;
                     constexpr int qx = qq % N, qy = (qq / N) % N, qz = qq / (N * N);
-                    const double kd = cf[(long long)(2 * NN + qq) * nc] * u[qq];
-                    const double Fx = kd * q.ih2x * cf[(long long)(3 * NN + qq) * nc];
-                    const double Fy = kd * q.ih2y * cf[(long long)(4 * NN + qq) * nc];
-                    const double Fz = kd * q.ih2z * cf[(long long)(5 * NN + qq) * nc];
+                    if constexpr (qx == 0 && qy == 0) {
+#pragma unroll
+                        for (int j = 0; j < N * N; ++j) {
+                            const long long o = (long long)(qz * N * N + j) * nc;
+                            nk[j] = cf[2 * NN * nc + o];
+                            ngx[j] = cf[3 * NN * nc + o];
+                            ngy[j] = cf[4 * NN * nc + o];
+                            ngz[j] = cf[5 * NN * nc + o];
+                        }
+                    }
+                    constexpr int j = qy * N + qx;
+                    const double kd = nk[j] * u[qq];
+                    const double Fx = kd * q.ih2x * ngx[j];
+                    const double Fy = kd * q.ih2y * ngy[j];
+                    const double Fz = kd * q.ih2z * ngz[j];
                     sfor<0, N>([&](auto rc) {
                         constexpr int r = decltype(rc)::value;
                         constexpr double dx = TB::D(qx, r), dy = TB::D(qy, r), dz = TB::D(qz, r);
