@@ -280,6 +280,23 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
     const FaceMap fm = face_map_of(q);
 #pragma unroll
     for (int az = 0; az < N; ++az) {
+        // capacities of the plane's nodes, one hinge at a time (each law
+        // coefficient read once per plane; every node adds its hinges in
+        // increasing order)
+        double cpl[N * N];
+        if (az < P || last) {
+#pragma unroll
+            for (int j = 0; j < N * N; ++j) {
+                const double T = sTz[az][(j / N) * BX + j % N];
+                cpl[j] = c0 + ((T >= Ts && T <= Tl) ? lat : 0.0);
+            }
+            for (int h = 0; h < nh; ++h) {
+                const double bh = L.b[h], dch = L.dc[h];
+#pragma unroll
+                for (int j = 0; j < N * N; ++j)
+                    cpl[j] = __builtin_fma(dch, fmax0(sTz[az][(j / N) * BX + j % N] - bh, 0.0), cpl[j]);
+            }
+        }
 #pragma unroll
         for (int ay = 0; ay < N; ++ay) {
 #pragma unroll
@@ -311,8 +328,7 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
                 const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1) ||
                                   is_face(gi, P * kTX, NX) || is_face(gj, P * kTY, NY);
                 const double T = sTz[az][ay * BX + ax];
-                double c = c0 + ((T >= Ts && T <= Tl) ? lat : 0.0);
-                for (int h = 0; h < nh; ++h) c = __builtin_fma(L.dc[h], fmax0(T - L.b[h], 0.0), c);
+                const double c = cpl[ay * N + ax];
                 const double m = lumped_mass_1d(gi, NX, P, hx) * lumped_mass_1d(gj, NY, P, hy) *
                                  lumped_mass_1d(gk, NZ, P, hz);
                 const double C = rho * c * m;
