@@ -37,7 +37,11 @@ constexpr int kATY = 4;
 __device__ __forceinline__ double capacity_log_slope(ConstLaw<double> &L, double T)
 {
     double c = L.c0, cs = 0.0;
-    for (int i = 0; i < L.n_hinge; ++i) {
+    // unrolled over the table size with a uniform guard, so that the law's
+    // coefficients are loaded together instead of one round trip per hinge
+#pragma unroll
+    for (int i = 0; i < kMaxBp; ++i) {
+        if (i >= L.n_hinge) break;
         const double x = T - L.b[i];
         c = __builtin_fma(L.dc[i], fmax0(x, 0.0), c);
         cs += x >= 0.0 ? L.dc[i] : 0.0;
