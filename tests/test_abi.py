@@ -89,3 +89,22 @@ def test_mesh_info_and_history_layers():
         assert nhl == 2 and nhc == 2 * 128 * 128 and nhq == 27 * nhc
     finally:
         L.pbf_destroy(ctx)
+
+
+def test_workspace_sizes_face_slots_and_rejects_oversized_boxes():
+    """The parity-slot storage holds one entry per column-face node (8 parities),
+    not one per node, and a box whose face nodes exceed the 32-bit index range of
+    the face kernels is rejected at workspace sizing with a message."""
+    L, ctx = _ctx()
+    try:
+        b = C.c_size_t()
+        assert L.pbf_mesh_box(ctx, 2, 128, 128, 64, 4e-3, 4e-3, 2e-3) == 0
+        assert L.pbf_workspace_bytes(ctx, C.byref(b)) == 0
+        n = 257 * 257 * 129
+        # 11 vectors of n doubles plus slots far below 8 n doubles (cfg2: ~0.93 M face nodes)
+        assert 11 * 8 * n < b.value < 11 * 8 * n + 8 * 8 * 1_000_000 + 2 * 2**30
+        assert L.pbf_mesh_box(ctx, 2, 4096, 4096, 4096, 1.0, 1.0, 1.0) == 0
+        assert L.pbf_workspace_bytes(ctx, C.byref(b)) != 0
+        assert b"too large" in L.pbf_last_error(ctx)
+    finally:
+        L.pbf_destroy(ctx)
