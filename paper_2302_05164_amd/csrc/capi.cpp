@@ -88,6 +88,8 @@ struct pbf_ctx {
     // kernel timing: 4 events per timed step (cell kernel start/stop, face kernel
     // start/stop), on every `timing_every`-th explicit step
     std::vector<hipEvent_t> tev;
+    hipEvent_t ev_read = nullptr;  // completion of a small device-to-host read (Krylov loops)
+    double *h_read = nullptr;      // pinned host scalars of that read
     size_t tev_used = 0;
     bool timing = false;
     int timing_every = 1;
@@ -997,6 +999,8 @@ void pbf_destroy(pbf_ctx *ctx)
 {
     if (!ctx) return;
     for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
+    if (ctx->ev_read) (void)hipEventDestroy(ctx->ev_read);
+    if (ctx->h_read) (void)hipHostFree(ctx->h_read);
     delete ctx;
 }
 
@@ -1540,10 +1544,16 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
             }
             PBF_HIP(c, launch_cg_pap(p, Ap, c->d_partials, c->d_scal, N, s));
             PBF_HIP(c, launch_cg_update(x, r, z, p, Ap, diag, c->d_partials, c->d_scal, rz_old, N, s));
-            PBF_HIP(c, hipMemcpyAsync(&rr, c->d_scal + CG_RR, sizeof(double), hipMemcpyDeviceToHost, s));
-            PBF_HIP(c, hipStreamSynchronize(s));
+            // |r|^2 into pinned memory; the next direction is computed while the
+            // host waits for that read only (the direction is unused when the loop ends)
+            if (!c->ev_read) PBF_HIP(c, hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));
+            if (!c->h_read) PBF_HIP(c, hipHostMalloc((void **)&c->h_read, 8 * sizeof(double), hipHostMallocDefault));
+            PBF_HIP(c, hipMemcpyAsync(c->h_read, c->d_scal + CG_RR, sizeof(double), hipMemcpyDeviceToHost, s));
+            PBF_HIP(c, hipEventRecord(c->ev_read, s));
             const int rz_new = rz_old == CG_RZ0 ? CG_RZ1 : CG_RZ0;
             PBF_HIP(c, launch_cg_direction(p, z, c->d_scal, rz_old, rz_new, N, s));
+            PBF_HIP(c, hipEventSynchronize(c->ev_read));
+            rr = c->h_read[0];
             rz_old = rz_new;
             ++k;
             last_rel = std::sqrt(rr) / bn;
