@@ -248,10 +248,14 @@ __device__ __forceinline__ void owner_nodes(const R *fe, const double *sS, doubl
     constexpr int N = P + 1, kTPB = kTX * kTY;
     const bool hasR = lx < kTX - 1 && cx + 1 < nx;
     const bool hasU = ly < kTY - 1 && cy + 1 < ny;
+    // nodes with local y = 0 belong to the lanes of the column's first row only
+    // (all in the first wavefront): the other wavefronts skip them as a whole
+    const bool has_row0 = __builtin_amdgcn_readfirstlane(tid) < kTX;
 #pragma unroll
     for (int az = 0; az < N; ++az) {
 #pragma unroll
         for (int ay = 0; ay < N; ++ay) {
+            if (ay == 0 && !has_row0) continue;  // uniform
 #pragma unroll
             for (int ax = 0; ax < N; ++ax) {
                 if ((ax == 0 && lx != 0) || (ay == 0 && ly != 0)) continue;

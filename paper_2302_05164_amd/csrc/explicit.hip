@@ -278,6 +278,9 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
     const unsigned dmask = q.dmask;
     const double hx = q.hx, hy = q.hy, hz = q.hz, dt = q.dt, T_D = q.T_D;
     const FaceMap fm = face_map_of(q);
+    // nodes with local y = 0 belong to the lanes of the column's first row only
+    // (all in the first wavefront): the other wavefronts skip them as a whole
+    const bool has_row0 = __builtin_amdgcn_readfirstlane(tid) < kTX;
 #pragma unroll
     for (int az = 0; az < N; ++az) {
         // capacities of the plane's nodes, one hinge at a time (each law
@@ -299,6 +302,7 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
         }
 #pragma unroll
         for (int ay = 0; ay < N; ++ay) {
+            if (ay == 0 && !has_row0) continue;  // uniform
 #pragma unroll
             for (int ax = 0; ax < N; ++ax) {
                 const int n = (az * N + ay) * N + ax;
