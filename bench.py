@@ -213,6 +213,41 @@ def implicit_timing(sim, T, rc, t, dt=1e-4):
     return res
 
 
+def octree_timing(steps=300, warmup=20):
+    """Explicit steps on the octree workload: Q2 over a 10x10x5 mm part, coarse
+    20x20x10 cells refined to level 6 around the scan path (hanging nodes through
+    their constraints), the state resident in HBM; HIP events on the library's
+    stream around the timed steps."""
+    import ctypes as C
+
+    import torch
+
+    import pbf_workloads as W
+    from paper_2302_05164_amd import pbftherm
+
+    prob = W.cfg3()
+    sim = pbftherm.from_problem(prob, device="cuda:0")
+    n = sim.info()["n_dofs"]
+    nl, nh, ml = C.c_int64(), C.c_int64(), C.c_int()
+    sim._check(sim.lib.pbf_octree_info(sim.ctx, C.byref(nl), C.byref(nh), C.byref(ml)))
+    v0 = torch.tensor(W.seeded_vector(n, 1), device="cuda")
+    dt = prob.dt_factor * 2.0 / sim.stability_lambda(v0, 50)
+    T, rc = sim.init_state(prob.T0)
+    T_tmp = torch.empty_like(T)
+    sim.explicit_steps(T, rc, 0.0, dt, warmup, T_tmp=T_tmp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    sim.explicit_steps(T, rc, warmup * dt, dt, steps, T_tmp=T_tmp)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"workload": prob.name, "n_dofs": n, "leaves": nl.value, "hanging_nodes": nh.value,
+            "max_level": ml.value, "steps": steps, "ms_per_step": ms / steps,
+            "value": n * steps / (ms / 1e3), "unit": "DoF-updates/s",
+            "finite": bool(torch.isfinite(T).all().item()), "T_max": float(T.max().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +258,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-operator timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-step timing")
+    ap.add_argument("--no-octree", action="store_true", help="skip the octree-mesh timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -336,6 +372,8 @@ def main():
     del end_state
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
+    if not args.no_octree:
+        out["octree"] = octree_timing()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
