@@ -99,7 +99,7 @@ __device__ __forceinline__ void surface_flux(const OctParams &p, const CellGeo &
 
 // explicit step / assembly: element vectors of diffusion, source and surface flux
 template <int P>
-__global__ void __launch_bounds__(kOctThreads) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kOctThreads) __attribute__((amdgpu_waves_per_eu(P == 2 ? 1 : 2)))
 k_oct_cells(const OctParams p)
 {
     using TB = Tables<P>;
@@ -114,11 +114,47 @@ k_oct_cells(const OctParams p)
     sweep<TagS<P>, N, 1>(t1, t2);
     sweep<TagS<P>, N, 2>(t2, v);
     const int hc = p.has_hist ? p.m.cell_hist[c] : -1;
+    // hinge sums of all points, one hinge at a time (each coefficient read once;
+    // every point adds its hinges in increasing order); hinges that no point of
+    // the wave exceeds add exactly zero and are skipped
+    double tmax = v[0];
+#pragma unroll
+    for (int a = 1; a < NN; ++a) tmax = fmax0(tmax, v[a]);
+    int nh = 0;
+    while (nh < law.n_hinge && __any(tmax > law.b[nh])) ++nh;
+    double kq[NN];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) kq[a] = law.k0;
+    for (int i = 0; i < nh; ++i) {
+        const double bi = law.b[i], dki = law.dk[i];
+#pragma unroll
+        for (int a = 0; a < NN; ++a) kq[a] = __builtin_fma(dki, fmax0(v[a] - bi, 0.0), kq[a]);
+    }
+    // the volume source's Gaussian once per (x, y) column of points
+    const bool vol_src = p.laser_on && p.laser_kind == 1;
+    double sq[N * N];
+    if (vol_src) {
+        sfor<0, N * N>([&](auto ic) {
+            constexpr int i = decltype(ic)::value % N, j = decltype(ic)::value / N;
+            constexpr double xi = TB::gp(i), et = TB::gp(j);
+            const double dxb = g.x0 + xi * g.hx - p.xb, dyb = g.y0 + et * g.hy - p.yb;
+            sq[decltype(ic)::value] = p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2);
+        });
+    }
 #pragma unroll
     for (int a = 0; a < NN; ++a) w[a] = 0.0;
+    // history of a z-plane of points, loaded together before the plane (the
+    // updates would otherwise order each point's load behind the previous store)
+    double rpl[N * N];
     sfor<0, NN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+        if constexpr (qx == 0 && qy == 0) {
+            if (hc >= 0) {
+#pragma unroll
+                for (int j = 0; j < N * N; ++j) rpl[j] = p.hist[(long long)(qz * N * N + j) * p.m.n_hist_cells + hc];
+            }
+        }
         auto gxf = [&](auto rc) { return v[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
         auto gyf = [&](auto rc) { return v[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
         auto gzf = [&](auto rc) { return v[tidx<N, 2>(decltype(rc)::value, qx, qy)]; };
@@ -126,12 +162,11 @@ k_oct_cells(const OctParams p)
         const double gy = rowdot<TagD<P>, qy, 0, N, false>(gyf, 0.0);
         const double gz = rowdot<TagD<P>, qz, 0, N, false>(gzf, 0.0);
         const double T = v[q];
-        double kpl = law.k0;
-        for (int i = 0; i < law.n_hinge; ++i) kpl = __builtin_fma(law.dk[i], fmax0(T - law.b[i], 0.0), kpl);
+        const double kpl = kq[q];
         double k = kpl;
         if (hc >= 0) {  // consolidated fraction: r = max(r, g), updated before use
             const long long hi = (long long)q * p.m.n_hist_cells + hc;
-            double r = p.hist[hi];
+            double r = rpl[qy * N + qx];
             const double gl = fmin0(fmax0((T - law.Ts) * law.inv_dT, 0.0), 1.0);
             if (gl > r) {
                 r = gl;
@@ -149,13 +184,10 @@ k_oct_cells(const OctParams p)
             if constexpr (dy != 0.0) w[tidx<N, 1>(r, qx, qz)] = __builtin_fma(dy, Fy, w[tidx<N, 1>(r, qx, qz)]);
             if constexpr (dz != 0.0) w[tidx<N, 2>(r, qx, qy)] = __builtin_fma(dz, Fz, w[tidx<N, 2>(r, qx, qy)]);
         });
-        if (p.laser_on && p.laser_kind == 1) {
-            constexpr double xi = TB::gp(qx), et = TB::gp(qy), ze = TB::gp(qz);
+        if (vol_src) {
+            constexpr double ze = TB::gp(qz);
             const double depth = p.m.Lz - (g.z0 + ze * g.hz);
-            if (depth >= 0.0 && depth <= p.h_powder) {
-                const double dxb = g.x0 + xi * g.hx - p.xb, dyb = g.y0 + et * g.hy - p.yb;
-                w[q] = __builtin_fma(wq * g.detJ, p.src_amp * exp(-(dxb * dxb + dyb * dyb) * p.two_over_R2), w[q]);
-            }
+            if (depth >= 0.0 && depth <= p.h_powder) w[q] = __builtin_fma(wq * g.detJ, sq[qy * N + qx], w[q]);
         }
     });
     sweep<TagSt<P>, N, 0>(w, t1);
