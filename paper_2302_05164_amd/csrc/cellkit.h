@@ -394,11 +394,18 @@ __device__ __forceinline__ void integrate3(const double *in, double *out)
 }
 
 // conductivity at a Gauss point with the lagged consolidated fraction
+// (The hinge loops below are unrolled over the table size with a uniform exit,
+// so that the law's coefficients are loaded together rather than one scalar
+// round trip per hinge; the sums keep the increasing hinge order.)
 template <typename L>
 __device__ __forceinline__ double law_k(L &law, double T, double r)
 {
     double kpl = law.k0;
-    for (int i = 0; i < law.n_hinge; ++i) kpl = __builtin_fma(law.dk[i], fmax0(T - law.b[i], 0.0), kpl);
+#pragma unroll
+    for (int i = 0; i < kMaxBp; ++i) {
+        if (i >= law.n_hinge) break;
+        kpl = __builtin_fma(law.dk[i], fmax0(T - law.b[i], 0.0), kpl);
+    }
     return kpl * (r + law.phi * (1.0 - r));
 }
 
@@ -409,8 +416,11 @@ template <typename L>
 __device__ __forceinline__ double law_kT(L &law, double T, double r)
 {
     double s = 0.0;
-    for (int i = 0; i < law.n_hinge; ++i)
+#pragma unroll
+    for (int i = 0; i < kMaxBp; ++i) {
+        if (i >= law.n_hinge) break;
         if (i == 0 ? T > law.b[0] : T >= law.b[i]) s += law.dk[i];
+    }
     return s * (r + law.phi * (1.0 - r));
 }
 
@@ -418,7 +428,11 @@ template <typename L>
 __device__ __forceinline__ double law_c(L &law, double T)
 {
     double c = law.c0;
-    for (int i = 0; i < law.n_hinge; ++i) c = __builtin_fma(law.dc[i], fmax0(T - law.b[i], 0.0), c);
+#pragma unroll
+    for (int i = 0; i < kMaxBp; ++i) {
+        if (i >= law.n_hinge) break;
+        c = __builtin_fma(law.dc[i], fmax0(T - law.b[i], 0.0), c);
+    }
     if (T >= law.Ts && T <= law.Tl) c += law.lat;
     return c;
 }
