@@ -301,15 +301,29 @@ __global__ void __launch_bounds__(256) k_oct_nodes(const OctNodeParams p)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= p.m.n_dofs) return;
+    // the dof's own values first, then its element entries four at a time (all
+    // loads of a chunk in flight together; the sum keeps the entry order)
+    const bool dir = p.m.dflag[i] != 0;
+    const double T = MODE <= 1 ? p.Tin[i] : 0.0;
+    const int e1 = p.m.nstart[i + 1];
+    int e = p.m.nstart[i];
     double f = 0.0;
-    for (int e = p.m.nstart[i]; e < p.m.nstart[i + 1]; ++e) {
+    for (; e + 4 <= e1; e += 4) {
+        double w[4], v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            w[j] = p.m.nw[e + j];
+            v[j] = p.m.E[p.m.nslot[e + j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f = __builtin_fma(MODE == 3 ? w[j] * w[j] : w[j], v[j], f);
+    }
+    for (; e < e1; ++e) {
         const double w = p.m.nw[e];
         f = __builtin_fma(MODE == 3 ? w * w : w, p.m.E[p.m.nslot[e]], f);
     }
-    const bool dir = p.m.dflag[i] != 0;
     if constexpr (MODE <= 1) {
         ConstLaw<double> &L = const_law(p.nlaw);
-        const double T = p.Tin[i];
         const double C = L.rho * law_c(L, T) * p.m.mass[i];
         if constexpr (MODE == 0) {
             p.Tout[i] = dir ? p.T_D : T + p.dt * f / C;
