@@ -37,10 +37,18 @@ __device__ __forceinline__ void oct_gather(const OctDev &m, const double *T, int
         double v;
         if (id >= 0) {
             v = T[id];
-        } else {
+        } else {  // hanging node: its constraint entries, loads of a pair in flight together
             const int h = -1 - id;
+            const int j1 = m.hstart[h + 1];
+            int j = m.hstart[h];
             v = 0.0;
-            for (int j = m.hstart[h]; j < m.hstart[h + 1]; ++j) v = __builtin_fma(m.hw[j], T[m.hdof[j]], v);
+            for (; j + 2 <= j1; j += 2) {
+                const double w0 = m.hw[j], w1 = m.hw[j + 1];
+                const double t0 = T[m.hdof[j]], t1 = T[m.hdof[j + 1]];
+                v = __builtin_fma(w0, t0, v);
+                v = __builtin_fma(w1, t1, v);
+            }
+            if (j < j1) v = __builtin_fma(m.hw[j], T[m.hdof[j]], v);
         }
         u[a] = v;
     }
