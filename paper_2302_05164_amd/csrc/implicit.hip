@@ -59,16 +59,30 @@ k_picard(const PicardParams p)
         const int lx = tid % kTX, ly = tid / kTX;
         const int cx = kTX * tx + lx, cy = kTY * ty + ly;
         const bool active = cx < q.nx && cy < q.ny;
-        for (int idx = tid; idx < NB; idx += kTPB) {
-            const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
-            const int gi = i0 + li, gj = j0 + lj;
-            const bool in = gi < q.NX && gj < q.NY;
-            const long long g = (long long)gi + (long long)q.NX * gj + NXY * (k0 + lk);
-            sT[0][idx] = in ? q.Tc[g] : 0.0;
-            sT[1][idx] = in ? q.Tk[g] : 0.0;
-            if constexpr (MODE == 0) {
-                sT[2][idx] = in ? q.x1[g] : 0.0;
-                sT[3][idx] = in ? q.x2[g] : 0.0;
+        {
+            // all loads of the lane first, so that their latencies overlap
+            constexpr int NL = (NB + kTPB - 1) / kTPB, NV = MODE == 0 ? 4 : 2;
+            double bv[NV][NL];
+#pragma unroll
+            for (int e = 0; e < NL; ++e) {
+                const int idx = tid + e * kTPB;
+                const int li = idx % BX, lj = (idx / BX) % BY, lk = idx / PLANE;
+                const int gi = i0 + li, gj = j0 + lj;
+                const bool in = idx < NB && gi < q.NX && gj < q.NY;
+                const long long g = (long long)gi + (long long)q.NX * gj + NXY * (k0 + lk);
+                bv[0][e] = in ? q.Tc[g] : 0.0;
+                bv[1][e] = in ? q.Tk[g] : 0.0;
+                if constexpr (MODE == 0) {
+                    bv[2][e] = in ? q.x1[g] : 0.0;
+                    bv[3][e] = in ? q.x2[g] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < NL; ++e) {
+                const int idx = tid + e * kTPB;
+                if (idx >= NB) continue;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sT[v][idx] = bv[v][e];
             }
         }
         __syncthreads();
