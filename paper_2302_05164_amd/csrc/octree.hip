@@ -31,25 +31,28 @@ template <int P>
 __device__ __forceinline__ void oct_gather(const OctDev &m, const double *T, int c, double *u)
 {
     constexpr int NN = (P + 1) * (P + 1) * (P + 1);
+    // all indices, then all regular values (loads in flight together; a hanging
+    // node reads dof 0 and is replaced below), then the hanging nodes'
+    // constraint sums, a pair of entries at a time (same summation order)
+    int id[NN];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) id[a] = m.cidx[(long long)a * m.n_cells + c];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) u[a] = T[id[a] >= 0 ? id[a] : 0];
 #pragma unroll
     for (int a = 0; a < NN; ++a) {
-        const int id = m.cidx[(long long)a * m.n_cells + c];
-        double v;
-        if (id >= 0) {
-            v = T[id];
-        } else {  // hanging node: its constraint entries, loads of a pair in flight together
-            const int h = -1 - id;
-            const int j1 = m.hstart[h + 1];
-            int j = m.hstart[h];
-            v = 0.0;
-            for (; j + 2 <= j1; j += 2) {
-                const double w0 = m.hw[j], w1 = m.hw[j + 1];
-                const double t0 = T[m.hdof[j]], t1 = T[m.hdof[j + 1]];
-                v = __builtin_fma(w0, t0, v);
-                v = __builtin_fma(w1, t1, v);
-            }
-            if (j < j1) v = __builtin_fma(m.hw[j], T[m.hdof[j]], v);
+        if (id[a] >= 0) continue;
+        const int h = -1 - id[a];
+        const int j1 = m.hstart[h + 1];
+        int j = m.hstart[h];
+        double v = 0.0;
+        for (; j + 2 <= j1; j += 2) {
+            const double w0 = m.hw[j], w1 = m.hw[j + 1];
+            const double t0 = T[m.hdof[j]], t1 = T[m.hdof[j + 1]];
+            v = __builtin_fma(w0, t0, v);
+            v = __builtin_fma(w1, t1, v);
         }
+        if (j < j1) v = __builtin_fma(m.hw[j], T[m.hdof[j]], v);
         u[a] = v;
     }
 }
@@ -213,7 +216,7 @@ k_oct_cells(const OctParams p)
 // Picard operator C(Tc)/dt + K(Tk) with the history held fixed: MODE 0 the
 // element vector of C x1 / dt + K x2 - f_vol, MODE 1 the element diagonal
 template <int P, int MODE>
-__global__ void __launch_bounds__(kOctThreads) __attribute__((amdgpu_waves_per_eu(P == 2 && MODE == 0 ? 1 : 2)))
+__global__ void __launch_bounds__(kOctThreads) __attribute__((amdgpu_waves_per_eu(P == 2 ? 1 : 2)))
 k_oct_picard(const OctParams p)
 {
     using TB = Tables<P>;
