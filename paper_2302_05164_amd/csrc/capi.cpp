@@ -1547,7 +1547,8 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
             // |r|^2 into pinned memory; the next direction is computed while the
             // host waits for that read only (the direction is unused when the loop ends)
             if (!c->ev_read) PBF_HIP(c, hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));
-            if (!c->h_read) PBF_HIP(c, hipHostMalloc((void **)&c->h_read, 8 * sizeof(double), hipHostMallocDefault));
+            if (!c->h_read)
+                PBF_HIP(c, hipHostMalloc((void **)&c->h_read, (2 * kGmMax + 8) * sizeof(double), hipHostMallocDefault));
             PBF_HIP(c, hipMemcpyAsync(c->h_read, c->d_scal + CG_RR, sizeof(double), hipMemcpyDeviceToHost, s));
             PBF_HIP(c, hipEventRecord(c->ev_read, s));
             const int rz_new = rz_old == CG_RZ0 ? CG_RZ1 : CG_RZ0;
@@ -1709,10 +1710,19 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
                 PBF_HIP(c, launch_maxpy(w, V, N, j + 1, nw.h1, N, s));
                 PBF_HIP(c, launch_mdot(w, V, N, j + 1, nw.partials, nw.h2, N, s));
                 PBF_HIP(c, launch_maxpy(w, V, N, j + 1, nw.h2, N, s));
-                PBF_HIP(c, hipMemcpyAsync(h1.data(), nw.h1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-                PBF_HIP(c, hipMemcpyAsync(h2.data(), nw.h2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-                double hn = 0.0;
-                if ((st = norm2(w, &hn))) return st;
+                PBF_HIP(c, launch_mdot(w, w, 0, 1, nw.partials, nw.hn, N, s));
+                // both projections and |w|^2 into pinned memory, one wait
+                if (!c->h_read)
+                    PBF_HIP(c, hipHostMalloc((void **)&c->h_read, (2 * kGmMax + 8) * sizeof(double),
+                                             hipHostMallocDefault));
+                double *pin = c->h_read;
+                PBF_HIP(c, hipMemcpyAsync(pin, nw.h1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                PBF_HIP(c, hipMemcpyAsync(pin + kGmMax, nw.h2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                PBF_HIP(c, hipMemcpyAsync(pin + 2 * kGmMax, nw.hn, sizeof(double), hipMemcpyDeviceToHost, s));
+                PBF_HIP(c, hipStreamSynchronize(s));
+                std::copy(pin, pin + j + 1, h1.begin());
+                std::copy(pin + kGmMax, pin + kGmMax + j + 1, h2.begin());
+                const double hn = std::sqrt(pin[2 * kGmMax]);
                 ++k;
                 for (int q = 0; q <= j; ++q) hc[q] = h1[q] + h2[q];
                 if (hn > 0) PBF_HIP(c, launch_div_scalar(Vn, w, hn, N, s));
