@@ -555,7 +555,7 @@ void launch_ty(int degree, int precision, int mode, const CellParams<double> &pd
 }  // namespace
 
 // 16 x 16 cells per column workgroup: measured fastest of 16x4, 16x8 and 16x16
-// on cfg2-size boxes (fewer column-face nodes, same per-lane work)
+// on 128x128x64 and 48x48x24 Q2 boxes (fewer column-face nodes, same per-lane work)
 int column_height() { return 16; }
 
 int resident_columns_per_cu(int ty) { return ty == 4 ? 8 : (ty == 8 ? 4 : 2); }
