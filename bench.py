@@ -2,10 +2,11 @@
 
 One "step" is one forward-Euler step of the whole hot path (sum-factorized
 operator, material law, laser source, lumped-mass update, tile-face completion)
-over the full mesh.  The default workload is the 128x128x64 Q2 box (8,520,321
-DoFs) with the seeded nonlinear law and the 10-track zigzag scan; the value is
-whole-job DoF-updates/s in FP64, inputs resident in HBM.  The FP32-operator
-variant is timed on the same workload and reported beside it.
+over the full mesh.  The default workload is the 160x160x80 Q2 box
+(16,589,601 DoFs, 4x4x2 mm) with the seeded nonlinear law and the 10-track
+zigzag scan; the value is whole-job DoF-updates/s in FP64, inputs resident in
+HBM.  The FP32-operator variant is timed on the same workload and reported
+beside it, with its error against the FP64 run after 5000 steps.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the build runs on one GPU.
 """
@@ -47,31 +48,47 @@ def algorithmic_counts(prob, info):
     return bytes_step, flops_step
 
 
-def cpu_baseline(prob, seconds_cap=60.0):
-    """The oracle (plain serial C) timed on a bounded sample: one explicit step
-    of the full workload mesh from its initial state."""
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, dt, steps=5):
+    """The oracle (plain serial C, one thread) timed on a bounded sample of the
+    workload: `steps` explicit steps of the full mesh at the benchmark's dt from
+    a seeded hot state (a melt pool under the beam, so the nonlinear law, the
+    latent heat and the source are all active)."""
     import oracle
+    import pbf_workloads as W
 
     o = oracle.Oracle(prob)
-    T = o.init_T()
+    T, t0 = W.hot_spot_state(prob, seed=17)
     rc = o.init_history()
-    dt = 2.5e-6
     t = time.perf_counter()
-    o.explicit_steps(T, rc, 0.0, dt, 1)
+    o.explicit_steps(T, rc, t0, dt, steps)
     el = time.perf_counter() - t
-    del np
-    return {"value": o.N / el, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 explicit step of {prob.name} ({o.N} DoFs) from the initial state, "
-                      f"serial C, {el:.2f} s"}
+    return {"value": o.N * steps / el, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{steps} explicit steps of {prob.name} ({o.N} DoFs, full mesh) at dt = {dt:.4e} s from "
+                      f"a seeded melt-pool state, serial C on one thread, {el:.2f} s"}
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_05164_amd", "csrc", "explicit.hip")
+# every source file the explicit cell kernel is compiled from
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_05164_amd", "csrc", f)
+                  for f in ("explicit.hip", "cellkit.h", "pbf_internal.h")]
 
 
 def kernel_source_hash():
     import hashlib
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def pmc_summary(fetch_dir, write_dir, out_path, workload, kernel="k_cells<2, double, 0"):
@@ -87,7 +104,8 @@ def pmc_summary(fetch_dir, write_dir, out_path, workload, kernel="k_cells<2, dou
             rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == name]
         return rows
 
-    run = ("python3 <repo>/bench.py --steps 30 --warmup 5 --no-cpu --no-fp32 --no-adjoint --no-implicit --calib-copy")
+    run = (f"python3 <repo>/bench.py --workload {workload} --steps 30 --warmup 5 --no-cpu --no-fp32 --no-adjoint "
+           "--no-implicit --no-octree --no-laplace --calib-copy")
     res = {"workload": workload, "kernel": kernel, "kernel_source_sha256_16": kernel_source_hash(),
            "commands": ["cd /tmp && export TMPDIR=/tmp",
                         f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/fetch -o run -- {run}",
@@ -133,6 +151,61 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     return nbytes
 
 
+def fp32_errors(sim, prob, dt, steps):
+    """Error of the FP32-operator run against the FP64 run after `steps` steps
+    from the initial state (the FP64 path is the one checked against the oracle
+    step by step, at these sizes on the whole field): max and relative-L2 error
+    over the whole field and over the melt pool {T_fp64 >= T_s}."""
+    import torch
+
+    out = {}
+    for prec in (64, 32):
+        T, rc = sim.init_state(prob.T0)
+        sim.explicit_steps(T, rc, 0.0, dt, steps, precision=prec)
+        out[prec] = T
+    torch.cuda.synchronize()
+    a, b = out[32], out[64]
+    d = a - b
+    pool = b >= prob.T_s
+    res = {"steps": steps, "dt": dt, "reference": "fp64 run of the same steps",
+           "max_abs_K": d.abs().max().item(),
+           "max_rel": (d.abs().max() / b.abs().max()).item(),
+           "rel_l2": (torch.linalg.norm(d) / torch.linalg.norm(b)).item(),
+           "max_rel_to_rise": (d.abs().max() / (b - prob.T0).abs().max()).item(),
+           "melt_pool_nodes": int(pool.sum().item())}
+    if res["melt_pool_nodes"]:
+        dp, bp = d[pool], b[pool]
+        res["melt_pool_max_abs_K"] = dp.abs().max().item()
+        res["melt_pool_max_rel"] = (dp.abs().max() / bp.abs().max()).item()
+        res["melt_pool_rel_l2"] = (torch.linalg.norm(dp) / torch.linalg.norm(bp)).item()
+    res["T_max_fp64"] = b.max().item()
+    # sensitivity of the model itself: the FP64 run from the same initial state
+    # perturbed by seeded +-1e-9 K (3e-12 relative, the FP64 parity scale); the
+    # apparent capacity jumps at T_s and T_l, so a node crossing them one step
+    # earlier or later changes its increment by a finite amount
+    import pbf_workloads as W
+    T, rc = sim.init_state(prob.T0)
+    T += torch.tensor(1e-9 * W.seeded_vector(T.numel(), 41), device=T.device)
+    sim.explicit_steps(T, rc, 0.0, dt, steps, precision=64)
+    torch.cuda.synchronize()
+    dq = T - b
+    res["fp64_perturbed_1e-9K"] = {"max_abs_K": dq.abs().max().item(),
+                                   "rel_l2": (torch.linalg.norm(dq) / torch.linalg.norm(b)).item()}
+    # one step of each operator from the same (FP64) state
+    one = {}
+    for prec in (64, 32):
+        T1, r1 = b.clone(), rc.clone()
+        sim.explicit_steps(T1, r1, steps * dt, dt, 1, precision=prec)
+        one[prec] = T1
+    torch.cuda.synchronize()
+    d1 = one[32] - one[64]
+    inc = one[64] - b
+    res["one_step"] = {"max_abs_K": d1.abs().max().item(),
+                       "max_rel": (d1.abs().max() / one[64].abs().max()).item(),
+                       "max_rel_to_increment": (d1.abs().max() / inc.abs().max()).item()}
+    return res
+
+
 def adjoint_timing(reps=1):
     """Adjoint/forward time ratio on the differentiation workload: the 48x48x24 Q2
     box with the seeded nonlinear law, 3000 explicit steps, 64 probes, gradients
@@ -149,7 +222,7 @@ def adjoint_timing(reps=1):
     sim = pbftherm.from_problem(prob, device="cuda:0")
     info = sim.info()
     v0 = torch.tensor(W.seeded_vector(info["n_dofs"], 1), device="cuda")
-    dt = prob.dt_factor * 2.0 / sim.stability_lambda(v0, 100)
+    dt = prob.dt_factor * sim.stability_dt(v0, 100)
     sim.set_probes(prob.probes, prob.targets)
     n, s = prob.steps, 30
     work = sim.gradient_work(s)
@@ -213,6 +286,34 @@ def implicit_timing(sim, T, rc, t, dt=1e-4):
     return res
 
 
+def laplace_timing(sim, info, prob, steps, warmup, step_ms, step_cell_ms):
+    """The constant-coefficient reference operator y = K x (unit conductivity,
+    no law, history, source, capacity or update) on the same mesh with the same
+    column kernels, timed like the explicit step; the explicit step's
+    throughput as a fraction of it (Section 5.1 reports 44% on CPUs)."""
+    import torch
+
+    x = torch.rand(info["n_dofs"], dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(warmup):
+        sim.laplace_apply(x, y)
+    torch.cuda.synchronize()
+    sim.timing_begin(steps, every=TIMING_EVERY)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sim.laplace_apply(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cell_ms, face_ms, _ = sim.timing_end()
+    n = info["n_dofs"]
+    return {"operator": "y = K x, unit conductivity, Q%d" % prob.degree, "ms_per_apply": ms,
+            "value": n / (ms / 1e3), "unit": "DoF/s", "kernel_ms": cell_ms, "face_kernel_ms": face_ms,
+            "explicit_step_fraction_of_laplace": ms / step_ms,
+            "explicit_kernel_fraction_of_laplace_kernel": cell_ms / step_cell_ms}
+
+
 def octree_timing(steps=300, warmup=20):
     """Explicit steps on the octree workload: Q2 over a 10x10x5 mm part, coarse
     20x20x10 cells refined to level 6 around the scan path (hanging nodes through
@@ -231,7 +332,7 @@ def octree_timing(steps=300, warmup=20):
     nl, nh, ml = C.c_int64(), C.c_int64(), C.c_int()
     sim._check(sim.lib.pbf_octree_info(sim.ctx, C.byref(nl), C.byref(nh), C.byref(ml)))
     v0 = torch.tensor(W.seeded_vector(n, 1), device="cuda")
-    dt = prob.dt_factor * 2.0 / sim.stability_lambda(v0, 50)
+    dt = prob.dt_factor * sim.stability_dt(v0, 50)
     T, rc = sim.init_state(prob.T0)
     T_tmp = torch.empty_like(T)
     sim.explicit_steps(T, rc, 0.0, dt, warmup, T_tmp=T_tmp)
@@ -248,17 +349,25 @@ def octree_timing(steps=300, warmup=20):
             "finite": bool(torch.isfinite(T).all().item()), "T_max": float(T.max().item())}
 
 
+def progress(msg):
+    """One progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg4", "cfg5", "cfg1"])
+    ap.add_argument("--workload", default="cfg4", choices=["cfg2", "cfg4", "cfg5", "cfg1"])
+    ap.add_argument("--fp32-error-steps", type=int, default=5000,
+                    help="steps of the FP32-operator vs FP64 error statement (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-operator timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-step timing")
     ap.add_argument("--no-octree", action="store_true", help="skip the octree-mesh timing")
+    ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace reference operator timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -286,8 +395,7 @@ def main():
     info = sim.info()
     # time step: half the explicit stability limit (power iteration on the GPU)
     v0 = torch.tensor(W.seeded_vector(info["n_dofs"], 1), device="cuda")
-    lam = sim.stability_lambda(v0, 100)
-    dt = prob.dt_factor * 2.0 / lam
+    dt = prob.dt_factor * sim.stability_dt(v0, 100)
     del v0
 
     results = {}
@@ -312,6 +420,7 @@ def main():
         finite = bool(torch.isfinite(T).all().item())
         results[prec] = dict(ms=ms, cell_ms=cell_ms, face_ms=face_ms, n=nt, finite=finite,
                              Tmax=float(T.max().item()))
+        progress(f"fp{prec} operator: {ms / args.steps:.4f} ms per step")
         if prec == 64:
             end_state = (T.clone(), rc.clone())
         del T, rc, T_tmp
@@ -367,15 +476,25 @@ def main():
                                 "ms_per_step": r32["ms"] / args.steps,
                                 "speedup_vs_fp64": v32 / value,
                                 "kernel_ms": r32["cell_ms"], "finite": r32["finite"]}
+        if args.fp32_error_steps > 0:
+            out["fp32_operator"]["error_vs_fp64"] = fp32_errors(sim, prob, dt, args.fp32_error_steps)
+            progress("fp32 error statement done")
+    if not args.no_laplace:
+        out["laplace_reference"] = laplace_timing(sim, info, prob, args.steps, args.warmup, ms_step,
+                                                  r64["cell_ms"])
+        progress("laplace reference done")
     if not args.no_implicit:
         out["implicit"] = implicit_timing(sim, *end_state, (args.warmup + args.steps) * dt)
+        progress("implicit step done")
     del end_state
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
+        progress("adjoint done")
     if not args.no_octree:
         out["octree"] = octree_timing()
+        progress("octree done")
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(prob, dt)
     print(json.dumps(out), flush=True)
 
 

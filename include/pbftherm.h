@@ -234,6 +234,17 @@ pbf_status pbf_explicit_steps(pbf_ctx *ctx, double *T, double *T_tmp, double *rc
 pbf_status pbf_assemble(pbf_ctx *ctx, const double *T, double *rc, double t, double *f, double *C,
                         int precision, void *stream);
 
+/* Reference operator for throughput comparisons (Section 5.1 compares the
+ * explicit step with a constant-coefficient matrix-free Laplace operator):
+ * y = K x with K the stiffness matrix of unit conductivity on the box mesh,
+ * K_ij = sum_e integral_e grad N_i . grad N_j (Gauss rule of degree+1 points
+ * per direction), evaluated with the same sum-factorized column kernels as
+ * the explicit step but with no material law, history, source, capacity or
+ * update.  Every node is included (no Dirichlet rows are removed).  x, y:
+ * device arrays of n_dofs doubles that must not overlap.  Box meshes only
+ * (PBF_EMESH on octrees).  Asynchronous. */
+pbf_status pbf_laplace_apply(pbf_ctx *ctx, const double *x, double *y, void *stream);
+
 /* Largest eigenvalue of C~^{-1} K_diff (eq. explicit_time_step) by `iters`
  * power iterations from the device vector v0 (n_dofs), with k and c_p frozen at
  * the breakpoint where k/(rho c_p) is largest; the estimate is the Rayleigh
@@ -241,6 +252,16 @@ pbf_status pbf_assemble(pbf_ctx *ctx, const double *T, double *rc, double t, dou
  * scratch arrays from the workspace.  Synchronizes. */
 pbf_status pbf_stability_lambda(pbf_ctx *ctx, const double *v0, int iters, double *lambda_max,
                                 void *stream);
+
+/* Critical explicit time step dt_crit = 2 / lambda_max (eq. explicit_time_step):
+ * the forward-Euler scheme is stable for dt < dt_crit.  lambda_max is estimated
+ * exactly as in pbf_stability_lambda (same arguments, same power iteration);
+ * dt_crit (host) receives 2/lambda_max, and lambda_max (host, may be NULL) the
+ * eigenvalue estimate itself.  Returns PBF_ENONFINITE when the estimate is not
+ * a positive finite number (for instance a start vector that is zero on every
+ * free node).  Synchronizes. */
+pbf_status pbf_stability_dt(pbf_ctx *ctx, const double *v0, int iters, double *dt_crit,
+                            double *lambda_max, void *stream);
 
 /* ---- implicit scheme (Section 3.2, eqs. backward_euler_nonlinear, Newton_1, Newton_2)
  * One backward-Euler step from T_n (time t) to T_out (time t + dt), solving
@@ -380,11 +401,11 @@ pbf_status pbf_gradient_backward(pbf_ctx *ctx, double t0, double dt, int n_steps
                                  double *dJdA, double *lam0, int64_t *n_advances, void *stream);
 
 /* ---- kernel timing (instrumentation) ------------------------------------------
- * pbf_timing_begin: from now on pbf_explicit_steps has the dispatches of the
- * cell kernel and of the tile-face kernel record HIP start/stop events on the
- * caller's stream (execution time of each kernel) on every `every`-th step
- * (1: all), for at most max_steps timed steps (host-side event pool, created
- * here).
+ * pbf_timing_begin: from now on pbf_explicit_steps (and pbf_laplace_apply)
+ * has the dispatches of the cell kernel and of the tile-face kernel record HIP
+ * start/stop events on the caller's stream (execution time of each kernel) on
+ * every `every`-th step or apply (1: all), for at most max_steps timed ones
+ * (host-side event pool, created here).
  * pbf_timing_end: waits for the recorded events and returns the average
  * duration in milliseconds of the cell kernel and of the tile-face kernel and
  * the number of timed steps; releases the events.  Synchronizes. */

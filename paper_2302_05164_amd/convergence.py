@@ -100,7 +100,7 @@ def temporal_convergence(prob, levels=3, obs=(0.5e-3, 0.0, 0.24e-3), layer_cells
     if dt_crit is None:
         s = pbftherm.from_problem(prob, device=device)
         v0 = torch.tensor(np.random.default_rng(1).uniform(-1, 1, s.info()["n_dofs"]), device=device)
-        dt_crit = 2.0 / s.stability_lambda(v0, 100)
+        dt_crit = s.stability_dt(v0, 100)
         del s
     runs = []
     for k in range(levels):

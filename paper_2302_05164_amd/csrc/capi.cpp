@@ -82,6 +82,9 @@ struct pbf_ctx {
         const double *cur = nullptr;  // executor state after the forward sweep
         double *next = nullptr;
         bool valid = false;
+        // every problem parameter the reversal reads (material, laser and track
+        // powers, boundary, probes), as seen by the forward sweep
+        std::vector<double> problem;
     } grad;
     Law<double> h_law64{}, h_lin64{}, h_zero64{};
     Law<float> h_law32{};
@@ -599,7 +602,7 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const dou
         pf.re = surface_params(c, law);
     }
     if (linear) pd.nlaw = c->d_lin64;
-    const bool timed = c->timing && mode == 0 && (c->timing_seen++ % c->timing_every) == 0 &&
+    const bool timed = c->timing && mode != 1 && (c->timing_seen++ % c->timing_every) == 0 &&
                        c->tev_used + 4 <= c->tev.size();
     hipEvent_t *ev = timed ? &c->tev[c->tev_used] : nullptr;
     PBF_HIP(c, launch_cells(c->degree, precision, mode, column_height(), pd, pf, s, ev ? ev[0] : nullptr,
@@ -1452,6 +1455,39 @@ pbf_status pbf_assemble(pbf_ctx *c, const double *T, double *rc, double t, doubl
     return operator_pass(c, 1, precision, LAW_FULL, T, nullptr, f, C, rc, t, 0.0, s);
 }
 
+pbf_status pbf_laplace_apply(pbf_ctx *c, const double *x, double *y, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    pbf_status st = check_bound(c);
+    if (st) return st;
+    if (c->octree) return fail(c, PBF_EMESH, "the Laplace reference operator runs on box meshes");
+    if (!x || !y) return fail(c, PBF_EINVAL, "NULL device array");
+    if (x == y) return fail(c, PBF_EINVAL, "x and y must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    CellParams<double> pd = cell_params<double>(c, c->d_law64, false);
+    pd.Tin = x;
+    pd.fout = y;
+    const CellParams<float> pf{};
+    const bool timed = c->timing && (c->timing_seen++ % c->timing_every) == 0 && c->tev_used + 4 <= c->tev.size();
+    hipEvent_t *ev = timed ? &c->tev[c->tev_used] : nullptr;
+    PBF_HIP(c, launch_cells(c->degree, PBF_PREC_FP64, 2, column_height(), pd, pf, s, ev ? ev[0] : nullptr,
+                            ev ? ev[1] : nullptr));
+    HaloParams h = geometry(c);
+    h.Tin = x;
+    h.fout = y;
+    const bool faces = h.GX + h.GY + h.GZ > 0;
+    PBF_HIP(c, launch_halo(2, h, s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
+    if (timed) {
+        if (!faces) {
+            PBF_HIP(c, hipEventRecord(ev[2], s));
+            PBF_HIP(c, hipEventRecord(ev[3], s));
+        }
+        c->tev_used += 4;
+    }
+    return PBF_OK;
+}
+
 pbf_status pbf_stability_lambda(pbf_ctx *c, const double *v0, int iters, double *lambda_max,
                                 void *stream)
 {
@@ -1478,6 +1514,21 @@ pbf_status pbf_stability_lambda(pbf_ctx *c, const double *v0, int iters, double 
     PBF_HIP(c, hipMemcpyAsync(sc, c->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PBF_HIP(c, hipStreamSynchronize(s));
     *lambda_max = sc[0] / sc[1];
+    return PBF_OK;
+}
+
+pbf_status pbf_stability_dt(pbf_ctx *c, const double *v0, int iters, double *dt_crit, double *lambda_max,
+                            void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!dt_crit) return fail(c, PBF_EINVAL, "dt_crit is NULL");
+    double lam = 0.0;
+    pbf_status st = pbf_stability_lambda(c, v0, iters, &lam, stream);
+    if (st) return st;
+    if (!(lam > 0.0) || !std::isfinite(lam))
+        return fail(c, PBF_ENONFINITE, "stability estimate is not a positive finite eigenvalue (%g)", lam);
+    *dt_crit = 2.0 / lam;
+    if (lambda_max) *lambda_max = lam;
     return PBF_OK;
 }
 
@@ -1890,6 +1941,40 @@ pbf_status pbf_adjoint_work_bytes(const pbf_ctx *c, int n_snaps, size_t *bytes)
     return PBF_OK;
 }
 
+// The problem parameters that the forward sweep, the replays and the reverse
+// steps of a gradient evaluation read, flattened in a fixed order: a backward
+// sweep may only run on the problem its forward sweep saw.
+static std::vector<double> grad_problem(const pbf_ctx *c)
+{
+    std::vector<double> v;
+    v.push_back(c->n_bp);
+    for (int i = 0; i < c->n_bp; ++i) {
+        v.push_back(c->T_bp[i]);
+        v.push_back(c->k_bp[i]);
+        v.push_back(c->cp_bp[i]);
+    }
+    for (double x : {c->rho, c->T_s, c->T_l, c->latent, c->phi, c->powder_depth, double(c->laser_kind), c->radius,
+                     c->absorptivity, c->h_powder, c->t_start, double(c->dmask), c->T_D})
+        v.push_back(x);
+    for (const pbf_track &t : c->tracks) {
+        for (int d = 0; d < 3; ++d) {
+            v.push_back(t.x0[d]);
+            v.push_back(t.x1[d]);
+        }
+        v.push_back(t.speed);
+        v.push_back(t.power);
+    }
+    for (int x : c->probe_cell) v.push_back(x);
+    v.insert(v.end(), c->probe_xi.begin(), c->probe_xi.end());
+    v.insert(v.end(), c->probe_target.begin(), c->probe_target.end());
+    return v;
+}
+
+static bool same_bits(const std::vector<double> &a, const std::vector<double> &b)
+{
+    return a.size() == b.size() && (a.empty() || std::memcmp(a.data(), b.data(), a.size() * sizeof(double)) == 0);
+}
+
 static pbf_status check_grad_args(pbf_ctx *c, double dt, int n_steps, int n_snaps, void *work, size_t work_bytes)
 {
     pbf_status st = check_bound(c);
@@ -1953,6 +2038,7 @@ pbf_status pbf_gradient_forward(pbf_ctx *c, const double *T0, const double *rc0,
     c->grad.dt = dt;
     c->grad.cur = g.cur;
     c->grad.next = g.next;
+    c->grad.problem = grad_problem(c);
     c->grad.valid = true;
     return PBF_OK;
 }
@@ -1969,6 +2055,10 @@ pbf_status pbf_gradient_backward(pbf_ctx *c, double t0, double dt, int n_steps, 
     if (!c->grad.valid || c->grad.work != work || c->grad.n_steps != n_steps || c->grad.n_snaps != n_snaps ||
         c->grad.t0 != t0 || c->grad.dt != dt)
         return fail(c, PBF_ESTATE, "no matching forward sweep: call pbf_gradient_forward with the same arguments");
+    if (!same_bits(c->grad.problem, grad_problem(c)))
+        return fail(c, PBF_ESTATE,
+                    "the problem changed since pbf_gradient_forward (material, laser, track powers, absorptivity, "
+                    "boundary or probes): restore it or run the forward sweep again");
     c->grad.valid = false;  // the reversal consumes the forward state
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_laws(c, s))) return st;

@@ -150,11 +150,40 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
     });
 }
 
+// Unit-conductivity diffusion at the Gauss points (the constant-coefficient
+// Laplace operator y = K x): flux W J^{-1} J^{-T} grad u, collocation transpose.
+template <int P, typename R, typename PP>
+__device__ __forceinline__ void flux_points_laplace(PP &p, const R *v, R *w)
+{
+    using TB = Tables<P>;
+    constexpr int N = P + 1, NN = N * N * N;
+    const R cx = p.detJ * p.ih2x, cy = p.detJ * p.ih2y, cz = p.detJ * p.ih2z;
+    sfor<0, NN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+        auto gxf = [&](auto rc) { return v[tidx<N, 0>(decltype(rc)::value, qy, qz)]; };
+        auto gyf = [&](auto rc) { return v[tidx<N, 1>(decltype(rc)::value, qx, qz)]; };
+        auto gzf = [&](auto rc) { return v[tidx<N, 2>(decltype(rc)::value, qx, qy)]; };
+        constexpr double wq = TB::gw(qx) * TB::gw(qy) * TB::gw(qz);
+        const R Fx = R(wq) * cx * rowdot<TagD<P>, qx, 0, N, false>(gxf, R(0));
+        const R Fy = R(wq) * cy * rowdot<TagD<P>, qy, 0, N, false>(gyf, R(0));
+        const R Fz = R(wq) * cz * rowdot<TagD<P>, qz, 0, N, false>(gzf, R(0));
+        sfor<0, N>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            constexpr double dx = TB::D(qx, r), dy = TB::D(qy, r), dz = TB::D(qz, r);
+            if constexpr (dx != 0.0) w[tidx<N, 0>(r, qy, qz)] = ffma(R(dx), Fx, w[tidx<N, 0>(r, qy, qz)]);
+            if constexpr (dy != 0.0) w[tidx<N, 1>(r, qx, qz)] = ffma(R(dy), Fy, w[tidx<N, 1>(r, qx, qz)]);
+            if constexpr (dz != 0.0) w[tidx<N, 2>(r, qx, qy)] = ffma(R(dz), Fz, w[tidx<N, 2>(r, qx, qy)]);
+        });
+    });
+}
+
 // ---------------------------------------------------------------------------
 // one cell: nodal values u -> element vector fe (diffusion, source, surface
-// flux).  Values are relative to Tref (zero in double precision).
+// flux).  Values are relative to Tref (zero in double precision).  MODE 2:
+// the unit-conductivity Laplace operator alone.
 // ---------------------------------------------------------------------------
-template <int P, typename R, typename PP>
+template <int P, typename R, int MODE, typename PP>
 __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R *u, int cx, int cy,
                                               int cz, R *fe)
 {
@@ -164,6 +193,16 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
     sweep<TagS<P>, N, 0>(u, t1);
     sweep<TagS<P>, N, 1>(t1, t2);
     sweep<TagS<P>, N, 2>(t2, v);  // values at the Gauss points
+    if constexpr (MODE == 2) {
+        R w[NN];
+#pragma unroll
+        for (int q = 0; q < NN; ++q) w[q] = R(0);
+        flux_points_laplace<P, R>(p, v, w);
+        sweep<TagSt<P>, N, 0>(w, t1);
+        sweep<TagSt<P>, N, 1>(t1, t2);
+        sweep<TagSt<P>, N, 2>(t2, fe);
+        return;
+    }
 
     // Wave-uniform truncation of the material law: hinge i (slope change at
     // breakpoint b_i) contributes only where T > b_i, and the latent heat and
@@ -268,11 +307,13 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
     ConstLaw<double> &L = const_law(q.nlaw);
     // capacity hinges that some node of the wave exceeds (hinges above every
     // node add exactly zero)
-    double tmax = sTz[0][0];
-#pragma unroll
-    for (int a = 1; a < N * N * N; ++a) tmax = fmax(tmax, sTz[a / (N * N)][((a / N) % N) * BX + a % N]);
     int nh = 0;
-    while (nh < L.n_hinge && __any(tmax > L.b[nh])) ++nh;
+    if constexpr (MODE != 2) {
+        double tmax = sTz[0][0];
+#pragma unroll
+        for (int a = 1; a < N * N * N; ++a) tmax = fmax(tmax, sTz[a / (N * N)][((a / N) % N) * BX + a % N]);
+        while (nh < L.n_hinge && __any(tmax > L.b[nh])) ++nh;
+    }
     const double c0 = L.c0, Ts = L.Ts, Tl = L.Tl, lat = L.lat, rho = L.rho;
     const int NX = q.NX, NY = q.NY, NZ = q.NZ;
     const unsigned dmask = q.dmask;
@@ -287,7 +328,7 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
         // coefficient read once per plane; every node adds its hinges in
         // increasing order)
         double cpl[N * N];
-        if (az < P || last) {
+        if (MODE != 2 && (az < P || last)) {
 #pragma unroll
             for (int j = 0; j < N * N; ++j) {
                 const double T = sTz[az][(j / N) * BX + j % N];
@@ -351,14 +392,15 @@ __device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS
                 } else {
                     double *dst = face ? slots + t : q.fout + g;
                     if (own) *dst = f;
-                    if (own && !face) q.Cout[g] = C;
+                    if (MODE == 1 && own && !face) q.Cout[g] = C;
                 }
             }
         }
     }
 }
 
-// MODE 0: explicit step (fused update into Tout); MODE 1: assemble f and C~.
+// MODE 0: explicit step (fused update into Tout); MODE 1: assemble f and C~;
+// MODE 2: the unit-conductivity Laplace operator y = K x into fout.
 //
 // Node ownership inside a column: the lane of cell (lx, ly) owns the nodes of
 // its cell with local x and y indices in 1..P (plus index 0 on the column's
@@ -456,8 +498,8 @@ k_cells(const CellParams<R> p)
         }
         R fe[NN];
         if (active) {
-            cell_operator<P, R>(q, lawp, u, cx, cy, cz, fe);
-            if (q.re.on && cz == q.nz - 1) {  // top face: radiation and evaporation
+            cell_operator<P, R, MODE>(q, lawp, u, cx, cy, cz, fe);
+            if (MODE != 2 && q.re.on && cz == q.nz - 1) {  // top face: radiation and evaporation
                 const int st = r0 + P < N ? r0 + P : r0 + P - N;
                 const double *top = sTl + st * PLANE;
                 surface_loss_face<P>(q.re, q.hx, q.hy, [&](int ax, int ay) { return top[ay * BX + ax]; }, fe);
@@ -516,6 +558,8 @@ __global__ void __launch_bounds__(256) k_halo(const HaloParams h)
     const double f = face_sum(h.slots, h.GX + h.GY + h.GZ, t, fn);
     if (MODE == 0) {  // the slots hold T_n + dt f_0 / C~ and the other columns' increments
         h.Tout[g] = f;
+    } else if (MODE == 2) {
+        h.fout[g] = f;
     } else {
         h.fout[g] = f;
         h.Cout[g] = node_capacity(const_law(h.nlaw), h.Tin[g], int(fn.gi), int(fn.gj), int(fn.gk), h.P, h.NX,
@@ -544,8 +588,15 @@ void launch_ty(int degree, int precision, int mode, const CellParams<double> &pd
     const dim3 grid(8 * tpx), block(kTX * TY);
 #define PBF_LAUNCH(P_, R_, M_, prm) launch_maybe_timed(k_cells<P_, R_, M_, TY>, grid, block, s, e0, e1, prm)
     if (precision == PBF_PREC_FP64) {
-        if (degree == 1) { if (mode == 0) PBF_LAUNCH(1, double, 0, pd); else PBF_LAUNCH(1, double, 1, pd); }
-        else { if (mode == 0) PBF_LAUNCH(2, double, 0, pd); else PBF_LAUNCH(2, double, 1, pd); }
+        if (degree == 1) {
+            if (mode == 0) PBF_LAUNCH(1, double, 0, pd);
+            else if (mode == 1) PBF_LAUNCH(1, double, 1, pd);
+            else PBF_LAUNCH(1, double, 2, pd);
+        } else {
+            if (mode == 0) PBF_LAUNCH(2, double, 0, pd);
+            else if (mode == 1) PBF_LAUNCH(2, double, 1, pd);
+            else PBF_LAUNCH(2, double, 2, pd);
+        }
     } else {
         if (degree == 1) { if (mode == 0) PBF_LAUNCH(1, float, 0, pf); else PBF_LAUNCH(1, float, 1, pf); }
         else { if (mode == 0) PBF_LAUNCH(2, float, 0, pf); else PBF_LAUNCH(2, float, 1, pf); }
@@ -575,7 +626,8 @@ hipError_t launch_halo(int mode, const HaloParams &hp, hipStream_t s, hipEvent_t
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (mode == 0) launch_maybe_timed(k_halo<0>, grid, block, s, e0, e1, hp);
-    else launch_maybe_timed(k_halo<1>, grid, block, s, e0, e1, hp);
+    else if (mode == 1) launch_maybe_timed(k_halo<1>, grid, block, s, e0, e1, hp);
+    else launch_maybe_timed(k_halo<2>, grid, block, s, e0, e1, hp);
     return hipGetLastError();
 }
 

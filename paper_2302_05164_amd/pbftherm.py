@@ -84,6 +84,8 @@ SIGNATURES = {
     "pbf_explicit_steps": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp],
     "pbf_assemble": [_vp, _vp, _vp, C.c_double, _vp, _vp, C.c_int, _vp],
     "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
+    "pbf_stability_dt": [_vp, _vp, C.c_int, _dp, _dp, _vp],
+    "pbf_laplace_apply": [_vp, _vp, _vp, _vp],
     "pbf_implicit_step": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int,
                           C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _vp],
     "pbf_newton_work_bytes": [_vp, C.c_int, C.POINTER(C.c_size_t)],
@@ -316,6 +318,23 @@ class Simulation:
         self._check(self.lib.pbf_stability_lambda(self.ctx, _f64(v0, i["n_dofs"], "v0"), int(iters),
                                                   C.byref(lam), self._stream()))
         return lam.value
+
+    def laplace_apply(self, x, y=None):
+        """y = K x, the unit-conductivity Laplace operator (reference kernel)."""
+        i = self.info()
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(self.lib.pbf_laplace_apply(self.ctx, _f64(x, i["n_dofs"], "x"), _f64(y, i["n_dofs"], "y"),
+                                               self._stream()))
+        return y
+
+    def stability_dt(self, v0, iters):
+        """Critical explicit step 2/lambda_max (eq. explicit_time_step)."""
+        i = self.info()
+        dt = C.c_double()
+        self._check(self.lib.pbf_stability_dt(self.ctx, _f64(v0, i["n_dofs"], "v0"), int(iters),
+                                              C.byref(dt), None, self._stream()))
+        return dt.value
 
     def newton_work(self, restart=30):
         """Device buffer for implicit_step_newton with the given GMRES restart length."""

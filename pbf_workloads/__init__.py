@@ -263,6 +263,38 @@ def sine_mode(degree: int, n: int, k=20.0, rho=7900.0, cp=500.0) -> Problem:
         t_start=0.0, tracks=np.zeros((0, 8)), steps=0, dt_factor=0.5, seed=0)
 
 
+def hot_spot_state(p: Problem, seed: int, peak=2600.0, width=120e-6, noise=5.0):
+    """A seeded temperature field on a box with a melt pool: T0 plus a Gaussian
+    bump of height peak - T0 and 1/e radius `width`, centred on the top surface
+    0.1 mm along the first track (a quarter as deep as wide), plus uniform noise
+    of +-noise K; Dirichlet nodes at T_D.  Returns (T, t) with t the time at
+    which the beam is at the bump's centre.  (Input data only: a field shape and
+    random numbers.)"""
+    rng = np.random.default_rng(seed)
+    NX, NY, NZ = p.nodes_per_dim
+    tr = p.tracks[0]
+    a, b = np.asarray(tr[0:3]), np.asarray(tr[3:6])
+    d = (b - a) / np.linalg.norm(b - a)
+    c = a + 0.1e-3 * d
+    x = np.linspace(0.0, p.L[0], NX)
+    y = np.linspace(0.0, p.L[1], NY)
+    z = np.linspace(0.0, p.L[2], NZ)
+    ex = np.exp(-((x - c[0]) / width) ** 2)
+    ey = np.exp(-((y - c[1]) / width) ** 2)
+    ez = np.exp(-((z - p.L[2]) / (0.25 * width)) ** 2)
+    T = (p.T0 + (peak - p.T0) * ez[:, None, None] * ey[None, :, None] * ex[None, None, :]).reshape(-1)
+    T += rng.uniform(-noise, noise, T.size)
+    m = p.dirichlet_mask
+    k, j, i = (np.arange(NZ)[:, None, None], np.arange(NY)[None, :, None], np.arange(NX)[None, None, :])
+    dmask = np.zeros((NZ, NY, NX), dtype=bool)
+    for bit, cond in ((1, i == 0), (2, i == NX - 1), (4, j == 0), (8, j == NY - 1), (16, k == 0),
+                      (32, k == NZ - 1)):
+        if m & bit:
+            dmask |= np.broadcast_to(cond, dmask.shape)
+    T[dmask.reshape(-1)] = p.T_D
+    return T, float(p.t_start + 0.1e-3 / tr[6])
+
+
 def seeded_vector(n: int, seed: int) -> np.ndarray:
     """Uniform(-1, 1) numbers: start vectors for power iterations and random fields."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)

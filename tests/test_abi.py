@@ -45,6 +45,10 @@ def test_host_validation_errors():
         # stepping before binding
         assert L.pbf_mesh_box(ctx, 2, 4, 4, 4, 1.0, 1.0, 1.0) == 0
         assert L.pbf_explicit_steps(ctx, None, None, None, 0.0, 1e-3, 1, 64, None) == -7
+        dt = C.c_double()
+        assert L.pbf_stability_dt(ctx, None, 10, C.byref(dt), None, None) == -7  # material not set
+        assert L.pbf_stability_dt(ctx, None, 10, None, None, None) == -1  # no output
+        assert L.pbf_laplace_apply(ctx, None, None, None) == -7
         assert L.pbf_set_dirichlet(ctx, 64, 293.0) == -1
         # unsorted breakpoints
         import numpy as np

@@ -181,8 +181,10 @@ def test_backward_without_forward_is_rejected():
 # ---------------------------------------------------------------------------
 # full size: the 48x48x24 Q2 box, 3000 steps, 64 probes, 10 tracks, 30 slots
 # ---------------------------------------------------------------------------
-def _full_size(linear=False):
+def _full_size(linear=False, latent=True):
     prob = W.cfg5()
+    if not latent:
+        prob = prob.replace(latent=0.0)
     if linear:
         prob = prob.replace(T_bp=np.array([0.0, 1e4]), k_bp=np.array([25.0, 25.0]),
                             cp_bp=np.array([600.0, 600.0]), latent=0.0, powder_k_factor=1.0,
@@ -190,7 +192,7 @@ def _full_size(linear=False):
     sim = sim_for(prob)
     info = sim.info()
     v0 = torch.tensor(W.seeded_vector(info["n_dofs"], 1), device="cuda")
-    dt = prob.dt_factor * 2.0 / sim.stability_lambda(v0, 100)
+    dt = prob.dt_factor * sim.stability_dt(v0, 100)
     sim.set_probes(prob.probes, prob.targets)
     return prob, sim, dt
 
@@ -235,3 +237,127 @@ def test_full_size_constant_law_central_differences():
         dJdP = g["dJdP"][k].item()
         print(f"track {k}: adjoint {dJdP:.12e} central difference {fd:.12e}")
         assert abs(dJdP - fd) <= 1e-7 * abs(fd)
+
+
+def test_backward_rejects_a_changed_problem():
+    """The reversal replays forward steps and forms dJ/dP = A dJ/dW: it must run
+    on the problem its forward sweep saw.  Changing the track powers, the
+    absorptivity or the law in between is refused; restoring them is accepted
+    and gives the unchanged gradient."""
+    need_gpu()
+    from paper_2302_05164_amd import pbftherm
+    prob, dt, n = _case("full")
+    ref = _gpu_gradient(prob, dt, n, n_snaps=4)
+    sim = sim_for(prob)
+    sim.set_probes(prob.probes, prob.targets)
+    T0, rc0 = sim.init_state(prob.T0)
+    work = sim.gradient_work(4)
+    P0 = prob.tracks[:, 7].copy()
+    for change in ("powers", "absorptivity", "law"):
+        sim.gradient_forward(T0, rc0, 0.0, dt, n, work)
+        if change == "powers":
+            sim.set_track_powers(P0 * 1.01, prob.absorptivity)
+        elif change == "absorptivity":
+            sim.set_track_powers(P0, prob.absorptivity * 1.01)
+        else:
+            sim.set_material(prob.T_bp, prob.k_bp * 1.01, prob.cp_bp, prob.rho, prob.T_s, prob.T_l,
+                             prob.latent, prob.powder_k_factor, prob.powder_depth)
+        with pytest.raises(pbftherm.PbfError, match="changed"):
+            sim.gradient_backward(0.0, dt, n, work)
+        sim.set_track_powers(P0, prob.absorptivity)
+        sim.set_material(prob.T_bp, prob.k_bp, prob.cp_bp, prob.rho, prob.T_s, prob.T_l,
+                         prob.latent, prob.powder_k_factor, prob.powder_depth)
+        g = sim.gradient_backward(0.0, dt, n, work)
+        torch.cuda.synchronize()
+        assert np.array_equal(g["dJdW"].cpu().numpy(), ref["dJdW"])
+
+
+# the seeded law unchanged (first breakpoint at the ambient temperature), the
+# full 48x48x24 mesh, 64 probes, 10 tracks; steps 170..219 of the scan from the
+# ambient state (the end of the first track and the start of the second), a
+# fixed step below the stability limit (7.66e-6 s)
+FULL_DT = 3.8e-6
+FULL_N0, FULL_N = 170, 50
+
+
+@pytest.mark.timeout(900)
+def test_full_size_real_law_gradient_vs_oracle():
+    """dJ/dW, dJ/dP, dJ/dA and dJ/dT_0 on the full differentiation mesh with the
+    unmodified nonlinear law, against the oracle's store-all adjoint, to 1e-5
+    relative (cold points sit exactly on the law's first breakpoint: both
+    one-sided slopes are valid there and the sides may pick different ones)."""
+    need_gpu()
+    prob = W.cfg5()
+    t0 = FULL_N0 * FULL_DT
+    sim = sim_for(prob)
+    sim.set_probes(prob.probes, prob.targets)
+    T0, rc0 = sim.init_state(prob.T0)
+    work = sim.gradient_work(8)
+    TN, J = sim.gradient_forward(T0, rc0, t0, FULL_DT, FULL_N, work)
+    g = sim.gradient_backward(t0, FULL_DT, FULL_N, work, with_lam0=True)
+    torch.cuda.synchronize()
+    o = oracle.Oracle(prob)
+    Jo, dWo, TNo, lam0o = o.adjoint(o.init_T(), t0, FULL_DT, FULL_N, prob.probes, prob.targets, with_lam0=True)
+    assert TNo.max() > prob.T_l
+    active = np.nonzero(dWo)[0]
+    assert len(active) >= 2  # two tracks inside the window
+    dW = g["dJdW"].cpu().numpy()
+    print(f"cfg5 real law, steps {FULL_N0}..{FULL_N0 + FULL_N - 1}: J gpu {J.item():.12e} oracle {Jo:.12e}")
+    for k in active:
+        print(f"  track {k}: dJ/dW gpu {dW[k]:.12e} oracle {dWo[k]:.12e} rel {abs(dW[k] / dWo[k] - 1):.2e}")
+    assert abs(J.item() - Jo) <= 1e-11 * abs(Jo)
+    mx, _ = rel_errors(TN.cpu().numpy(), TNo)
+    assert mx <= 1e-13
+    np.testing.assert_allclose(dW, dWo, rtol=1e-5, atol=1e-5 * np.abs(dWo).max())
+    A = prob.absorptivity
+    P = prob.tracks[:, 7]
+    np.testing.assert_allclose(g["dJdP"].cpu().numpy(), A * dWo, rtol=1e-5, atol=1e-5 * A * np.abs(dWo).max())
+    dA = g["dJdA"].item()
+    dAo = float(np.dot(P, dWo))
+    print(f"  dJ/dA gpu {dA:.12e} oracle {dAo:.12e}")
+    assert abs(dA - dAo) <= 1e-5 * abs(dAo)
+    _vec_close(g["lam0"].cpu().numpy(), lam0o, 1e-5, "dJ/dT0")
+
+
+@pytest.mark.timeout(900)
+def test_full_size_central_differences_without_latent_heat():
+    """The 3000-step run of the differentiation workload with the seeded k(T)
+    and c_p(T) tables, the powder history and the moving source, but no latent
+    heat: central differences of J at h = 1e-4 relative against the adjoint for
+    three tracks and the absorptivity.  (With latent heat the apparent capacity
+    jumps at T_s and T_l, so J itself jumps wherever a node's temperature
+    crosses those values one step earlier or later: central differences at any
+    h then measure the jumps, not the derivative, and the gradient is checked
+    against the oracle's adjoint instead.)"""
+    need_gpu()
+    prob, sim, dt = _full_size(latent=False)
+    P0 = prob.tracks[:, 7].copy()
+    A0 = prob.absorptivity
+    J, g = _full_gradient(sim, prob, dt, 30, powers=P0)
+    work = sim.gradient_work(1)
+
+    def J_at(P, A):
+        sim.set_track_powers(P, A)
+        T0, rc0 = sim.init_state(prob.T0)
+        _, Jv = sim.gradient_forward(T0, rc0, 0.0, dt, prob.steps, work)
+        torch.cuda.synchronize()
+        return Jv.item()
+
+    hrel = 1e-4
+    for name, k in [("P0", 0), ("P5", 5), ("P9", 9), ("A", None)]:
+        ad = g["dJdP"][k].item() if k is not None else g["dJdA"].item()
+        Js = []
+        for sgn in (1.0, -1.0):
+            P, A = P0.copy(), A0
+            if k is None:
+                A = A0 * (1.0 + sgn * hrel)
+                step = A0 * hrel
+            else:
+                P[k] = P0[k] * (1.0 + sgn * hrel)
+                step = P0[k] * hrel
+            Js.append(J_at(P, A))
+        fd = (Js[0] - Js[1]) / (2.0 * step)
+        err = abs(fd - ad) / abs(ad)
+        print(f"{name}: adjoint {ad:.10e} central difference (h = {hrel:g} rel) {fd:.10e} rel diff {err:.2e}")
+        assert err <= 1e-4, name
+    sim.set_track_powers(P0, A0)

@@ -4,8 +4,9 @@ the same seeded inputs, element by element.
 FP64 bar: max-relative and relative-L2 error <= 1e-12 (relative to max|T| and
 ||T||).  Cases cover Q1 and Q2, meshes smaller than one GPU tile, exact tile
 multiples and ragged tails, the surface and the volume source, the powder
-history, the assembled vectors f and C~, the stability estimate, and one step at
-the full benchmark sizes checked on sampled nodes."""
+history, the assembled vectors f and C~, the stability estimate, Dirichlet
+conditions on every face, the sine eigenmode against its discrete closed form,
+and steps at the full benchmark sizes (whole field and sampled nodes)."""
 import numpy as np
 import pytest
 import torch
@@ -160,34 +161,89 @@ def _sampled_nodes(prob, rng, T, n_random=160):
     return np.array(sorted(nodes), dtype=np.int64)
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("cfg", ["cfg2", "cfg4"])
-def test_full_size_step_on_sampled_nodes(cfg):
-    """At the benchmark sizes: advance the GPU state 150 steps, then check one
-    more GPU step against the oracle's step from the same state at sampled nodes
-    (melt pool, tile faces, boundaries, random)."""
+def test_full_size_steps_vs_oracle(cfg):
+    """At the benchmark sizes and launch configuration: from a seeded state with a
+    melt pool under the beam and partly consolidated powder, two GPU steps
+    against two oracle steps over the whole field, then a third GPU step against
+    the oracle's step evaluated at sampled nodes (melt pool, tile faces,
+    segment ends, boundaries, random) from the oracle's own state."""
     need_gpu()
     prob = W.CONFIGS[cfg]()
+    o = oracle.Oracle(prob)
+    T0, t0 = W.hot_spot_state(prob, seed=17)
+    rc_full = o.init_history()
+    rng = np.random.default_rng(23)
+    powder = rc_full == 0.0
+    rc_full[powder] = np.where(rng.random(powder.sum()) < 0.3, rng.random(powder.sum()), 0.0)
+    dt = 2.5e-6
     sim = sim_for(prob)
     info = sim.info()
-    T, rc = sim.init_state(prob.T0)
-    dt = 2.5e-6
-    n0 = 150
-    sim.explicit_steps(T, rc, 0.0, dt, n0)
+    from tests.gpu_util import full_to_history
+    T = torch.tensor(T0, device="cuda")
+    rc = torch.tensor(full_to_history(prob, rc_full, info["n_hist_layers"]), device="cuda")
+    sim.explicit_steps(T, rc, t0, dt, 2)
     torch.cuda.synchronize()
-    Tn = T.cpu().numpy()
-    rn = rc.cpu().numpy()
-    sim.explicit_steps(T, rc, n0 * dt, dt, 1)
+    Tg2 = T.cpu().numpy()
+    rg2 = history_to_full(prob, rc.cpu().numpy(), info["n_hist_layers"])
+    To, ro = T0.copy(), rc_full.copy()
+    o.explicit_steps(To, ro, t0, dt, 2)
+    assert To.max() > prob.T_l
+    mx, l2 = rel_errors(Tg2, To)
+    print(f"{cfg}: 2 steps full field max rel {mx:.2e} rel-L2 {l2:.2e} Tmax {To.max():.0f}")
+    assert mx <= TOL64 and l2 <= TOL64
+    assert np.abs(rg2 - ro).max() <= 1e-12
+    sim.explicit_steps(T, rc, t0 + 2 * dt, dt, 1)
     torch.cuda.synchronize()
-    Tn1 = T.cpu().numpy()
-    assert Tn.max() > prob.T_l  # a melt pool exists
-    o = oracle.Oracle(prob)
-    rng = np.random.default_rng(11)
-    nodes = _sampled_nodes(prob, rng, Tn)
-    rc_full = history_to_full(prob, rn, info["n_hist_layers"])
-    ref = o.explicit_step_sampled(Tn, rc_full, n0 * dt, dt, nodes)
-    err = np.abs(Tn1[nodes] - ref).max() / np.abs(ref).max()
-    print(f"{cfg}: {len(nodes)} sampled nodes, max rel err {err:.2e}, Tmax {Tn.max():.0f}")
+    Tg3 = T.cpu().numpy()
+    nodes = _sampled_nodes(prob, rng, To)
+    ref = o.explicit_step_sampled(To, ro, t0 + 2 * dt, dt, nodes)
+    err = np.abs(Tg3[nodes] - ref).max() / np.abs(ref).max()
+    print(f"{cfg}: third step, {len(nodes)} sampled nodes, max rel err {err:.2e}")
     assert err <= TOL64
+
+
+@pytest.mark.parametrize("degree,n", [(1, 40), (2, 20)])
+def test_explicit_sine_mode_closed_form(degree, n):
+    """Every face Dirichlet, constant coefficients: the GPU's forward-Euler steps
+    of sin(pi x) sin(pi y) sin(pi z) equal the discrete closed form (Q1: scalar
+    decay factor; Q2: 8x8 matrix power on the invariant subspace).  n cells per
+    direction span two column tiles with a ragged tail and several z-segments."""
+    need_gpu()
+    from tests.sine_modes import q1_explicit, q2_explicit, sine_field
+    k, rho, cp = 20.0, 7900.0, 500.0
+    alpha = k / (rho * cp)
+    prob = W.sine_mode(degree, n, k=k, rho=rho, cp=cp)
+    h = 1.0 / n
+    dt = 0.4 * 2.0 / (alpha * (4.0 if degree == 1 else 36.0) / h ** 2)
+    A, nsteps = 120.0, 30
+    sim = sim_for(prob)
+    T = torch.tensor(prob.T_D + A * sine_field(degree, n), device="cuda")
+    rc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sim.explicit_steps(T, rc, 0.0, dt, nsteps)
+    torch.cuda.synchronize()
+    expect = prob.T_D + A * (q1_explicit if degree == 1 else q2_explicit)(n, alpha, dt, nsteps)
+    err = np.abs(T.cpu().numpy() - expect).max() / A
+    print(f"Q{degree} n={n}: max |T - closed form| / A = {err:.2e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("mask", [W.ALL_FACES, W.ALL_FACES & ~W.FACE_ZP, W.FACE_XP | W.FACE_YM | W.FACE_ZM])
+def test_dirichlet_faces_nonlinear_vs_oracle(mask):
+    """Dirichlet on side and top faces (x/y column-face nodes, ragged far faces,
+    segment ends) on a ragged multi-column box run through the beam."""
+    need_gpu()
+    prob = W.small_nonlinear(nx=21, ny=18, nz=11, steps=100, track_length=0.5e-3).replace(dirichlet_mask=mask)
+    dt = oracle_dt(prob)
+    Tg, rg, To, ro, info = _run_pair(prob, prob.steps, dt)
+    mx, l2 = rel_errors(Tg, To)
+    print(f"mask {mask}: max rel {mx:.2e} rel-L2 {l2:.2e} Tmax {To.max():.0f}")
+    assert To.max() > prob.T0 + 500.0
+    assert mx <= TOL64 and l2 <= TOL64
+    assert np.abs(rg - ro).max() <= 1e-9
+    d = oracle.Oracle(prob).dirichlet_mask()
+    assert np.all(Tg[d] == prob.T_D)
 
 
 def test_fp32_operator_error_vs_fp64_oracle():
@@ -204,3 +260,25 @@ def test_fp32_operator_error_vs_fp64_oracle():
     mp = np.abs(Tg[melt] - To[melt]).max() / np.abs(To[melt]).max() if melt.any() else 0.0
     print(f"fp32 op: max rel {mx:.2e} rel-L2 {l2:.2e} max/rise {mx_rise:.2e} melt pool max rel {mp:.2e}")
     assert mx <= 1e-4 and l2 <= 1e-4
+
+
+@pytest.mark.parametrize("degree,dims", [(2, (21, 18, 11)), (1, (37, 17, 9)), (2, (3, 2, 1))])
+def test_laplace_reference_operator_vs_oracle(degree, dims):
+    """The unit-conductivity reference operator y = K x equals minus the
+    oracle's diffusion vector for a constant law k = 1 (laser off, no powder)
+    at every node, on ragged multi-column boxes."""
+    need_gpu()
+    nx, ny, nz = dims
+    base = W.small_nonlinear(nx=nx, ny=ny, nz=nz, steps=0).replace(degree=degree)
+    prob = base.replace(T_bp=np.array([0.0, 1e9]), k_bp=np.array([1.0, 1.0]), cp_bp=np.array([500.0, 500.0]),
+                        latent=0.0, powder_k_factor=1.0, powder_depth=0.0, laser_kind=W.LASER_OFF)
+    o = oracle.Oracle(prob)
+    x = W.seeded_vector(o.N, 31) * 100.0 + 500.0
+    f, _, _ = o.assemble(x, o.init_history(), 0.0)
+    sim = sim_for(base)  # the reference operator ignores the law, history and laser
+    y = sim.laplace_apply(torch.tensor(x, device="cuda"))
+    torch.cuda.synchronize()
+    err = np.abs(y.cpu().numpy() + f).max() / np.abs(f).max()
+    print(f"Laplace Q{degree} {dims}: max rel {err:.2e}")
+    assert err <= TOL64
+

@@ -215,7 +215,7 @@ def test_octree_configuration_properties():
     assert fa[inner].max() <= 1e-11 * fa.max()
     sim = pbftherm.from_problem(p)
     v0 = torch.tensor(W.seeded_vector(sim.info()["n_dofs"], 1), device="cuda")
-    dt = 0.5 * 2.0 / sim.stability_lambda(v0, 50)
+    dt = 0.5 * sim.stability_dt(v0, 50)
     T, rc = sim.init_state(p.T0)
     Tp = T.clone()
     sim.explicit_steps(T, rc, 0.0, dt, 1)

@@ -18,6 +18,7 @@ import scipy.linalg as sl
 import pbf_workloads as W
 from oracle import Oracle, gauss_legendre, lagrange, lagrange_deriv
 from tests.fem1d import global_1d, global_3d
+from tests.sine_modes import q1_explicit, q2_explicit, sine_field
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -110,10 +111,7 @@ def test_operator_symmetric_and_annihilates_constants_nonlinear():
 # --------------------------------------------------------------------------
 # decaying eigenmode sin(pi x) sin(pi y) sin(pi z)
 # --------------------------------------------------------------------------
-def _sine_field(deg, n):
-    x = np.linspace(0.0, 1.0, deg * n + 1)
-    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
-    return (np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)).ravel()
+_sine_field = sine_field
 
 
 @pytest.mark.parametrize("n", [5, 8])
@@ -126,17 +124,13 @@ def test_sine_mode_q1_discrete_closed_form(n):
     o = Oracle(prob)
     alpha = k / (rho * cp)
     h = 1.0 / n
-    a = 2.0 / h ** 2 * (1.0 - math.cos(math.pi * h))
-    b = (2.0 + math.cos(math.pi * h)) / 3.0
-    lam = 3.0 * a * b * b
     dt = 0.4 * 2.0 / (alpha * 4.0 / h ** 2)
-    s = _sine_field(1, n)
     A = 150.0
-    T = prob.T_D + A * s
+    T = prob.T_D + A * _sine_field(1, n)
     rc = o.init_history()
     nsteps = 7
     o.explicit_steps(T, rc, 0.0, dt, nsteps)
-    expect = prob.T_D + A * s * (1.0 - dt * alpha * lam) ** nsteps
+    expect = prob.T_D + A * q1_explicit(n, alpha, dt, nsteps)
     np.testing.assert_allclose(T, expect, rtol=0, atol=1e-12 * A)
 
 
@@ -150,36 +144,13 @@ def test_sine_mode_q2_invariant_subspace(n):
     prob = W.sine_mode(2, n, k=k, rho=rho, cp=cp)
     o = Oracle(prob)
     h = 1.0 / n
-    M1, K1 = global_1d(2, n, h)
-    Ml = M1.sum(axis=1)
-    x = np.linspace(0, 1, 2 * n + 1)
-    s1 = np.sin(np.pi * x)
-    v = s1.copy(); v[1::2] = 0.0
-    m = s1.copy(); m[0::2] = 0.0
-    B = np.stack([v, m], 1)
-    inner = slice(1, -1)
-    coef = []
-    for Op in (K1 / Ml[:, None], M1 / Ml[:, None]):
-        Y = Op @ B
-        c, *_ = np.linalg.lstsq(B[inner], Y[inner], rcond=None)
-        assert np.abs(B[inner] @ c - Y[inner]).max() < 1e-9 * np.abs(Y).max()
-        coef.append(c)
-    Ak, Am = coef  # Op B = B A on interior rows
-    # 3D operator on kron(B, B, B) coefficients (z, y, x order)
-    L3 = np.kron(Am, np.kron(Am, Ak)) + np.kron(Am, np.kron(Ak, Am)) + np.kron(Ak, np.kron(Am, Am))
     dt = 0.4 * 2.0 / (alpha * 36.0 / h ** 2)
-    step = np.eye(8) - dt * alpha * L3
-    c0 = np.zeros(8)
-    # sine = (v + m) per direction -> all 8 combinations with coefficient 1
-    c0[:] = 1.0
     nsteps = 6
-    cN = np.linalg.matrix_power(step, nsteps) @ c0
-    basis = np.kron(B, np.kron(B, B))  # columns: (z,y,x) combos in the same order as L3
     A0 = 80.0
     T = prob.T_D + A0 * _sine_field(2, n)
     rc = o.init_history()
     o.explicit_steps(T, rc, 0.0, dt, nsteps)
-    np.testing.assert_allclose(T, prob.T_D + A0 * basis @ cN, rtol=0, atol=1e-11 * A0)
+    np.testing.assert_allclose(T, prob.T_D + A0 * q2_explicit(n, alpha, dt, nsteps), rtol=0, atol=1e-11 * A0)
 
 
 @pytest.mark.parametrize("deg", [1, 2])
