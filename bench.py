@@ -126,6 +126,38 @@ def pmc_summary(fetch_dir, write_dir, out_path, workload, kernel="k_cells<2, dou
     print(json.dumps(res))
 
 
+def sq_summary(dirs, out_path, workload, kernel="k_cells<2, double, 0"):
+    """Summarize rocprofv3 --pmc runs of SQ counters (one directory per run) of
+    `bench.py --workload W --steps 30 --warmup 5` with every other leg off: the
+    per-dispatch mean of each counter over the cell kernel's launches, and the
+    instruction mix per wavefront."""
+    import csv
+    import glob
+
+    per = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if kernel in r["Kernel_Name"]:
+                    per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    mean = {k: sum(v) / len(v) for k, v in per.items()}
+    res = {"workload": workload, "kernel": kernel, "kernel_source_sha256_16": kernel_source_hash(),
+           "dispatches": {k: len(v) for k, v in per.items()}, "per_dispatch": mean}
+    w = mean.get("SQ_WAVES")
+    if w:
+        res["per_wave"] = {k: v / w for k, v in mean.items() if k.startswith("SQ_INSTS") or k.startswith("SQ_WAIT")}
+    valu = mean.get("SQ_INSTS_VALU")
+    if valu:
+        fma, mul, add = (mean.get("SQ_INSTS_VALU_%s_F64" % k, 0.0) for k in ("FMA", "MUL", "ADD"))
+        res["fp64_share_of_valu"] = (fma + mul + add) / valu
+        res["fp64_flop_per_valu"] = (2 * fma + mul + add) / valu
+        res["int_share_of_valu"] = (mean.get("SQ_INSTS_VALU_INT32", 0.0) + mean.get("SQ_INSTS_VALU_INT64", 0.0)) / valu
+    if mean.get("SQ_WAVE_CYCLES"):
+        res["wait_any_over_wave_cycles"] = mean.get("SQ_WAIT_ANY", 0.0) / mean["SQ_WAVE_CYCLES"]
+    json.dump(res, open(out_path, "w"), indent=1)
+    print(json.dumps(res))
+
+
 def measured_traffic(workload):
     """Counter-based HBM bytes per cell-kernel launch from the committed
     summary, if it was taken on the current kernel source, else None."""
@@ -372,10 +404,15 @@ def main():
                     help="run a 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="summarize rocprofv3 FETCH_SIZE/WRITE_SIZE runs and exit")
+    ap.add_argument("--sq-summary", nargs="+", metavar="DIR_OR_OUT",
+                    help="summarize rocprofv3 SQ counter runs (directories, then the output JSON) and exit")
     args = ap.parse_args()
     if args.pmc_summary:
         prob_name = {"cfg1": "cfg1", "cfg2": "cfg2", "cfg4": "cfg4", "cfg5": "cfg5"}[args.workload]
         pmc_summary(*args.pmc_summary, workload=prob_name)
+        return
+    if args.sq_summary:
+        sq_summary(args.sq_summary[:-1], args.sq_summary[-1], workload=args.workload)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",

@@ -323,12 +323,19 @@ def test_full_size_real_law_gradient_vs_oracle():
 def test_full_size_central_differences_without_latent_heat():
     """The 3000-step run of the differentiation workload with the seeded k(T)
     and c_p(T) tables, the powder history and the moving source, but no latent
-    heat: central differences of J at h = 1e-4 relative against the adjoint for
-    three tracks and the absorptivity.  (With latent heat the apparent capacity
-    jumps at T_s and T_l, so J itself jumps wherever a node's temperature
-    crosses those values one step earlier or later: central differences at any
-    h then measure the jumps, not the derivative, and the gradient is checked
-    against the oracle's adjoint instead.)"""
+    heat: central differences of J against the adjoint for three tracks and the
+    absorptivity.  (With latent heat the apparent capacity jumps at T_s and
+    T_l, so J itself jumps wherever a node's temperature crosses those values
+    one step earlier or later: central differences at any h then measure the
+    jumps, not the derivative, and the gradient is checked against the oracle's
+    adjoint instead.)  Without latent heat J is continuous but only piecewise
+    smooth: the tables are piecewise linear in T and the consolidated fraction
+    is a running maximum, so a perturbation moves Gauss points across kinks and
+    a central difference carries an error of first order in h.  At the
+    workload's h = 1e-4 (relative) the agreement is bounded by 1e-3 (measured
+    0.9e-4 .. 2.5e-4); it tightens as h shrinks, and at h = 1e-7 central
+    differences agree with the adjoint to the 1e-5 bar (measured 3e-8 .. 4e-7;
+    J ~ 4e7 is deterministic, so round-off stays near 1e-7 there)."""
     need_gpu()
     prob, sim, dt = _full_size(latent=False)
     P0 = prob.tracks[:, 7].copy()
@@ -343,21 +350,21 @@ def test_full_size_central_differences_without_latent_heat():
         torch.cuda.synchronize()
         return Jv.item()
 
-    hrel = 1e-4
     for name, k in [("P0", 0), ("P5", 5), ("P9", 9), ("A", None)]:
         ad = g["dJdP"][k].item() if k is not None else g["dJdA"].item()
-        Js = []
-        for sgn in (1.0, -1.0):
-            P, A = P0.copy(), A0
-            if k is None:
-                A = A0 * (1.0 + sgn * hrel)
-                step = A0 * hrel
-            else:
-                P[k] = P0[k] * (1.0 + sgn * hrel)
-                step = P0[k] * hrel
-            Js.append(J_at(P, A))
-        fd = (Js[0] - Js[1]) / (2.0 * step)
-        err = abs(fd - ad) / abs(ad)
-        print(f"{name}: adjoint {ad:.10e} central difference (h = {hrel:g} rel) {fd:.10e} rel diff {err:.2e}")
-        assert err <= 1e-4, name
+        for hrel, bound in ((1e-4, 1e-3), (1e-7, 1e-5)):
+            Js = []
+            for sgn in (1.0, -1.0):
+                P, A = P0.copy(), A0
+                if k is None:
+                    A = A0 * (1.0 + sgn * hrel)
+                    step = A0 * hrel
+                else:
+                    P[k] = P0[k] * (1.0 + sgn * hrel)
+                    step = P0[k] * hrel
+                Js.append(J_at(P, A))
+            fd = (Js[0] - Js[1]) / (2.0 * step)
+            err = abs(fd - ad) / abs(ad)
+            print(f"{name}: adjoint {ad:.10e} central difference (h = {hrel:g} rel) {fd:.10e} rel diff {err:.2e}")
+            assert err <= bound, (name, hrel)
     sim.set_track_powers(P0, A0)
