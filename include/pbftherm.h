@@ -216,7 +216,9 @@ pbf_status pbf_bind_device(pbf_ctx *ctx, void *workspace, size_t bytes, void *st
 
 /* T[n_dofs] <- T0 (T_D on Dirichlet nodes); rc[n_hist_qp] <- initial
  * consolidated fraction (0 powder, 1 consolidated).  rc may be NULL when
- * n_hist_qp is 0.  Asynchronous. */
+ * n_hist_qp is 0.  T0 is also the reference temperature of the FP32 operator
+ * (it evaluates T - T0).  Needs a mesh and a material; a bound workspace only
+ * on octree meshes.  Asynchronous. */
 pbf_status pbf_init_state(pbf_ctx *ctx, double T0, double *T, double *rc, void *stream);
 
 /* ---- explicit scheme (Section 3.2, eq. forward_euler) -------------------------
@@ -228,6 +230,26 @@ pbf_status pbf_init_state(pbf_ctx *ctx, double T0, double *T, double *rc, void *
  * PBF_PREC_FP32.  The result is in T.  Asynchronous. */
 pbf_status pbf_explicit_steps(pbf_ctx *ctx, double *T, double *T_tmp, double *rc, double t0,
                               double dt, int n_steps, int precision, void *stream);
+
+/* pbf_explicit_steps for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same steps, kernels and results as pbf_explicit_steps, but
+ * no workspace has to be bound.  The step's scratch (the device copies of the
+ * material law and the column-face partial sums) lives in a static device
+ * array of 32 MiB per GPU that the library holds until the process ends; the
+ * call allocates nothing.  Box meshes only (PBF_EMESH on octrees).  Meshes
+ * whose scratch exceeds 32 MiB are refused with PBF_ENOMEM (Q2 boxes up to
+ * about 5M nodes fit); *scratch_bytes (may be NULL) receives the scratch the
+ * mesh needs, also when it is refused.  Requires a mesh and a material
+ * (PBF_ESTATE otherwise); a bound workspace is neither needed nor touched.
+ * Every call on one GPU uses that GPU's array: calls that overlap in time on
+ * the same GPU (other streams, other threads, other contexts) race and must
+ * be serialized by the caller.  The law is copied into the array at every
+ * call, which waits for the stream once before the steps are enqueued; the
+ * steps themselves are asynchronous.  The stream must belong to the current
+ * device. */
+pbf_status pbf_explicit_steps_noalloc(pbf_ctx *ctx, double *T, double *T_tmp, double *rc, double t0, double dt,
+                                      int n_steps, int precision, size_t *scratch_bytes, void *stream);
 
 /* f(T) and C~(T) at time t into device arrays f, C (n_dofs doubles each) with the
  * history updated in rc as in a step (eq. vector_evaluation).  Asynchronous. */

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -988,6 +989,76 @@ pbf_status oct_upload(pbf_ctx *c, hipStream_t s, bool all)
 
 }  // namespace
 
+// ---- explicit steps without a workspace ----------------------------------
+// The scratch of the explicit step on boxes (the device copies of the laws and
+// the parity slots of the column-face partial sums) lives in one static device
+// array per GPU.  Host code never names the array in a launch or a copy: its
+// device address is taken once per device with hipGetSymbolAddress (with that
+// device current) and kept here.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// device address of the static scratch array on the current device
+pbf_status static_scratch(pbf_ctx *c, char **out)
+{
+    int dev = -1;
+    PBF_HIP(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(c, PBF_EDEVICE, "device %d: the static scratch supports devices 0..%d", dev,
+                    kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(c, PBF_EDEVICE, "hipGetSymbolAddress of the static scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return PBF_OK;
+}
+
+// Points the context's law and slot arrays into the static scratch for the
+// duration of one call and restores the bound workspace's pointers after it.
+struct ScratchBinding {
+    pbf_ctx *c;
+    Law<double> *law64, *lin64, *zero64;
+    Law<float> *law32;
+    double *slots;
+    bool laws_dirty;
+    ScratchBinding(pbf_ctx *ctx, char *base)
+        : c(ctx), law64(ctx->d_law64), lin64(ctx->d_lin64), zero64(ctx->d_zero64), law32(ctx->d_law32),
+          slots(ctx->d_slots), laws_dirty(ctx->laws_dirty)
+    {
+        char *p = base;
+        c->d_law64 = (Law<double> *)p;
+        p += align256(sizeof(Law<double>));
+        c->d_lin64 = (Law<double> *)p;
+        p += align256(sizeof(Law<double>));
+        c->d_zero64 = (Law<double> *)p;
+        p += align256(sizeof(Law<double>));
+        c->d_law32 = (Law<float> *)p;
+        p += align256(sizeof(Law<float>));
+        c->d_slots = (double *)p;
+        c->laws_dirty = true;  // another call may have left its own laws in the array
+    }
+    ~ScratchBinding()
+    {
+        c->d_law64 = law64;
+        c->d_lin64 = lin64;
+        c->d_zero64 = zero64;
+        c->d_law32 = law32;
+        c->d_slots = slots;
+        c->laws_dirty = laws_dirty;
+    }
+};
+}  // namespace
+
 extern "C" {
 
 pbf_status pbf_create(pbf_ctx **out)
@@ -1386,8 +1457,11 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
 pbf_status pbf_init_state(pbf_ctx *c, double T0, double *T, double *rc, void *stream)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
-    pbf_status st = check_bound(c);
-    if (st) return st;
+    if (!c->has_mesh) return fail(c, PBF_ESTATE, "no mesh: call pbf_mesh_box first");
+    if (!c->has_material) return fail(c, PBF_ESTATE, "no material: call pbf_set_material first");
+    // box meshes need no workspace here (the fills take their sizes as arguments)
+    if (c->octree && !c->bound) return fail(c, PBF_ESTATE, "no device workspace: call pbf_bind_device first");
+    pbf_status st = PBF_OK;
     if (!T) return fail(c, PBF_EINVAL, "T is NULL");
     if (n_hist_qp(c) > 0 && !rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
     if (!std::isfinite(T0)) return fail(c, PBF_EINVAL, "T0 must be finite");
@@ -1396,7 +1470,7 @@ pbf_status pbf_init_state(pbf_ctx *c, double T0, double *T, double *rc, void *st
         c->Tref = T0;
         c->laws_dirty = true;
     }
-    if ((st = upload_laws(c, s))) return st;
+    if (c->bound && (st = upload_laws(c, s))) return st;
     PBF_HIP(c, launch_fill(T, T0, alloc_dofs(c), s));
     PBF_HIP(c, launch_init_dirichlet(T, geometry(c), c->T_D, s));
     if (c->growing) {
@@ -1427,6 +1501,43 @@ pbf_status pbf_explicit_steps(pbf_ctx *c, double *T, double *T_tmp, double *rc, 
         return fail(c, PBF_EINVAL, "precision must be 64 or 32");
     if (c->octree && precision != PBF_PREC_FP64) return fail(c, PBF_EINVAL, "octree meshes run in FP64 only");
     hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_laws(c, s))) return st;
+    double *cur = T, *nxt = T_tmp;
+    for (int n = 0; n < n_steps; ++n) {
+        const double t = t0 + n * dt;
+        st = operator_pass(c, 0, precision, LAW_FULL, cur, nxt, nullptr, nullptr, rc, t, dt, s);
+        if (st) return st;
+        std::swap(cur, nxt);
+    }
+    if (cur != T) PBF_HIP(c, hipMemcpyAsync(T, cur, n_dofs(c) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return PBF_OK;
+}
+
+pbf_status pbf_explicit_steps_noalloc(pbf_ctx *c, double *T, double *T_tmp, double *rc, double t0, double dt,
+                                      int n_steps, int precision, size_t *scratch_bytes, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->has_mesh) return fail(c, PBF_ESTATE, "no mesh: call pbf_mesh_box first");
+    if (!c->has_material) return fail(c, PBF_ESTATE, "no material: call pbf_set_material first");
+    if (c->octree) return fail(c, PBF_EMESH, "explicit steps without a workspace run on box meshes only");
+    const long long faces = slot_entries(c);
+    const size_t need = align256(sizeof(Law<double>)) * 3 + align256(sizeof(Law<float>)) +
+                        align256(8 * (size_t)faces * sizeof(double));
+    if (scratch_bytes) *scratch_bytes = need;
+    if (need > kStaticScratchBytes)
+        return fail(c, PBF_ENOMEM, "mesh needs %zu bytes of scratch; the static scratch holds %zu bytes", need,
+                    kStaticScratchBytes);
+    if (!T || !T_tmp || T == T_tmp) return fail(c, PBF_EINVAL, "T and T_tmp must be distinct device arrays");
+    if (n_hist_qp(c) > 0 && !rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
+    if (n_steps < 0) return fail(c, PBF_EINVAL, "n_steps must be >= 0");
+    if (!(dt > 0) || !std::isfinite(t0)) return fail(c, PBF_EINVAL, "need dt > 0 and finite t0");
+    if (precision != PBF_PREC_FP64 && precision != PBF_PREC_FP32)
+        return fail(c, PBF_EINVAL, "precision must be 64 or 32");
+    char *base = nullptr;
+    pbf_status st = static_scratch(c, &base);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    ScratchBinding bind(c, base);
     if ((st = upload_laws(c, s))) return st;
     double *cur = T, *nxt = T_tmp;
     for (int n = 0; n < n_steps; ++n) {

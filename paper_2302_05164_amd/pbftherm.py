@@ -82,6 +82,8 @@ SIGNATURES = {
     "pbf_bind_device": [_vp, _vp, C.c_size_t, _vp],
     "pbf_init_state": [_vp, C.c_double, _vp, _vp, _vp],
     "pbf_explicit_steps": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp],
+    "pbf_explicit_steps_noalloc": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int,
+                                   C.POINTER(C.c_size_t), _vp],
     "pbf_assemble": [_vp, _vp, _vp, C.c_double, _vp, _vp, C.c_int, _vp],
     "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
     "pbf_stability_dt": [_vp, _vp, C.c_int, _dp, _dp, _vp],
@@ -303,6 +305,18 @@ class Simulation:
             int(precision), self._stream()))
         return T
 
+    def explicit_steps_noalloc(self, T, rc, t0, dt, n_steps, T_tmp, precision=PREC_FP64):
+        """pbf_explicit_steps_noalloc: the same steps with the scratch in the
+        library's static device array (no workspace needed).  Returns the
+        scratch bytes the mesh needs."""
+        i = self.info()
+        need = C.c_size_t(0)
+        self._check(self.lib.pbf_explicit_steps_noalloc(
+            self.ctx, _f64(T, i["n_dofs"], "T"), _f64(T_tmp, i["n_dofs"], "T_tmp"),
+            _ptr(rc) if i["n_hist_qp"] else None, float(t0), float(dt), int(n_steps),
+            int(precision), C.byref(need), self._stream()))
+        return need.value
+
     def assemble(self, T, rc, t, precision=PREC_FP64):
         i = self.info()
         f = torch.empty_like(T)
@@ -504,11 +518,12 @@ class Simulation:
         return a.value, b.value, n.value
 
 
-def from_problem(prob, device="cuda:0", leaves=None, active_layers=None):
+def from_problem(prob, device="cuda:0", leaves=None, active_layers=None, bind=True):
     """Simulation set up from a problem description object with the attributes
     of pbf_workloads.Problem (argument marshalling only); an octree mesh when the
     problem (or the `leaves` argument) holds leaves; a growing box with the bottom
-    active_layers cell layers active when given."""
+    active_layers cell layers active when given; no workspace is bound when
+    bind is False."""
     lv = leaves if leaves is not None else getattr(prob, "leaves", None)
     s = Simulation(prob.degree, prob.nx, prob.ny, prob.nz, prob.L, device=device,
                    max_level=getattr(prob, "max_level", 0), leaves=lv)
@@ -523,5 +538,6 @@ def from_problem(prob, device="cuda:0", leaves=None, active_layers=None):
                            prob.C_P, prob.C_T, prob.C_M, prob.h_v, prob.T_h0, prob.dT_max)
     if active_layers is not None:
         s.set_active_layers(active_layers)
-    s.bind()
+    if bind:
+        s.bind()
     return s

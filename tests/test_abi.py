@@ -112,3 +112,31 @@ def test_workspace_sizes_face_slots_and_rejects_oversized_boxes():
         assert b"too large" in L.pbf_last_error(ctx)
     finally:
         L.pbf_destroy(ctx)
+
+
+def test_noalloc_steps_host_refusals():
+    """pbf_explicit_steps_noalloc refuses on the host, before any device call:
+    no material, octree meshes, and boxes whose scratch exceeds the 32 MiB
+    static array (reporting the bytes the mesh needs)."""
+    import numpy as np
+    from paper_2302_05164_amd import pbftherm
+    L, ctx = _ctx()
+    need = C.c_size_t(0)
+    try:
+        assert L.pbf_mesh_box(ctx, 2, 128, 128, 64, 4e-3, 4e-3, 2e-3) == 0
+        assert L.pbf_explicit_steps_noalloc(ctx, None, None, None, 0.0, 1e-6, 1, 64, C.byref(need), None) == -7
+        T = np.array([293.0, 3000.0])
+        k = np.array([20.0, 30.0])
+        dp = C.POINTER(C.c_double)
+        m = pbftherm._Material(2, T.ctypes.data_as(dp), k.ctypes.data_as(dp), k.ctypes.data_as(dp),
+                               7900.0, 1563.0, 1623.0, 0.0, 0.01, 0.0)
+        assert L.pbf_set_material(ctx, C.byref(m)) == 0
+        assert L.pbf_explicit_steps_noalloc(ctx, None, None, None, 0.0, 1e-6, 1, 64, C.byref(need), None) == -2
+        assert need.value > 32 << 20
+        assert b"static scratch" in L.pbf_last_error(ctx)
+        lv = np.array([0, 0, 0, 0], dtype=np.int32)
+        assert L.pbf_mesh_octree(ctx, 2, 1, 1, 1, 1e-3, 1e-3, 1e-3, 0, 1,
+                                 lv.ctypes.data_as(C.POINTER(C.c_int32))) == 0
+        assert L.pbf_explicit_steps_noalloc(ctx, None, None, None, 0.0, 1e-6, 1, 64, None, None) == -3
+    finally:
+        L.pbf_destroy(ctx)
