@@ -282,118 +282,272 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
     }
 }
 
-// Owner-computes completion of the nodes of one cell layer (explicit step or
-// assembly).  The lane of cell (lx, ly) owns the nodes of its cell with local
-// x and y in 1..P (plus 0 on the column's low faces).  The sum order of every
-// node is fixed: carry (cells below), own, right, upper, diagonal neighbour.
-// Top-plane sums are carried in sC to the next layer; nodes on column faces and
-// segment ends go to the parity slot array; the others are completed here.
-// Everything is straight-line per lane: the law constants are read once, the
-// capacity hinges are truncated once per layer to those that some node of the
-// wave exceeds, and every node ends in one store through a selected address.
+// Lane mapping of node-plane loads: the P*kTX + 1 nodes of a row are loaded by
+// P*kTX consecutive lanes (one coalesced row segment each) plus one lane for
+// the row's last node; the rows of `np` consecutive planes (BY rows each) are
+// dealt out kTPB / (P*kTX) rows per pass.  Element e of a lane is row
+// (tid / W) + RPP*e at column tid % W for e < NPASS, and the last node of row
+// tid for e == NPASS.  Offsets are 32-bit, relative to the planes' first node
+// (i0, j0, k); the caller checks that a column's planes fit in 32 bits.
+template <int P, int kTY, int NP>
+struct PlaneRows {
+    static constexpr int W = P * kTX, BX = W + 1, BY = P * kTY + 1, kTPB = kTX * kTY;
+    static constexpr int RPP = kTPB / W, NROWS = NP * BY, NPASS = (NROWS + RPP - 1) / RPP;
+    static constexpr int NE = NPASS + 1;  // elements per lane
+    // row and column of element e of lane tid (row < 0: no element)
+    __device__ static __forceinline__ void at(int tid, int e, int &row, int &li)
+    {
+        if (e < NPASS) {
+            row = tid / W + RPP * e;
+            li = tid % W;
+            if (row >= NROWS) row = -1;
+        } else {
+            row = tid < NROWS ? tid : -1;
+            li = W;
+        }
+    }
+    // plane and row within the plane of a row index (row >= 0)
+    __device__ static __forceinline__ void split(int row, int &lp, int &lj)
+    {
+        lp = 0;
+#pragma unroll
+        for (int k = 1; k < NP; ++k) lp += row >= k * BY ? 1 : 0;
+        lj = row - lp * BY;
+    }
+};
+
+// 1/x for the positive, normal capacities of the update: hardware reciprocal
+// refined by two Newton steps (relative error near one unit in the last place).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// 1/m of the 1D row-sum lumped mass (h (1/6, 2/3, 1/6) per Q2 cell, h (1/2, 1/2)
+// per Q1 cell) at a node: midpoint, interior vertex or boundary vertex
+template <int P>
+__device__ __forceinline__ double inv_mass_1d(bool midpoint, bool boundary, double ih)
+{
+    if constexpr (P == 2) return (midpoint ? 1.5 : (boundary ? 6.0 : 3.0)) * ih;
+    else return (boundary ? 2.0 : 1.0) * ih;
+}
+
+// Completion of the nodes of one cell layer (explicit step or assembly), in
+// two parts that share one barrier after the LDS staging of the cell vectors.
+//
+// Interior nodes (column-local x and y index in 1..P*kTX-1 and 1..P*kTY-1): the
+// lane of cell (lx, ly) owns its cell's nodes with local x and y in 1..P.  Their
+// sum order is fixed: carry (cells below), own, right, upper, diagonal
+// neighbour.  None of them lies on a column face, so every one is completed
+// here (straight-line code: no face test, 32-bit offsets from the layer's
+// base, a reciprocal instead of a division) except on the end planes of a
+// segment, which go to the slot array as a whole.
+//
+// Perimeter nodes (column-local x or y index 0 or P*kTX, P*kTY): spread over
+// all lanes, one (position, z-plane) item each; contributions of the (one to
+// four) containing cells of the column in a fixed order (cells by y, then x),
+// read from the staged x = 0 planes and y = 0 rows and from the staged high
+// faces of the last row and column (sE); top-plane sums are carried in sPC
+// (two buffers alternating by layer, since the item of a node's bottom plane
+// and that of its top plane may run on different lanes).  Column-face and
+// segment-end nodes store their partial sums to the slot array; boundary nodes
+// of the domain are completed here.
 template <int P, int kTY, int MODE, typename Q, typename R>
-__device__ __forceinline__ void owner_update(Q &q, const R *fe, const double *sS, double *sC,
-                                             const double *sTl, int r0, int tid, int lx, int ly,
-                                             int cx, int cy, int k0, int seg, bool first, bool last,
-                                             double *slots, long long NXY)
+__device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *sS, const double *sE,
+                                               double *sC, double *sPC, const double *sT, int r0, int tid,
+                                               int lx, int ly, int tx, int ty, int cz, int seg, bool first,
+                                               bool last, bool active, double *slots)
 {
     constexpr int N = P + 1, kTPB = kTX * kTY;
     constexpr int BX = P * kTX + 1, BY = P * kTY + 1, PLANE = BX * BY;
-    const bool hasR = lx < kTX - 1 && cx + 1 < q.nx;
-    const bool hasU = ly < kTY - 1 && cy + 1 < q.ny;
-    const double *sTz[N];  // node plane az of the layer (rotating slots)
-#pragma unroll
-    for (int az = 0; az < N; ++az) sTz[az] = sTl + (r0 + az < N ? r0 + az : r0 + az - N) * PLANE;
+    constexpr int NPER = 2 * BY + 2 * (BX - 2);  // perimeter positions of a node plane
     ConstLaw<double> &L = const_law(q.nlaw);
-    // capacity hinges that some node of the wave exceeds (hinges above every
-    // node add exactly zero)
-    int nh = 0;
-    if constexpr (MODE != 2) {
-        double tmax = sTz[0][0];
-#pragma unroll
-        for (int a = 1; a < N * N * N; ++a) tmax = fmax(tmax, sTz[a / (N * N)][((a / N) % N) * BX + a % N]);
-        while (nh < L.n_hinge && __any(tmax > L.b[nh])) ++nh;
-    }
-    const double c0 = L.c0, Ts = L.Ts, Tl = L.Tl, lat = L.lat, rho = L.rho;
     const int NX = q.NX, NY = q.NY, NZ = q.NZ;
+    const int i0 = P * kTX * tx, j0 = P * kTY * ty, k0 = P * cz;
     const unsigned dmask = q.dmask;
-    const double hx = q.hx, hy = q.hy, hz = q.hz, dt = q.dt, T_D = q.T_D;
-    const FaceMap fm = face_map_of(q);
-    // nodes with local y = 0 belong to the lanes of the column's first row only
-    // (all in the first wavefront): the other wavefronts skip them as a whole
-    const bool has_row0 = __builtin_amdgcn_readfirstlane(tid) < kTX;
+    const double dtr = q.dt / L.rho;
+    const double ihx = 1.0 / q.hx, ihy = 1.0 / q.hy, ihz = 1.0 / q.hz;  // uniform
+    int slot_r[N];  // node plane az of the layer (rotating slots)
 #pragma unroll
-    for (int az = 0; az < N; ++az) {
-        // capacities of the plane's nodes, one hinge at a time (each law
-        // coefficient read once per plane; every node adds its hinges in
-        // increasing order)
-        double cpl[N * N];
-        if (MODE != 2 && (az < P || last)) {
+    for (int az = 0; az < N; ++az) slot_r[az] = (r0 + az < N ? r0 + az : r0 + az - N) * PLANE;
+
+    // ---------------- interior nodes ----------------
+    if (active) {
+        const int cx = kTX * tx + lx, cy = kTY * ty + ly;
+        const bool hasR = cx + 1 < q.nx, hasU = cy + 1 < q.ny;  // right/upper cell exists
+        const bool xin = lx < kTX - 1, yin = ly < kTY - 1;     // the ax = P / ay = P nodes are interior
+        const bool bx = cx == q.nx - 1, by = cy == q.ny - 1;   // ... and on the domain's high boundary
+        const double *sTl = sT + P * (ly * BX + lx);
+        // capacity hinges that some node of the wave exceeds
+        int nh = 0;
+        if constexpr (MODE != 2) {
+            double tmax = sTl[slot_r[0] + BX + 1];
 #pragma unroll
-            for (int j = 0; j < N * N; ++j) {
-                const double T = sTz[az][(j / N) * BX + j % N];
-                cpl[j] = c0 + ((T >= Ts && T <= Tl) ? lat : 0.0);
+            for (int az = 0; az < N; ++az)
+#pragma unroll
+                for (int ay = 1; ay < N; ++ay)
+#pragma unroll
+                    for (int ax = 1; ax < N; ++ax) tmax = fmax(tmax, sTl[slot_r[az] + ay * BX + ax]);
+            while (nh < L.n_hinge && __any(tmax > L.b[nh])) ++nh;
+        }
+        const double c0 = L.c0, Ts = L.Ts, Tl = L.Tl, lat = L.lat;
+        // base of the layer's nodes (uniform) and the lane's 32-bit offset
+        double *const out = MODE == 0 ? q.Tout : q.fout;
+        const long long base = (long long)i0 + (long long)NX * j0 + (long long)NX * NY * k0;
+        const unsigned NXY = unsigned(NX) * unsigned(NY);
+        const unsigned lane_off = unsigned(P * lx) + unsigned(NX) * unsigned(P * ly);
+#pragma unroll
+        for (int az = 0; az < N; ++az) {
+            if (az == P && !last) {  // uniform: partial sums carried to the next layer
+#pragma unroll
+                for (int ay = 1; ay < N; ++ay)
+#pragma unroll
+                    for (int ax = 1; ax < N; ++ax) {
+                        const int n = (az * N + ay) * N + ax;
+                        double f = double(fe[n]);
+                        if (ax == P) f += hasR ? sS[(az * N + ay) * kTPB + tid + 1] : 0.0;
+                        if (ay == P) f += hasU ? sS[(N * N + az * P + ax - 1) * kTPB + tid + kTX] : 0.0;
+                        if (ax == P && ay == P) f += (hasR && hasU) ? sS[(az * N) * kTPB + tid + kTX + 1] : 0.0;
+                        sC[(ay * N + ax) * kTPB + tid] = f;
+                    }
+                continue;
             }
-            for (int h = 0; h < nh; ++h) {
-                const double bh = L.b[h], dch = L.dc[h];
+            const int gk = k0 + az;
+            // uniform over the workgroup: segment ends are column faces
+            const bool zface = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1);
+            const bool zlater = az == 0 && first && gk > 0;
+            const bool zdir = ((dmask & 16u) && gk == 0) || ((dmask & 32u) && gk == NZ - 1);
+            const double iz = inv_mass_1d<P>(P == 2 && az == 1, gk == 0 || gk == NZ - 1, ihz);
+            const int zf = az == 0 ? seg - 1 : seg;
+            // capacities of the plane's interior nodes, one hinge at a time (each
+            // law coefficient read once per plane; every node adds its hinges in
+            // increasing order)
+            double cpl[P * P];
+            if constexpr (MODE != 2) {
 #pragma unroll
-                for (int j = 0; j < N * N; ++j)
-                    cpl[j] = __builtin_fma(dch, fmax0(sTz[az][(j / N) * BX + j % N] - bh, 0.0), cpl[j]);
+                for (int j = 0; j < P * P; ++j) {
+                    const double T = sTl[slot_r[az] + (j / P + 1) * BX + j % P + 1];
+                    cpl[j] = c0 + ((T >= Ts && T <= Tl) ? lat : 0.0);
+                }
+                for (int h = 0; h < nh; ++h) {
+                    const double bh = L.b[h], dch = L.dc[h];
+#pragma unroll
+                    for (int j = 0; j < P * P; ++j)
+                        cpl[j] = __builtin_fma(dch, fmax0(sTl[slot_r[az] + (j / P + 1) * BX + j % P + 1] - bh, 0.0), cpl[j]);
+                }
+            }
+#pragma unroll
+            for (int ay = 1; ay < N; ++ay) {
+                if (ay == P && !yin) continue;
+#pragma unroll
+                for (int ax = 1; ax < N; ++ax) {
+                    if (ax == P && !xin) continue;
+                    const int n = (az * N + ay) * N + ax;
+                    double f = 0.0;
+                    if (az == 0 && !first) f = sC[(ay * N + ax) * kTPB + tid];
+                    f += double(fe[n]);
+                    if (ax == P) f += hasR ? sS[(az * N + ay) * kTPB + tid + 1] : 0.0;
+                    if (ay == P) f += hasU ? sS[(N * N + az * P + ax - 1) * kTPB + tid + kTX] : 0.0;
+                    if (ax == P && ay == P) f += (hasR && hasU) ? sS[(az * N) * kTPB + tid + kTX + 1] : 0.0;
+                    const unsigned off = lane_off + unsigned(ax) + unsigned(NX) * unsigned(ay) + NXY * unsigned(az);
+                    const bool dir = zdir || ((dmask & 2u) && bx && ax == P) || ((dmask & 8u) && by && ay == P);
+                    if constexpr (MODE == 2) {
+                        if (zface)
+                            slots[q.fm.GX + q.fm.GY + ((long long)zf * NY + j0 + P * ly + ay) * NX + i0 + P * lx + ax] = f;
+                        else
+                            out[base + off] = f;
+                        continue;
+                    }
+                    const double T = sTl[slot_r[az] + ay * BX + ax];
+                    const double c = cpl[(ay - 1) * P + ax - 1];
+                    if constexpr (MODE == 0) {
+                        const double ixm = inv_mass_1d<P>(P == 2 && ax == 1, ax == P && bx, ihx);
+                        const double iym = inv_mass_1d<P>(P == 2 && ay == 1, ay == P && by, ihy);
+                        const double inc = f * (dtr * ixm * iym * iz) * rcp_nr(c);
+                        if (zface) {
+                            const double val = dir ? (zlater ? 0.0 : q.T_D) : (zlater ? inc : T + inc);
+                            slots[q.fm.GX + q.fm.GY + ((long long)zf * NY + j0 + P * ly + ay) * NX + i0 + P * lx + ax] = val;
+                        } else {
+                            out[base + off] = dir ? q.T_D : T + inc;
+                        }
+                    } else {  // MODE 1
+                        if (zface) {
+                            slots[q.fm.GX + q.fm.GY + ((long long)zf * NY + j0 + P * ly + ay) * NX + i0 + P * lx + ax] = f;
+                        } else {
+                            const int gi = i0 + P * lx + ax, gj = j0 + P * ly + ay;
+                            const double m = lumped_mass_1d(gi, NX, P, q.hx) * lumped_mass_1d(gj, NY, P, q.hy) *
+                                             lumped_mass_1d(gk, NZ, P, q.hz);
+                            out[base + off] = f;
+                            q.Cout[base + off] = L.rho * c * m;
+                        }
+                    }
+                }
             }
         }
-#pragma unroll
-        for (int ay = 0; ay < N; ++ay) {
-            if (ay == 0 && !has_row0) continue;  // uniform
-#pragma unroll
-            for (int ax = 0; ax < N; ++ax) {
-                const int n = (az * N + ay) * N + ax;
-                double f = 0.0;
-                if (az == 0 && !first) f = sC[(ay * N + ax) * kTPB + tid];
-                f += double(fe[n]);
-                if (ax == P) {
-                    const double r = sS[(az * N + ay) * kTPB + tid + 1];
-                    f += hasR ? r : 0.0;
-                }
-                if (ay == P) {
-                    const double u = ax == 0 ? sS[(az * N) * kTPB + tid + kTX]
-                                             : sS[(N * N + az * P + ax - 1) * kTPB + tid + kTX];
-                    f += hasU ? u : 0.0;
-                }
-                if (ax == P && ay == P) {
-                    const double d = sS[(az * N) * kTPB + tid + kTX + 1];
-                    f += (hasR && hasU) ? d : 0.0;
-                }
-                if (az == P && !last) {  // uniform: completed by the next layer
-                    sC[(ay * N + ax) * kTPB + tid] = f;
-                    continue;
-                }
-                const bool own = (ax != 0 || lx == 0) && (ay != 0 || ly == 0);
-                const int gi = P * cx + ax, gj = P * cy + ay, gk = k0 + az;
-                const long long g = (long long)gi + (long long)NX * gj + NXY * gk;
-                const bool face = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1) ||
-                                  is_face(gi, P * kTX, NX) || is_face(gj, P * kTY, NY);
-                const double T = sTz[az][ay * BX + ax];
-                const double c = cpl[ay * N + ax];
-                const double m = lumped_mass_1d(gi, NX, P, hx) * lumped_mass_1d(gj, NY, P, hy) *
-                                 lumped_mass_1d(gk, NZ, P, hz);
-                const double C = rho * c * m;
-                const long long t = face_slot(gi, gj, gk, az == 0 ? seg - 1 : seg, P * kTX, P * kTY, NX, NY, NZ, fm);
-                if (MODE == 0) {
-                    // face nodes: the lowest containing column (the first term of the face
-                    // kernel's fixed-order sum) stores its complete update, the others only
-                    // their increment, so the face kernel needs neither T_n nor C~
-                    const bool dir = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ);
-                    const double inc = dt * f / C;
-                    const bool later = (ax == 0 && is_face(gi, P * kTX, NX)) ||
-                                       (ay == 0 && is_face(gj, P * kTY, NY)) || (az == 0 && first && gk > 0);
-                    const double val = dir ? ((face && later) ? 0.0 : T_D) : ((face && later) ? inc : T + inc);
-                    double *dst = face ? slots + t : q.Tout + g;
-                    if (own) *dst = val;
-                } else {
-                    double *dst = face ? slots + t : q.fout + g;
-                    if (own) *dst = f;
-                    if (MODE == 1 && own && !face) q.Cout[g] = C;
-                }
+    }
+
+    // ---------------- perimeter nodes ----------------
+    const double *pc_prev = sPC + ((cz & 1) ^ 1) * NPER;
+    double *pc_cur = sPC + (cz & 1) * NPER;
+    const FaceMap fm = face_map_of(q);
+    for (int it = tid; it < NPER * N; it += kTPB) {
+        const int az = it / NPER, pos = it - az * NPER;
+        int li, lj;
+        if (pos < BY) { li = 0; lj = pos; }
+        else if (pos < 2 * BY) { li = P * kTX; lj = pos - BY; }
+        else if (pos < 2 * BY + BX - 2) { lj = 0; li = pos - 2 * BY + 1; }
+        else { lj = P * kTY; li = pos - 2 * BY - (BX - 2) + 1; }
+        const int gi = i0 + li, gj = j0 + lj, gk = k0 + az;
+        if (gi >= NX || gj >= NY) continue;
+        double f = (az == 0 && !first) ? pc_prev[pos] : 0.0;
+        // containing cells of the column: x cells cxa..cxb, y cells cya..cyb
+        const int cxa = li % P == 0 ? max(li / P - 1, 0) : li / P, cxb = min(li / P, kTX - 1);
+        const int cya = lj % P == 0 ? max(lj / P - 1, 0) : lj / P, cyb = min(lj / P, kTY - 1);
+        for (int cyl = cya; cyl <= cyb; ++cyl) {
+            if (kTY * ty + cyl >= q.ny) break;
+            for (int cxl = cxa; cxl <= cxb; ++cxl) {
+                if (kTX * tx + cxl >= q.nx) break;
+                const int ax = li - P * cxl, ay = lj - P * cyl, t = cxl + kTX * cyl;
+                double v;
+                if (ax == 0) v = sS[(az * N + ay) * kTPB + t];
+                else if (ay == 0) v = sS[(N * N + az * P + ax - 1) * kTPB + t];
+                else if (ax == P && cxl == kTX - 1) v = sE[(az * P + ay - 1) * kTY + cyl];
+                else v = sE[P * N * kTY + (az * P + ax - 1) * kTX + cxl];
+                f += v;
+            }
+        }
+        if (az == P && !last) {
+            pc_cur[pos] = f;
+            continue;
+        }
+        const bool fx = is_face(gi, P * kTX, NX), fy = is_face(gj, P * kTY, NY);
+        const bool fz = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1);
+        const bool face = fx || fy || fz;
+        const long long g = (long long)gi + (long long)NX * gj + (long long)NX * NY * gk;
+        const long long t = face_slot(gi, gj, gk, az == 0 ? seg - 1 : seg, P * kTX, P * kTY, NX, NY, NZ, fm);
+        if constexpr (MODE == 2) {
+            if (face) slots[t] = f;
+            else q.fout[g] = f;
+            continue;
+        }
+        const double T = sT[slot_r[az] + lj * BX + li];
+        const double C = node_capacity(L, T, gi, gj, gk, P, NX, NY, NZ, q.hx, q.hy, q.hz);
+        if constexpr (MODE == 0) {
+            const bool dir = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ);
+            const double inc = q.dt * f / C;
+            const bool later = (li == 0 && fx) || (lj == 0 && fy) || (az == 0 && first && gk > 0);
+            const double val = dir ? ((face && later) ? 0.0 : q.T_D) : ((face && later) ? inc : T + inc);
+            if (face) slots[t] = val;
+            else q.Tout[g] = val;
+        } else {
+            if (face) slots[t] = f;
+            else {
+                q.fout[g] = f;
+                q.Cout[g] = C;
             }
         }
     }
@@ -423,10 +577,13 @@ k_cells(const CellParams<R> p)
     constexpr int N = P + 1, NN = N * N * N;
     constexpr int BX = P * kTX + 1, BY = P * kTY + 1, PLANE = BX * BY, NB = N * PLANE;
     constexpr int NSH = N * N + P * N;  // staged per cell: x = 0 plane, then y = 0 row for x = 1..P
-    constexpr int NPF = (P * PLANE + kTPB - 1) / kTPB;  // prefetched values per lane
     __shared__ double sT[NB];
     __shared__ double sS[NSH * kTPB + kTX + 1];  // padded: neighbour reads of edge lanes stay inside
     __shared__ double sC[N * N * kTPB];  // carry: top-plane partial sums per lane, (y, x) major
+    // high faces of the column's last cell column (x = P, y = 1..P) and last cell
+    // row (y = P, x = 1..P), for the perimeter nodes
+    __shared__ double sE[P * N * (kTX + kTY)];
+    __shared__ double sPC[2 * (2 * (P * kTY + 1) + 2 * (P * kTX - 1))];  // perimeter carries
 
     // Each XCD owns a contiguous range of tiles (whole columns when the range
     // is a multiple of the segment count).  Within it the top segments, which
@@ -451,23 +608,27 @@ k_cells(const CellParams<R> p)
     // the N node planes of the first layer: every load of the lane is issued
     // before the first store, so the latencies overlap
     {
-        constexpr int NL = (NB + kTPB - 1) / kTPB;
-        double val[NL];
+        using PR = PlaneRows<P, kTY, N>;
+        const double *src = p.Tin + ((long long)i0 + (long long)p.NX * j0 + NXY * (P * z0));
+        const int nxl = p.NX - i0, nyl = p.NY - j0;
+        double val[PR::NE];
 #pragma unroll
-        for (int e = 0; e < NL; ++e) {
-            const unsigned idx = threadIdx.x + unsigned(e * kTPB);
-            const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
-            const unsigned li = rem % BX, lj = rem / BX;
-            const int gi = i0 + int(li), gj = j0 + int(lj), gk = P * z0 + int(lp);
+        for (int e = 0; e < PR::NE; ++e) {
+            int row, li;
+            PR::at(threadIdx.x, e, row, li);
+            int lp, lj;
+            PR::split(row, lp, lj);
             val[e] = 0.0;
-            if (idx < unsigned(NB) && gi < p.NX && gj < p.NY)
-                val[e] = p.Tin[(long long)gi + (long long)p.NX * gj + NXY * gk];
+            if (row >= 0 && li < nxl && lj < nyl)
+                val[e] = src[unsigned(lp) * unsigned(NXY) + unsigned(lj) * unsigned(p.NX) + unsigned(li)];
         }
 #pragma unroll
-        for (int e = 0; e < NL; ++e) {
-            const unsigned idx = threadIdx.x + unsigned(e * kTPB);
-            const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
-            if (idx < unsigned(NB)) sT[((P * z0 + int(lp)) % N) * PLANE + rem] = val[e];
+        for (int e = 0; e < PR::NE; ++e) {
+            int row, li;
+            PR::at(threadIdx.x, e, row, li);
+            int lp, lj;
+            PR::split(row, lp, lj);
+            if (row >= 0) sT[((P * z0 + lp) % N) * PLANE + lj * BX + li] = val[e];
         }
     }
     __syncthreads();
@@ -505,41 +666,53 @@ k_cells(const CellParams<R> p)
                 surface_loss_face<P>(q.re, q.hx, q.hy, [&](int ax, int ay) { return top[ay * BX + ax]; }, fe);
             }
             stage_shared<P, kTPB>(sS, fe, tid);
+            if (lx == kTX - 1) {
+#pragma unroll
+                for (int az = 0; az < N; ++az)
+#pragma unroll
+                    for (int ay = 1; ay < N; ++ay) sE[(az * P + ay - 1) * kTY + ly] = double(fe[(az * N + ay) * N + P]);
+            }
+            if (ly == kTY - 1) {
+#pragma unroll
+                for (int az = 0; az < N; ++az)
+#pragma unroll
+                    for (int ax = 1; ax < N; ++ax)
+                        sE[P * N * kTY + (az * P + ax - 1) * kTX + lx] = double(fe[(az * N + P) * N + ax]);
+            }
         }
         __syncthreads();
         // 2. loads of the next layer's new planes (global planes k0+N .. k0+N+P-1)
+        using PR = PlaneRows<P, kTY, P>;
         const bool more = cz + 1 < z1;
-        double pf[NPF];
+        double pf[PR::NE];
         if (more) {
+            const double *src = q.Tin + ((long long)i0 + (long long)q.NX * j0 + NXY * (k0 + N));
+            const int nxl = q.NX - i0, nyl = q.NY - j0;
 #pragma unroll
-            for (int e = 0; e < NPF; ++e) {
-                const unsigned idx = unsigned(tid) + unsigned(e * kTPB);
+            for (int e = 0; e < PR::NE; ++e) {
+                int row, li;
+                PR::at(tid, e, row, li);
+                int lp, lj;
+                PR::split(row, lp, lj);
                 pf[e] = 0.0;
-                if (idx < unsigned(P * PLANE)) {
-                    const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
-                    const unsigned li = rem % BX, lj = rem / BX;
-                    const int gi = i0 + int(li), gj = j0 + int(lj);
-                    if (gi < q.NX && gj < q.NY)
-                        pf[e] = q.Tin[(long long)gi + (long long)q.NX * gj + NXY * (k0 + N + int(lp))];
-                }
+                if (row >= 0 && li < nxl && lj < nyl)
+                    pf[e] = src[unsigned(lp) * unsigned(NXY) + unsigned(lj) * unsigned(q.NX) + unsigned(li)];
             }
         }
-        // 3. owned nodes: sum, carry, completion
-        if (active) {
-            owner_update<P, kTY, MODE>(q, fe, sS, sC, sTl, r0, tid, lx, ly, cx, cy, k0, seg, cz == z0,
-                                       cz == z1 - 1, q.slots + tpar * q.fm.GT, NXY);
-        }
+        // 3. node completion: interior nodes per lane, perimeter spread over the lanes
+        complete_layer<P, kTY, MODE>(q, fe, sS, sE, sC, sPC, sT, r0, tid, lx, ly, tx, ty, cz, seg, cz == z0,
+                                     cz == z1 - 1, active, q.slots + tpar * q.fm.GT);
         __syncthreads();
         // 4. the new planes replace planes k0 .. k0+P-1 (slots r0 .. r0+P-1 mod N)
         if (more) {
 #pragma unroll
-            for (int e = 0; e < NPF; ++e) {
-                const unsigned idx = unsigned(tid) + unsigned(e * kTPB);
-                if (idx < unsigned(P * PLANE)) {
-                    const unsigned lp = idx / PLANE, rem = idx - lp * PLANE;
-                    const int sl = r0 + int(lp) < N ? r0 + int(lp) : r0 + int(lp) - N;
-                    sT[sl * PLANE + rem] = pf[e];
-                }
+            for (int e = 0; e < PR::NE; ++e) {
+                int row, li;
+                PR::at(tid, e, row, li);
+                int lp, lj;
+                PR::split(row, lp, lj);
+                const int sl = r0 + lp < N ? r0 + lp : r0 + lp - N;
+                if (row >= 0) sT[sl * PLANE + lj * BX + li] = pf[e];
             }
             __syncthreads();
         }
