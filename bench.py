@@ -289,9 +289,10 @@ def adjoint_timing(reps=1):
 
 def implicit_timing(sim, T, rc, t, dt=1e-4):
     """One backward-Euler step of dt from the end state of the explicit run,
-    solved by Picard iterations with Jacobi-CG and by Newton's method with
-    restarted GMRES(30) (relative residual 1e-10 per linear system, 1e-8 K on
-    the update); wall time on the library's stream, iteration counts."""
+    solved by Picard iterations with CG and by Newton's method with restarted
+    GMRES(30) (relative residual 1e-10 per linear system, 1e-8 K on the
+    update), each with the Jacobi preconditioner and with the geometric
+    multigrid V-cycle; wall time on the library's stream, iteration counts."""
     import torch
 
     def timed(fn):
@@ -303,18 +304,30 @@ def implicit_timing(sim, T, rc, t, dt=1e-4):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), out
 
-    work = sim.newton_work(30)
     res = {"dt": dt}
-    r1 = rc.clone()
-    ms, (Tp, ip) = timed(lambda: sim.implicit_step(T, r1, t, dt, cg_rtol=1e-10, picard_tol=1e-8, picard_max_it=60))
-    res["picard_cg"] = {"ms": ms, "outer": ip["picard_iters"], "krylov": ip["cg_iters"],
-                        "ms_per_krylov": ms / max(1, ip["cg_iters"])}
-    r2 = rc.clone()
-    ms, (Tn, inw) = timed(lambda: sim.implicit_step_newton(T, r2, t, dt, lin_rtol=1e-10, restart=30,
-                                                           newton_tol=1e-8, newton_max_it=60, work=work))
-    res["newton_gmres"] = {"ms": ms, "outer": inw["newton_iters"], "krylov": inw["lin_iters"],
-                           "ms_per_krylov": ms / max(1, inw["lin_iters"]), "work_bytes": work["bytes"]}
-    res["max_abs_diff_K"] = float((Tp - Tn).abs().max().item())
+    roots = {}
+    for kind in ("jacobi", "multigrid"):
+        sim.set_preconditioner(kind)
+        work = sim.newton_work(30)
+        r1 = rc.clone()
+        ms, (Tp, ip) = timed(lambda: sim.implicit_step(T, r1, t, dt, cg_rtol=1e-10, picard_tol=1e-8,
+                                                       picard_max_it=60))
+        res[f"picard_cg_{kind}"] = {"ms": ms, "outer": ip["picard_iters"], "krylov": ip["cg_iters"],
+                                    "ms_per_krylov": ms / max(1, ip["cg_iters"])}
+        r2 = rc.clone()
+        ms, (Tn, inw) = timed(lambda: sim.implicit_step_newton(T, r2, t, dt, lin_rtol=1e-10, restart=30,
+                                                               newton_tol=1e-8, newton_max_it=60, work=work))
+        res[f"newton_gmres_{kind}"] = {"ms": ms, "outer": inw["newton_iters"], "krylov": inw["lin_iters"],
+                                       "ms_per_krylov": ms / max(1, inw["lin_iters"]), "work_bytes": work["bytes"]}
+        roots[kind] = (Tp, Tn)
+        del work
+    sim.set_preconditioner("jacobi")
+    res["max_abs_diff_K"] = {
+        "picard_vs_newton": float((roots["jacobi"][0] - roots["jacobi"][1]).abs().max().item()),
+        "multigrid_vs_jacobi_picard": float((roots["multigrid"][0] - roots["jacobi"][0]).abs().max().item()),
+        "multigrid_vs_jacobi_newton": float((roots["multigrid"][1] - roots["jacobi"][1]).abs().max().item())}
+    j, m = res["picard_cg_jacobi"], res["newton_gmres_multigrid"]
+    res["best_over_jacobi_picard"] = {"krylov": j["krylov"] / max(1, m["krylov"]), "time": j["ms"] / m["ms"]}
     return res
 
 
@@ -346,39 +359,45 @@ def laplace_timing(sim, info, prob, steps, warmup, step_ms, step_cell_ms):
             "explicit_kernel_fraction_of_laplace_kernel": cell_ms / step_cell_ms}
 
 
-def octree_timing(steps=300, warmup=20):
-    """Explicit steps on the octree workload: Q2 over a 10x10x5 mm part, coarse
-    20x20x10 cells refined to level 6 around the scan path (hanging nodes through
-    their constraints), the state resident in HBM; HIP events on the library's
-    stream around the timed steps."""
-    import ctypes as C
-
-    import torch
-
+def octree_timing(n_explicit=200, n_implicit=1):
+    """The octree schedule on the octree workload (Q2 over a 10x10x5 mm part,
+    coarse 20x20x10 cells refined to level 6 within 200 um of the window
+    [s - 8 mm, s + 100 um] of the scan path around the beam's arc length s,
+    about 5.2M dofs): a bounded sample of the stated 2000 explicit steps with a
+    remesh every 100 and 50 backward-Euler steps of 1 ms (Jacobi-CG to 1e-10),
+    namely the first n_explicit steps (with their remeshes) and the first
+    n_implicit implicit steps.  GPU times from HIP events on the library's
+    stream; remesh times are host wall time (mesh build and transfer)."""
     import pbf_workloads as W
-    from paper_2302_05164_amd import pbftherm
+    from paper_2302_05164_amd import octree_schedule as S
 
     prob = W.cfg3()
-    sim = pbftherm.from_problem(prob, device="cuda:0")
-    n = sim.info()["n_dofs"]
-    nl, nh, ml = C.c_int64(), C.c_int64(), C.c_int()
-    sim._check(sim.lib.pbf_octree_info(sim.ctx, C.byref(nl), C.byref(nh), C.byref(ml)))
-    v0 = torch.tensor(W.seeded_vector(n, 1), device="cuda")
-    dt = prob.dt_factor * sim.stability_dt(v0, 50)
-    T, rc = sim.init_state(prob.T0)
-    T_tmp = torch.empty_like(T)
-    sim.explicit_steps(T, rc, 0.0, dt, warmup, T_tmp=T_tmp)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    sim.explicit_steps(T, rc, warmup * dt, dt, steps, T_tmp=T_tmp)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    return {"workload": prob.name, "n_dofs": n, "leaves": nl.value, "hanging_nodes": nh.value,
-            "max_level": ml.value, "steps": steps, "ms_per_step": ms / steps,
-            "value": n * steps / (ms / 1e3), "unit": "DoF-updates/s",
-            "finite": bool(torch.isfinite(T).all().item()), "T_max": float(T.max().item())}
+    T, rc, sim, rec = S.run(prob, n_explicit=n_explicit, n_implicit=n_implicit)
+    blocks, imp = rec["blocks"], rec["implicit"]
+    ms_expl = sum(b["ms"] for b in blocks) / n_explicit
+    dofs = [b["dofs"] for b in blocks]
+    out = {"workload": prob.name, "dt": rec["dt"], "explicit_steps": n_explicit,
+           "remesh_every": prob.remesh_every, "dofs_per_block": dofs,
+           "leaves_per_block": [b["leaves"] for b in blocks],
+           "hanging_per_block": [b["hanging"] for b in blocks],
+           "ms_per_explicit_step": ms_expl,
+           "value": sum(b["dofs"] * b["steps"] for b in blocks) / (sum(b["ms"] for b in blocks) / 1e3),
+           "unit": "DoF-updates/s",
+           "remesh_host_ms": [round(b["remesh_host_ms"], 1) for b in blocks if "remesh_host_ms" in b],
+           "setup_host_ms": rec["setup_host_ms"],
+           "finite": bool(torch_isfinite(T)), "T_max": float(T.max().item())}
+    if imp:
+        ms_imp = sum(r["ms"] for r in imp) / len(imp)
+        out["implicit"] = {"dt": prob.implicit_dt, "steps": len(imp), "ms_per_step": ms_imp,
+                           "picard_iters": [r["picard"] for r in imp], "cg_iters": [r["cg"] for r in imp],
+                           "ms_per_cg_iter": sum(r["ms"] for r in imp) / max(1, sum(r["cg"] for r in imp)),
+                           "implicit_over_explicit_step": ms_imp / ms_expl}
+    return out
+
+
+def torch_isfinite(T):
+    import torch
+    return torch.isfinite(T).all().item()
 
 
 def progress(msg):

@@ -92,6 +92,49 @@ pbf_status pbf_mesh_box(pbf_ctx *ctx, int degree, int nx, int ny, int nz, double
  * Resets material, laser and binding like pbf_mesh_box. */
 pbf_status pbf_mesh_octree(pbf_ctx *ctx, int degree, int nx, int ny, int nz, double Lx, double Ly,
                            double Lz, int max_level, int64_t n_leaves, const int32_t *leaves);
+/* ---- growing octree builds (Section 4.1, mesh adaptivity and layer activation)
+ * The coarse cells (size h_coarse = 2^max_level h_powder, eq.
+ * coarse_fine_relation, so the finest cell is one powder layer thick) span the
+ * build chamber [0,Lx]x[0,Ly]x[0,Lz]; the active part is z < top (top in
+ * finest cells): cells above it are inactive and carry no dofs, so the leaves
+ * tile [0,Lx]x[0,Ly]x[0, top*h_finest] only.  The free surface (source depth,
+ * surface losses), the powder depth and the Dirichlet face z+ are at z = top.
+ * Every leaf keeps its history (buried unfused powder stays powder).
+ * pbf_mesh_octree_growing: like pbf_mesh_octree with the active top `top`.
+ * pbf_octree_history_min: rc_min[e] (host, n_leaves) = the smallest
+ *   consolidated fraction over the quadrature points of leaf e of the device
+ *   history rc (1 for leaves without history).  Synchronizes.
+ * pbf_octree_layer_leaves: the leaves after activating the layer
+ *   [current top, new_top) (new_top == current top: the current top layer
+ *   alone): the current layer and every cell whose distance to it is at most
+ *   d_haz finest cells (the paper's d_HAZ = 4 h_powder is 4) are refined to
+ *   the finest level; an octet of sibling leaves farther than d_haz below the
+ *   current layer is replaced by its parent if the consolidated fraction exceeds
+ *   r_coarsen (the paper's 0.9) at every quadrature point of all eight (one
+ *   level per activation); the new layer is added at the finest level; then
+ *   leaves two or more levels coarser than a leaf they touch (face, edge or
+ *   vertex) are split until the tree is 2:1 balanced.  rc_min: per-leaf
+ *   minima of the history (host, pbf_octree_history_min; NULL: 1 everywhere);
+ *   leaves: host array of 4*capacity int32 in Morton order (NULL: count only).
+ *   Host only (no workspace needed).
+ * pbf_octree_grow_bytes: prepares the move to such leaves with the active top
+ *   new_top (>= the current top), then pbf_octree_remesh binds the new
+ *   workspace and transfers: dofs inside the old part take the old field,
+ *   dofs above the old top the initial temperature of pbf_init_state; history
+ *   points above the old top start as powder (0 within the powder depth of the
+ *   new top, 1 below), points of a coarsened parent take the minimum over the
+ *   points of its eight old children, the others the nearest Gauss point of
+ *   the old leaf containing them.  pbf_octree_remesh_bytes on a growing build
+ *   keeps the top and uses the same rules.
+ * Errors: PBF_ESTATE without a growing octree or binding, PBF_EMESH for
+ * invalid leaf sets, PBF_EINVAL for a top that moves down. */
+pbf_status pbf_mesh_octree_growing(pbf_ctx *ctx, int degree, int nx, int ny, int nz, double Lx, double Ly,
+                                   double Lz, int max_level, int64_t top, int64_t n_leaves, const int32_t *leaves);
+pbf_status pbf_octree_history_min(pbf_ctx *ctx, const double *rc, double *rc_min, void *stream);
+pbf_status pbf_octree_layer_leaves(pbf_ctx *ctx, const double *rc_min, int64_t new_top, int64_t d_haz,
+                                   double r_coarsen, int32_t *leaves, int64_t capacity, int64_t *n_leaves);
+pbf_status pbf_octree_grow_bytes(pbf_ctx *ctx, int64_t new_top, int64_t n_leaves, const int32_t *leaves,
+                                 size_t *bytes, int64_t *new_n_dofs, int64_t *new_n_hist_qp);
 /* leaves, hanging nodes and finest level of the current octree mesh */
 pbf_status pbf_octree_info(const pbf_ctx *ctx, int64_t *n_leaves, int64_t *n_hanging, int *max_level);
 /* Remesh onto new leaves (same coarse box, degree and max_level).
@@ -180,6 +223,23 @@ typedef struct {
     const pbf_track *tracks;   /* host array, copied */
 } pbf_laser;
 pbf_status pbf_set_laser(pbf_ctx *ctx, const pbf_laser *l);
+
+/* Leaves for pbf_mesh_octree / pbf_octree_remesh refined around a window of a
+ * scan path (the octree workload; mesh input, not part of the paper's method):
+ * coarse nx x ny x nz cells over [0,Lx]x[0,Ly]x[0,Lz]; every cell within
+ * `radius` of the beam path between arc lengths s_lo and s_hi (measured along
+ * the tracks in order from the first track's start) reaches max_level.  The
+ * path is sampled at points at most half a finest cell apart; a level-l cell is
+ * split when its box comes closer than R_{l+1} to a sampled point, with
+ * R_max = radius and R_l = R_{l+1} + (diagonal of a level-l cell), which keeps
+ * the tree 2:1 balanced across faces, edges and vertices.  leaves: host array
+ * of 4*capacity int32 (level, ix, iy, iz rows in Morton order of the origins);
+ * *n_leaves receives the count.  With leaves == NULL only the count is
+ * returned; a too small capacity returns PBF_ENOMEM.  ctx (may be NULL) takes
+ * the error message.  Host only. */
+pbf_status pbf_octree_path_leaves(pbf_ctx *ctx, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                                  int max_level, double radius, int n_tracks, const pbf_track *tracks,
+                                  double s_lo, double s_hi, int32_t *leaves, int64_t capacity, int64_t *n_leaves);
 
 /* ---- radiation and evaporation (Section 2, eqs. bc_rad_evap, bc_radiation,
  * bc_evaporation) ---------------------------------------------------------------
@@ -284,6 +344,26 @@ pbf_status pbf_stability_lambda(pbf_ctx *ctx, const double *v0, int iters, doubl
  * free node).  Synchronizes. */
 pbf_status pbf_stability_dt(pbf_ctx *ctx, const double *v0, int iters, double *dt_crit,
                             double *lambda_max, void *stream);
+
+/* Preconditioner of the implicit steps' linear systems (pbf_implicit_step:
+ * CG; pbf_implicit_step_newton: GMRES, on the right).  kind 0: Jacobi (the
+ * default).  kind 1: one geometric multigrid V-cycle (box meshes): levels Q1 on
+ * the same mesh below Q2, then Q1 on meshes coarsened 2x while every cell count
+ * is even and more than 4096 nodes remain; each level rediscretizes the Picard
+ * matrix C(T_n)/dt + K(T^i) (Section 3.2; for Newton its symmetric part) from
+ * the temperatures injected from the finer level, with the consolidated
+ * fraction taken as 1; Chebyshev smoothing of D^-1 A of smoothing_degree
+ * steps before and after the coarse correction (the same polynomial, so the
+ * cycle is symmetric positive definite), eigenvalue bounds from a power
+ * iteration at the first iteration of each step, restriction = transposed
+ * trilinear interpolation, coarsest level by a Chebyshev polynomial of
+ * coarse_degree steps.  Only the iteration changes, not the solution (each
+ * linear solve still stops at the relative residual asked for).  Call after
+ * the mesh, Dirichlet faces and material and before pbf_bind_device (the
+ * coarse levels take their memory from the workspace, which grows).  Errors:
+ * PBF_ESTATE before mesh and material, PBF_EMESH on octrees and growing boxes,
+ * PBF_EINVAL for degrees outside [1, 8] (smoothing) and [1, 64] (coarse). */
+pbf_status pbf_set_implicit_preconditioner(pbf_ctx *ctx, int kind, int smoothing_degree, int coarse_degree);
 
 /* ---- implicit scheme (Section 3.2, eqs. backward_euler_nonlinear, Newton_1, Newton_2)
  * One backward-Euler step from T_n (time t) to T_out (time t + dt), solving

@@ -105,6 +105,8 @@ def lib():
         O = C.c_void_p
         L.or_oct_build.argtypes = [P, C.c_int, C.c_int64, _i64p]
         L.or_oct_build.restype = O
+        L.or_oct_build_top.argtypes = [P, C.c_int, C.c_int64, _i64p, C.c_int64]
+        L.or_oct_build_top.restype = O
         L.or_oct_free.argtypes = [O]
         L.or_oct_free.restype = None
         for nm in ("or_oct_n_dofs", "or_oct_n_hanging", "or_oct_n_qp"):
@@ -125,6 +127,7 @@ def lib():
                                            C.POINTER(C.c_int), _dp]
         L.or_oct_probe.argtypes = [O, _dp, C.c_int, _dp, _dp]
         L.or_oct_transfer.argtypes = [O, _dp, _dp, O, _dp, _dp]
+        L.or_oct_transfer_growing.argtypes = [O, _dp, _dp, O, C.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -337,13 +340,19 @@ class OctOracle:
     """The oracle on an octree mesh: prob is a problem description with coarse
     cells nx, ny, nz, max_level and leaves (n, 4) = (level, ix, iy, iz)."""
 
-    def __init__(self, prob, leaves=None, track_power=None):
+    def __init__(self, prob, leaves=None, track_power=None, top=None):
+        """top (finest cells): the active top of a growing build (leaves cover
+        z < top); None: the box top."""
         self.base = Oracle(prob, track_power=track_power)  # holds the problem struct
         self.L = self.base.L
         lv = np.ascontiguousarray(prob.leaves if leaves is None else leaves, dtype=np.int64)
         self._leaves = lv
-        self.h = self.L.or_oct_build(C.byref(self.base.s), int(prob.max_level), len(lv),
-                                     lv.ctypes.data_as(_i64p))
+        if top is None:
+            self.h = self.L.or_oct_build(C.byref(self.base.s), int(prob.max_level), len(lv),
+                                         lv.ctypes.data_as(_i64p))
+        else:
+            self.h = self.L.or_oct_build_top(C.byref(self.base.s), int(prob.max_level), len(lv),
+                                             lv.ctypes.data_as(_i64p), int(top))
         if not self.h:
             raise RuntimeError("or_oct_build failed")
         self.prob = prob
@@ -404,6 +413,15 @@ class OctOracle:
         if self.L.or_oct_probe(self.h, _ptr(np.ascontiguousarray(T)), len(pts), _ptr(pts), _ptr(vals)):
             raise ValueError("probe outside the mesh")
         return vals
+
+    def transfer_growing(self, T, rc, new, T0):
+        """(T, history) across the adaptation and layer activation of a growing
+        build, onto the octree `new` (an OctOracle with a higher or equal top)."""
+        Tn, rn = np.zeros(new.N), np.zeros(new.NQ)
+        if self.L.or_oct_transfer_growing(self.h, _ptr(np.ascontiguousarray(T)), _ptr(rc), new.h, float(T0),
+                                          _ptr(Tn), _ptr(rn)):
+            raise ValueError("transfer: a new point lies outside the old mesh")
+        return Tn, rn
 
     def transfer(self, T, rc, new):
         """(T, history) on the octree `new` (an OctOracle) from this one."""

@@ -45,6 +45,7 @@ struct or_octree {
     int64_t *cd;
     double *cw;
     double *mass;       /* lumped mass per dof */
+    int64_t top;        /* active top in finest units (the box top unless the part grows) */
 };
 
 static int64_t leaf_span(const or_octree *O, int64_t e) /* leaf size in lattice steps */
@@ -140,6 +141,16 @@ void or_oct_free(or_octree *O)
 
 or_octree *or_oct_build(const or_problem *P, int max_level, int64_t n_leaves, const int64_t *leaves)
 {
+    return or_oct_build_top(P, max_level, n_leaves, leaves, (int64_t)P->nz << max_level);
+}
+
+/* An octree whose leaves cover the box only up to z = top (finest units): the
+ * active part of a growing build (Section 4.1: cells above the current layer
+ * carry no dofs).  The free surface, the source depth and the powder depth are
+ * measured from z = top, and Dirichlet nodes of face z+ lie on z = top. */
+or_octree *or_oct_build_top(const or_problem *P, int max_level, int64_t n_leaves, const int64_t *leaves,
+                            int64_t top)
+{
     or_octree *O = calloc(1, sizeof(or_octree));
     if (!O || or_make_ref(P->degree, &O->R)) { free(O); return NULL; }
     O->P = *P;
@@ -151,6 +162,8 @@ or_octree *or_oct_build(const or_problem *P, int max_level, int64_t n_leaves, co
     O->unit[0] = P->Lx / P->nx / (double)((int64_t)1 << max_level);
     O->unit[1] = P->Ly / P->ny / (double)((int64_t)1 << max_level);
     O->unit[2] = P->Lz / P->nz / (double)((int64_t)1 << max_level);
+    O->top = top;
+    O->P.Lz = (double)top * O->unit[2];  /* the active top */
     int nn = O->R.nn, n1 = O->p + 1;
     /* nodes: all leaf nodes, sorted and unique */
     int64_t *all = malloc(sizeof(int64_t) * 3 * n_leaves * nn);
@@ -253,7 +266,7 @@ void or_oct_dof_coords(const or_octree *O, double *xyz)
 static int oct_is_dirichlet(const or_octree *O, int64_t i)
 {
     const int64_t *x = O->key + 3 * O->dnode[i];
-    int64_t n[3] = {(int64_t)O->P.nx << O->maxl, (int64_t)O->P.ny << O->maxl, (int64_t)O->P.nz << O->maxl};
+    int64_t n[3] = {(int64_t)O->P.nx << O->maxl, (int64_t)O->P.ny << O->maxl, O->top};
     unsigned msk = O->P.dirichlet_mask;
     for (int d = 0; d < 3; ++d) {
         if ((msk & (1u << (2 * d))) && x[d] == 0) return 1;
@@ -307,7 +320,7 @@ static void surface_loss_face(const or_octree *O, int64_t e, const double *Te, d
 {
     const ref_elem *R = &O->R;
     const or_problem *P = &O->P;
-    int64_t top = ((int64_t)P->nz << O->maxl);
+    int64_t top = O->top;
     if (!or_surface_loss_on(P) || O->leaf[4 * e + 3] + ((int64_t)1 << (O->maxl - O->leaf[4 * e])) != top) return;
     double x0[3], h[3];
     leaf_geometry(O, e, x0, h);
@@ -375,7 +388,7 @@ static void oct_cell(const or_octree *O, int64_t e, const double *T, double *rc_
             fv[a] += W * R->N[a][q] * src;
         }
     }
-    int64_t top = ((int64_t)P->nz << O->maxl);
+    int64_t top = O->top;
     if (P->laser_kind == 0 && O->leaf[4 * e + 3] + ((int64_t)1 << (O->maxl - O->leaf[4 * e])) == top) {
         int n1 = R->n1;
         for (int j = 0; j < n1; ++j)
@@ -654,6 +667,73 @@ int or_oct_probe(const or_octree *O, const double *T, int n, const double *pts, 
         int64_t e = oct_locate(O, pts + 3 * s, xi);
         if (e < 0) return -1;
         vals[s] = oct_eval(O, e, xi, T);
+    }
+    return 0;
+}
+
+/* Transfer across the adaptation of a growing build (Section 4.1: refinement,
+ * coarsening and activation of a new layer).  New dofs inside the old active
+ * part take the old finite element field there, dofs above the old top the
+ * initial temperature T0 (parts deposited later start at the initial
+ * temperature).  A new quadrature point above the old top starts as powder
+ * (0 within the powder depth of the new top, 1 below); inside the old part it
+ * takes the value of the nearest quadrature point of the old leaf that contains
+ * it when the new leaf is that leaf or one of its descendants, and the minimum
+ * over all quadrature points of the old leaves inside it when the new leaf is
+ * a coarsened parent (unfused powder in any child stays visible). */
+int or_oct_transfer_growing(const or_octree *Oo, const double *To, const double *rco, const or_octree *On,
+                            double T0, double *Tn, double *rcn)
+{
+    const double ztop_old = Oo->P.Lz;
+    double *xyz = malloc(sizeof(double) * 3 * On->ndofs);
+    or_oct_dof_coords(On, xyz);
+    for (int64_t i = 0; i < On->ndofs; ++i) {
+        double xi[3];
+        if (xyz[3 * i + 2] > ztop_old + 1e-12 * ztop_old) { Tn[i] = T0; continue; }
+        int64_t e = oct_locate(Oo, xyz + 3 * i, xi);
+        if (e < 0) { free(xyz); return -1; }
+        Tn[i] = oct_eval(Oo, e, xi, To);
+    }
+    free(xyz);
+    for (int64_t e = 0; e < On->nl; ++e) {
+        double x0[3], h[3];
+        leaf_geometry(On, e, x0, h);
+        const int ln = (int)On->leaf[4 * e];
+        for (int q = 0; q < On->R.nq; ++q) {
+            double pt[3], xi[3], oxo[3], oh[3];
+            for (int d = 0; d < 3; ++d) pt[d] = x0[d] + On->R.xi[q][d] * h[d];
+            double *out = rcn + e * On->R.nq + q;
+            if (pt[2] > ztop_old) { *out = (On->P.Lz - pt[2] <= On->P.powder_depth) ? 0.0 : 1.0; continue; }
+            int64_t eo = oct_locate(Oo, pt, xi);
+            if (eo < 0) return -1;
+            if (Oo->leaf[4 * eo] > ln) { /* coarsened: minimum over the old leaves inside the new one */
+                double m = 1e300;
+                for (int64_t f = 0; f < Oo->nl; ++f) {
+                    double fx[3], fh[3];
+                    leaf_geometry(Oo, f, fx, fh);
+                    int in = 1;
+                    for (int d = 0; d < 3; ++d)
+                        if (fx[d] < x0[d] - 1e-12 * h[d] || fx[d] + fh[d] > x0[d] + h[d] + 1e-12 * h[d]) in = 0;
+                    if (!in) continue;
+                    for (int qo = 0; qo < Oo->R.nq; ++qo)
+                        if (rco[f * Oo->R.nq + qo] < m) m = rco[f * Oo->R.nq + qo];
+                }
+                *out = m;
+                continue;
+            }
+            leaf_geometry(Oo, eo, oxo, oh);
+            int best = 0;
+            double bd = 1e300;
+            for (int qo = 0; qo < Oo->R.nq; ++qo) {
+                double d2 = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    double dx = oxo[d] + Oo->R.xi[qo][d] * oh[d] - pt[d];
+                    d2 += dx * dx;
+                }
+                if (d2 < bd) { bd = d2; best = qo; }
+            }
+            *out = rco[eo * Oo->R.nq + best];
+        }
     }
     return 0;
 }

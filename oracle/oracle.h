@@ -112,6 +112,8 @@ int or_adjoint_run(const or_problem *P, const double *T0, double t0, double dt, 
  * hist: 0 update (explicit step), 1 peek, 2 lagged. */
 typedef struct or_octree or_octree;
 or_octree *or_oct_build(const or_problem *P, int max_level, int64_t n_leaves, const int64_t *leaves);
+or_octree *or_oct_build_top(const or_problem *P, int max_level, int64_t n_leaves, const int64_t *leaves,
+                            int64_t top);
 void or_oct_free(or_octree *O);
 int64_t or_oct_n_dofs(const or_octree *O);
 int64_t or_oct_n_hanging(const or_octree *O);
@@ -129,5 +131,7 @@ int or_oct_implicit_step(const or_octree *O, const double *Tn, double *rc, doubl
 int or_oct_probe(const or_octree *O, const double *T, int n, const double *pts, double *vals);
 int or_oct_transfer(const or_octree *Oo, const double *To, const double *rco, const or_octree *On,
                     double *Tn, double *rcn);
+int or_oct_transfer_growing(const or_octree *Oo, const double *To, const double *rco, const or_octree *On,
+                            double T0, double *Tn, double *rcn);
 
 #endif

@@ -41,6 +41,7 @@ struct pbf_ctx {
     SurfaceLoss re{};
     // FP32 reference temperature
     double Tref = 0.0;
+    double T_init = 0.0;  // initial temperature (pbf_init_state): activated dofs of a growing octree
     // device binding
     bool bound = false;
     char *ws = nullptr;
@@ -74,6 +75,7 @@ struct pbf_ctx {
         OctMesh mesh;
         std::vector<int32_t> cell, src;  // per new dof: old leaf; per new history point: source
         std::vector<double> xi;          // per new dof: reference coordinates in the old leaf
+        std::vector<int32_t> grp_start, grp_idx;  // coarsened parents: old history points to take the min of
     } pending;
     // last gradient forward sweep (checked by the backward sweep)
     struct {
@@ -89,6 +91,12 @@ struct pbf_ctx {
     } grad;
     Law<double> h_law64{}, h_lin64{}, h_zero64{};
     Law<float> h_law32{};
+    // implicit-step preconditioner: 0 Jacobi, 1 geometric multigrid V-cycle
+    // (boxes: Q1 on the same mesh below Q2, then 2x coarser Q1 meshes)
+    int precond = 0, mg_smooth = 2, mg_coarse = 8;
+    std::vector<pbf_ctx *> mg;     // coarse levels (owned)
+    double *d_mg[3] = {};          // fine-level smoother vectors
+    std::vector<double> mg_lmax;   // lambda_max(D^-1 A) per level (0 = fine)
     // kernel timing: 4 events per timed step (cell kernel start/stop, face kernel
     // start/stop), on every `timing_every`-th explicit step
     std::vector<hipEvent_t> tev;
@@ -948,11 +956,11 @@ size_t oct_tables(pbf_ctx *c, char *base)
     d.n_dofs = (int)m.n_dofs;
     d.n_hist_cells = (int)m.n_hist_cells;
     d.maxl = m.maxl;
-    d.top_iz = m.n0[2] << m.maxl;
+    d.top_iz = (int)m.top;
     d.ux = m.unit[0];
     d.uy = m.unit[1];
     d.uz = m.unit[2];
-    d.Lz = m.L[2];
+    d.Lz = (double)m.top * m.unit[2];
     return off;
 }
 
@@ -987,6 +995,228 @@ pbf_status oct_upload(pbf_ctx *c, hipStream_t s, bool all)
     return PBF_OK;
 }
 
+}  // namespace
+
+// ---- geometric multigrid preconditioner of the implicit systems (boxes) ----
+// Levels: the fine problem (Q2 or Q1), Q1 on the same mesh when the fine
+// degree is 2, then Q1 on meshes coarsened 2x in every direction while all
+// cell counts are even and the coarse lattice keeps more than kMgCoarseNodes
+// nodes.  Every level rediscretizes the Picard matrix C(T_n)/dt + K(T^i) with
+// the temperatures injected from the next finer level (coarse nodes are fine
+// nodes) and the consolidated fraction taken as 1 (the coarse levels carry no
+// powder history: only the preconditioner changes, not the solution).  The
+// V-cycle smooths with Chebyshev polynomials of D^-1 A (the same polynomial
+// before and after the coarse correction, so the cycle is symmetric and
+// positive definite and serves CG), restricts with the transpose of trilinear
+// interpolation, and treats the coarsest level with a higher-degree Chebyshev
+// polynomial.
+namespace {
+constexpr long long kMgCoarseNodes = 4096;
+constexpr double kMgRange = 15.0, kMgCoarseRange = 60.0, kMgSafety = 1.15;
+
+struct MgLevel {
+    pbf_ctx *c;
+    long long N;
+    HaloParams ge, hp;
+    const double *Tn;
+    double *Ti, *diag, *x, *b, *r, *d, *t;
+    const double *coef;
+    bool fine;
+};
+
+pbf_status mg_build_levels(pbf_ctx *c)
+{
+    for (pbf_ctx *l : c->mg) pbf_destroy(l);
+    c->mg.clear();
+    int deg = c->degree, nx = c->nx, ny = c->ny, nz = c->nz;
+    auto nodes = [](int d, int a, int b, int e) { return (long long)(d * a + 1) * (d * b + 1) * (d * e + 1); };
+    for (;;) {
+        int nd = 1, ax = nx, ay = ny, az = nz;
+        if (deg == 1) {
+            if (nx % 2 || ny % 2 || nz % 2) break;
+            ax = nx / 2;
+            ay = ny / 2;
+            az = nz / 2;
+        }
+        if (deg == 1 && nodes(1, ax, ay, az) <= kMgCoarseNodes / 8) break;
+        if (deg == 1 && nodes(1, nx, ny, nz) <= kMgCoarseNodes) break;
+        pbf_ctx *l = nullptr;
+        if (pbf_create(&l) != PBF_OK) return fail(c, PBF_ENOMEM, "multigrid level");
+        c->mg.push_back(l);
+        pbf_status st = pbf_mesh_box(l, nd, ax, ay, az, c->L[0], c->L[1], c->L[2]);
+        if (!st) st = pbf_set_dirichlet(l, c->dmask, c->T_D);
+        if (!st) {
+            pbf_material m{};
+            m.n_bp = c->n_bp;
+            m.T_bp = c->T_bp;
+            m.k_bp = c->k_bp;
+            m.cp_bp = c->cp_bp;
+            m.rho = c->rho;
+            m.T_s = c->T_s;
+            m.T_l = c->T_l;
+            m.latent = c->latent;
+            m.powder_k_factor = c->phi;
+            m.powder_depth = 0.0;  // no history on coarse levels
+            st = pbf_set_material(l, &m);
+        }
+        if (st) return fail(c, st, "multigrid level: %s", l->err.c_str());
+        deg = 1;
+        nx = ax;
+        ny = ay;
+        nz = az;
+    }
+    c->mg_lmax.assign(c->mg.size() + 1, 0.0);
+    return PBF_OK;
+}
+
+// the levels of the current solve; level 0 solves with the fine operator's cache
+std::vector<MgLevel> mg_levels(pbf_ctx *c, const double *T_n, double *Ti, double *diag, const double *fine_coef)
+{
+    std::vector<MgLevel> L;
+    MgLevel f{};
+    f.c = c;
+    f.N = n_dofs(c);
+    f.ge = geometry(c);
+    f.hp = geometry(c, picard_column_height(), kPicardResident);
+    f.Tn = T_n;
+    f.Ti = Ti;
+    f.diag = diag;
+    f.r = c->d_mg[0];
+    f.d = c->d_mg[1];
+    f.t = c->d_mg[2];
+    f.coef = fine_coef;
+    f.fine = true;
+    L.push_back(f);
+    for (pbf_ctx *l : c->mg) {
+        MgLevel v{};
+        v.c = l;
+        v.N = n_dofs(l);
+        v.ge = geometry(l);
+        v.hp = geometry(l, picard_column_height(), kPicardResident);
+        v.Tn = l->d_cg[0];
+        v.Ti = l->d_cg[1];
+        v.diag = l->d_cg[2];
+        v.x = l->d_cg[3];
+        v.b = l->d_cg[4];
+        v.r = l->d_cg[5];
+        v.d = l->d_cg[6];
+        v.t = l->d_cg[7];
+        v.coef = l->d_coef;
+        v.fine = false;
+        L.push_back(v);
+    }
+    return L;
+}
+
+// y = A_l x (Picard matrix of the level, from its coefficient cache)
+pbf_status mg_apply(const MgLevel &v, const double *x, double *y, double dt, hipStream_t s)
+{
+    pbf_ctx *c = v.c;
+    PicardParams pa = picard_params(c, v.ge, v.Tn, v.Ti, x, x, y, nullptr, dt, nullptr);
+    pa.coef = const_cast<double *>(v.coef);
+    pa.ncells = (long long)c->nx * c->ny * c->nz;
+    PBF_HIP(c, launch_picard_capply(c->degree, false, pa, v.ge, s));
+    return PBF_OK;
+}
+
+// coarse-level temperatures, diagonals and coefficient caches for T^i
+pbf_status mg_setup(pbf_ctx *c, std::vector<MgLevel> &L, double dt, hipStream_t s)
+{
+    for (size_t l = 1; l < L.size(); ++l) {
+        MgLevel &v = L[l];
+        const MgLevel &f = L[l - 1];
+        PBF_HIP(c, launch_mg_inject(const_cast<double *>(v.Tn), f.Tn, v.ge, f.ge.NX, f.ge.NY, s));
+        PBF_HIP(c, launch_mg_inject(v.Ti, f.Ti, v.ge, f.ge.NX, f.ge.NY, s));
+        pbf_status st = picard_pass(v.c, 1, v.hp, v.Tn, v.Ti, nullptr, nullptr, v.diag, nullptr, dt, nullptr, s);
+        if (st) return fail(c, st, "multigrid level: %s", v.c->err.c_str());
+        PicardParams pc = picard_params(v.c, v.ge, v.Tn, v.Ti, nullptr, nullptr, nullptr, nullptr, dt, nullptr);
+        pc.coef = const_cast<double *>(v.coef);
+        pc.ncells = (long long)v.c->nx * v.c->ny * v.c->nz;
+        PBF_HIP(c, launch_picard_coef(1, false, pc, s));
+    }
+    return PBF_OK;
+}
+
+// lambda_max(D^-1 A) of every level by power iteration (synchronizes)
+pbf_status mg_eigen(pbf_ctx *c, std::vector<MgLevel> &L, double dt, hipStream_t s)
+{
+    for (size_t l = 0; l < L.size(); ++l) {
+        MgLevel &v = L[l];
+        double *vec = v.d, *w = v.t;
+        PBF_HIP(c, launch_seed(vec, v.N, s));  // fixed pseudo-random start (all frequencies)
+        double lam = 0.0;
+        for (int it = 0; it < 12; ++it) {
+            pbf_status st = mg_apply(v, vec, w, dt, s);
+            if (st) return st;
+            PBF_HIP(c, launch_div(w, w, v.diag, v.N, s));
+            PBF_HIP(c, launch_dot_to(vec, w, c->d_partials, c->d_scal + SC_MG, v.N, s));
+            PBF_HIP(c, launch_dot_to(vec, vec, c->d_partials, c->d_scal + SC_MG + 1, v.N, s));
+            PBF_HIP(c, launch_dot_to(w, w, c->d_partials, c->d_scal + SC_MG + 2, v.N, s));
+            double h[3];
+            PBF_HIP(c, hipMemcpyAsync(h, c->d_scal + SC_MG, sizeof h, hipMemcpyDeviceToHost, s));
+            PBF_HIP(c, hipStreamSynchronize(s));
+            if (!(h[1] > 0) || !(h[2] > 0)) break;
+            lam = h[0] / h[1];
+            PBF_HIP(c, launch_div_scalar(vec, w, std::sqrt(h[2]), v.N, s));
+        }
+        if (!(lam > 0) || !std::isfinite(lam)) return fail(c, PBF_ENONFINITE, "multigrid: no eigenvalue estimate");
+        c->mg_lmax[l] = kMgSafety * lam;
+    }
+    return PBF_OK;
+}
+
+// x <- Chebyshev sweep of `degree` steps on A_l x = b (from x = 0 if zero);
+// eigenvalues of D^-1 A in [lmax / range, lmax]
+pbf_status mg_smooth(pbf_ctx *c, const MgLevel &v, const double *b, double *x, int degree, double lmax,
+                     double range, bool zero, double dt, hipStream_t s)
+{
+    const double l0 = lmax / range, l1 = lmax;
+    const double theta = 0.5 * (l1 + l0), delta = 0.5 * (l1 - l0), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    pbf_status st;
+    // first step: d = D^-1 r / theta
+    if (zero) {
+        PBF_HIP(c, launch_cheb(x, v.d, b, v.diag, 0.0, 1.0 / theta, true, v.N, s));
+    } else {
+        if ((st = mg_apply(v, x, v.t, dt, s))) return st;
+        PBF_HIP(c, launch_sub(v.r, b, v.t, v.N, s));
+        PBF_HIP(c, launch_cheb(x, v.d, v.r, v.diag, 0.0, 1.0 / theta, false, v.N, s));
+    }
+    for (int k = 1; k < degree; ++k) {
+        if ((st = mg_apply(v, x, v.t, dt, s))) return st;
+        PBF_HIP(c, launch_sub(v.r, b, v.t, v.N, s));
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        PBF_HIP(c, launch_cheb(x, v.d, v.r, v.diag, rho_new * rho, 2.0 * rho_new / delta, false, v.N, s));
+        rho = rho_new;
+    }
+    return PBF_OK;
+}
+
+// z = M^-1 r by one V-cycle
+pbf_status mg_vcycle(pbf_ctx *c, std::vector<MgLevel> &L, const double *r, double *z, double dt, hipStream_t s)
+{
+    L[0].b = const_cast<double *>(r);
+    L[0].x = z;
+    const size_t nl = L.size();
+    pbf_status st;
+    for (size_t l = 0; l + 1 < nl; ++l) {
+        MgLevel &v = L[l];
+        if ((st = mg_smooth(c, v, v.b, v.x, c->mg_smooth, c->mg_lmax[l], kMgRange, true, dt, s))) return st;
+        if ((st = mg_apply(v, v.x, v.t, dt, s))) return st;
+        PBF_HIP(c, launch_sub(v.r, v.b, v.t, v.N, s));
+        MgLevel &w = L[l + 1];
+        PBF_HIP(c, launch_mg_restrict(w.b, v.r, w.ge, v.ge.NX, v.ge.NY, v.ge.NZ, s));
+    }
+    MgLevel &cl = L[nl - 1];
+    if ((st = mg_smooth(c, cl, cl.b, cl.x, c->mg_coarse, c->mg_lmax[nl - 1], kMgCoarseRange, true, dt, s)))
+        return st;
+    for (size_t l = nl - 1; l-- > 0;) {
+        MgLevel &v = L[l];
+        PBF_HIP(c, launch_mg_prolong_add(v.x, L[l + 1].x, v.ge, L[l + 1].ge.NX, L[l + 1].ge.NY, s));
+        if ((st = mg_smooth(c, v, v.b, v.x, c->mg_smooth, c->mg_lmax[l], kMgRange, false, dt, s))) return st;
+    }
+    return PBF_OK;
+}
 }  // namespace
 
 // ---- explicit steps without a workspace ----------------------------------
@@ -1072,6 +1302,7 @@ pbf_status pbf_create(pbf_ctx **out)
 void pbf_destroy(pbf_ctx *ctx)
 {
     if (!ctx) return;
+    for (pbf_ctx *l : ctx->mg) pbf_destroy(l);
     for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
     if (ctx->ev_read) (void)hipEventDestroy(ctx->ev_read);
     if (ctx->h_read) (void)hipHostFree(ctx->h_read);
@@ -1094,6 +1325,9 @@ pbf_status pbf_mesh_box(pbf_ctx *c, int degree, int nx, int ny, int nz, double L
                     NZ = (long long)degree * nz + 1;
     if (NX > (1 << 30) || NY > (1 << 30) || NZ > (1 << 30) || NX * NY * NZ > (1LL << 40))
         return fail(c, PBF_EMESH, "mesh too large");
+    // the column kernels address the degree+1 node planes of a cell layer with
+    // 32-bit offsets
+    if (NX * NY * (degree + 1) >= (1LL << 31)) return fail(c, PBF_EMESH, "mesh too large: node planes too big");
     c->has_mesh = true;
     c->octree = false;
     c->oct = OctMesh{};
@@ -1110,8 +1344,8 @@ pbf_status pbf_mesh_box(pbf_ctx *c, int degree, int nx, int ny, int nz, double L
     return PBF_OK;
 }
 
-pbf_status pbf_mesh_octree(pbf_ctx *c, int degree, int nx, int ny, int nz, double Lx, double Ly, double Lz,
-                           int max_level, int64_t n_leaves, const int32_t *leaves)
+static pbf_status mesh_octree(pbf_ctx *c, int degree, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                              int max_level, int64_t top, bool growing, int64_t n_leaves, const int32_t *leaves)
 {
     if (!c) return fail(nullptr, PBF_EINVAL, "pbf_mesh_octree: ctx is NULL");
     if (degree != 1 && degree != 2) return fail(c, PBF_EMESH, "degree %d not supported (1 or 2)", degree);
@@ -1122,7 +1356,9 @@ pbf_status pbf_mesh_octree(pbf_ctx *c, int degree, int nx, int ny, int nz, doubl
     const double L[3] = {Lx, Ly, Lz};
     OctMesh m;
     std::string err;
-    if (!oct_build(m, degree, max_level, n0, L, n_leaves, leaves, err)) return fail(c, PBF_EMESH, "%s", err.c_str());
+    if (!oct_build(m, degree, max_level, n0, L, n_leaves, leaves, err, top))
+        return fail(c, PBF_EMESH, "%s", err.c_str());
+    m.growing = growing;
     c->has_mesh = true;
     c->octree = true;
     c->oct = std::move(m);
@@ -1137,6 +1373,96 @@ pbf_status pbf_mesh_octree(pbf_ctx *c, int degree, int nx, int ny, int nz, doubl
     c->laws_dirty = true;
     c->pending.ready = false;
     compute_history_layers(c);
+    return PBF_OK;
+}
+
+pbf_status pbf_mesh_octree(pbf_ctx *c, int degree, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                           int max_level, int64_t n_leaves, const int32_t *leaves)
+{
+    return mesh_octree(c, degree, nx, ny, nz, Lx, Ly, Lz, max_level, -1, false, n_leaves, leaves);
+}
+
+pbf_status pbf_mesh_octree_growing(pbf_ctx *c, int degree, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                                   int max_level, int64_t top, int64_t n_leaves, const int32_t *leaves)
+{
+    if (c && top < 1) return fail(c, PBF_EINVAL, "the active top must be >= 1 finest cell");
+    return mesh_octree(c, degree, nx, ny, nz, Lx, Ly, Lz, max_level, top, true, n_leaves, leaves);
+}
+
+pbf_status pbf_octree_history_min(pbf_ctx *c, const double *rc, double *rc_min, void *stream)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!c->octree) return fail(c, PBF_ESTATE, "no octree mesh");
+    if (!rc_min) return fail(c, PBF_EINVAL, "rc_min is NULL");
+    const OctMesh &m = c->oct;
+    std::fill(rc_min, rc_min + m.n_cells, 1.0);
+    const int64_t nq = n_hist_qp(c);
+    if (nq == 0) return PBF_OK;
+    if (!rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
+    std::vector<double> h(nq);
+    hipStream_t s = (hipStream_t)stream;
+    PBF_HIP(c, hipMemcpyAsync(h.data(), rc, nq * sizeof(double), hipMemcpyDeviceToHost, s));
+    PBF_HIP(c, hipStreamSynchronize(s));
+    const int64_t npt = (int64_t)(c->degree + 1) * (c->degree + 1) * (c->degree + 1);
+    for (int64_t e = 0; e < m.n_cells; ++e) {
+        const int32_t hc = m.cell_hist[e];
+        if (hc < 0) continue;
+        double v = h[hc];
+        for (int64_t q = 1; q < npt; ++q) v = std::min(v, h[q * m.n_hist_cells + hc]);
+        rc_min[e] = v;
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_octree_layer_leaves(pbf_ctx *c, const double *rc_min, int64_t new_top, int64_t d_haz, double r_coarsen,
+                                   int32_t *leaves, int64_t capacity, int64_t *n_leaves)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (!n_leaves) return fail(c, PBF_EINVAL, "n_leaves is NULL");
+    if (!c->octree || !c->oct.growing) return fail(c, PBF_ESTATE, "no growing octree (pbf_mesh_octree_growing)");
+    if (d_haz < 0 || !std::isfinite(r_coarsen)) return fail(c, PBF_EINVAL, "need d_haz >= 0 and a finite r_coarsen");
+    const OctMesh &m = c->oct;
+    std::vector<double> rmin(m.n_cells, 1.0);
+    if (rc_min) std::copy(rc_min, rc_min + m.n_cells, rmin.begin());
+    std::vector<int32_t> out;
+    std::string err;
+    if (!oct_layer_leaves(m, rmin, new_top, d_haz, r_coarsen, out, err)) return fail(c, PBF_EINVAL, "%s", err.c_str());
+    *n_leaves = (int64_t)(out.size() / 4);
+    if (!leaves) return PBF_OK;
+    if (capacity < *n_leaves)
+        return fail(c, PBF_ENOMEM, "leaf array holds %lld leaves, %lld needed", (long long)capacity, (long long)*n_leaves);
+    std::copy(out.begin(), out.end(), leaves);
+    return PBF_OK;
+}
+
+pbf_status pbf_octree_path_leaves(pbf_ctx *c, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                                  int max_level, double radius, int n_tracks, const pbf_track *tracks,
+                                  double s_lo, double s_hi, int32_t *leaves, int64_t capacity, int64_t *n_leaves)
+{
+    if (!n_leaves) return fail(c, PBF_EINVAL, "n_leaves is NULL");
+    if (n_tracks < 0 || (n_tracks > 0 && !tracks)) return fail(c, PBF_EINVAL, "bad track list");
+    const int n0[3] = {nx, ny, nz};
+    const double L[3] = {Lx, Ly, Lz};
+    std::vector<double> tr(8 * (size_t)n_tracks);
+    for (int k = 0; k < n_tracks; ++k) {
+        for (int d = 0; d < 3; ++d) {
+            tr[8 * k + d] = tracks[k].x0[d];
+            tr[8 * k + 3 + d] = tracks[k].x1[d];
+        }
+        tr[8 * k + 6] = tracks[k].speed;
+        tr[8 * k + 7] = tracks[k].power;
+    }
+    std::vector<int32_t> out;
+    std::string err;
+    if (!oct_path_leaves(n0, L, max_level, radius, tr.data(), n_tracks, s_lo, s_hi, out, err))
+        return fail(c, PBF_EINVAL, "%s", err.c_str());
+    *n_leaves = (int64_t)(out.size() / 4);
+    if (capacity < *n_leaves)
+        return leaves ? fail(c, PBF_ENOMEM, "leaf array holds %lld leaves, %lld needed", (long long)capacity,
+                             (long long)*n_leaves)
+                      : PBF_OK;
+    if (!leaves) return PBF_OK;
+    std::copy(out.begin(), out.end(), leaves);
     return PBF_OK;
 }
 
@@ -1392,6 +1718,15 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     b += align256(3 * kMaxProbes * sizeof(int)) + align256(4 * kMaxProbes * sizeof(double));
     b += align256(picard_coef_count(c) * sizeof(double));  // CG-apply coefficient cache (boxes)
     b += oct_tables(const_cast<pbf_ctx *>(c), nullptr);  // octree tables and element buffer
+    if (c->precond == 1) {  // multigrid: fine smoother vectors and the coarse levels' workspaces
+        b += 3 * align256(N * sizeof(double));
+        for (pbf_ctx *l : c->mg) {
+            size_t lb = 0;
+            pbf_status st = pbf_workspace_bytes(l, &lb);
+            if (st) return fail(const_cast<pbf_ctx *>(c), st, "multigrid level: %s", l->err.c_str());
+            b += align256(lb);
+        }
+    }
     *bytes = b;
     return PBF_OK;
 }
@@ -1441,10 +1776,23 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
     c->d_coef = (double *)p;
     p += align256(picard_coef_count(c) * sizeof(double));
     c->probes_dirty = !c->probe_target.empty();
+    c->bound = false;
     if (c->octree) {
         compute_history_layers(c);  // Dirichlet flags and history leaves for the current setup
-        oct_tables(c, p);
+        p += oct_tables(c, p);
         if ((st = oct_upload(c, (hipStream_t)stream, true))) return st;
+    }
+    if (c->precond == 1) {
+        for (int k = 0; k < 3; ++k) {
+            c->d_mg[k] = (double *)p;
+            p += align256(N * sizeof(double));
+        }
+        for (pbf_ctx *l : c->mg) {
+            size_t lb = 0;
+            if ((st = pbf_workspace_bytes(l, &lb))) return fail(c, st, "multigrid level: %s", l->err.c_str());
+            if ((st = pbf_bind_device(l, p, lb, stream))) return fail(c, st, "multigrid level: %s", l->err.c_str());
+            p += align256(lb);
+        }
     }
     c->ws = (char *)workspace;
     c->ws_bytes = bytes;
@@ -1466,6 +1814,7 @@ pbf_status pbf_init_state(pbf_ctx *c, double T0, double *T, double *rc, void *st
     if (n_hist_qp(c) > 0 && !rc) return fail(c, PBF_EINVAL, "rc is NULL but the mesh has history");
     if (!std::isfinite(T0)) return fail(c, PBF_EINVAL, "T0 must be finite");
     hipStream_t s = (hipStream_t)stream;
+    c->T_init = T0;
     if (c->Tref != T0) {
         c->Tref = T0;
         c->laws_dirty = true;
@@ -1643,6 +1992,26 @@ pbf_status pbf_stability_dt(pbf_ctx *c, const double *v0, int iters, double *dt_
     return PBF_OK;
 }
 
+pbf_status pbf_set_implicit_preconditioner(pbf_ctx *c, int kind, int smoothing_degree, int coarse_degree)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (kind != 0 && kind != 1) return fail(c, PBF_EINVAL, "kind must be 0 (Jacobi) or 1 (multigrid)");
+    if (kind == 1) {
+        if (!c->has_mesh || !c->has_material) return fail(c, PBF_ESTATE, "set the mesh and the material first");
+        if (c->octree || c->growing) return fail(c, PBF_EMESH, "the multigrid preconditioner needs a full box mesh");
+        if (smoothing_degree < 1 || smoothing_degree > 8 || coarse_degree < 1 || coarse_degree > 64)
+            return fail(c, PBF_EINVAL, "smoothing degree in [1, 8], coarse degree in [1, 64]");
+    }
+    c->precond = kind;
+    c->mg_smooth = smoothing_degree;
+    c->mg_coarse = coarse_degree;
+    c->bound = false;  // the workspace size changes
+    if (kind == 1) return mg_build_levels(c);
+    for (pbf_ctx *l : c->mg) pbf_destroy(l);
+    c->mg.clear();
+    return PBF_OK;
+}
+
 pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, double *rc, double t,
                              double dt, double cg_rtol, int cg_max_it, double picard_tol,
                              int picard_max_it, int *cg_iters_total, int *picard_iters,
@@ -1676,6 +2045,9 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
     bool cg_fail = false, converged = false;
     double last_rel = 0.0;
     double hs[8];
+    const bool mg = c->precond == 1 && !c->octree;
+    std::vector<MgLevel> lev;
+    if (mg) lev = mg_levels(c, T_n, Ti, diag, c->d_coef);
     for (it = 0; it < picard_max_it;) {
         // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_RE(T_n) - f_vol, and diag(A(T^i))
         PBF_HIP(c, launch_sub(d, Ti, T_n, N, s));
@@ -1689,6 +2061,13 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
             PBF_HIP(c, launch_picard_coef(c->degree, false, pc, s));
         }
         PBF_HIP(c, launch_cg_start(y, diag, r, z, p, x, c->d_partials, c->d_scal, ge, N, s));
+        if (mg) {  // z = M^-1 r by a V-cycle, p = z, rz = r.z
+            if ((st = mg_setup(c, lev, dt, s))) return st;
+            if (it == 0 && (st = mg_eigen(c, lev, dt, s))) return st;
+            if ((st = mg_vcycle(c, lev, r, z, dt, s))) return st;
+            PBF_HIP(c, hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            PBF_HIP(c, launch_dot_to(r, z, c->d_partials, c->d_scal + CG_RZ0, N, s));
+        }
         PBF_HIP(c, hipMemcpyAsync(hs, c->d_scal + CG_RZ0, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
         PBF_HIP(c, hipStreamSynchronize(s));
         const double bn = std::sqrt(hs[CG_BN2 - CG_RZ0]);
@@ -1714,6 +2093,10 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
             PBF_HIP(c, hipMemcpyAsync(c->h_read, c->d_scal + CG_RR, sizeof(double), hipMemcpyDeviceToHost, s));
             PBF_HIP(c, hipEventRecord(c->ev_read, s));
             const int rz_new = rz_old == CG_RZ0 ? CG_RZ1 : CG_RZ0;
+            if (mg) {  // z = M^-1 r, rz = r.z
+                if ((st = mg_vcycle(c, lev, r, z, dt, s))) return st;
+                PBF_HIP(c, launch_dot_to(r, z, c->d_partials, c->d_scal + rz_new, N, s));
+            }
             PBF_HIP(c, launch_cg_direction(p, z, c->d_scal, rz_old, rz_new, N, s));
             PBF_HIP(c, hipEventSynchronize(c->ev_read));
             rr = c->h_read[0];
@@ -1833,6 +2216,9 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
     int total = 0, it = 0;
     bool lin_fail = false, converged = false;
     double last_rel = 0.0;
+    const bool mg = c->precond == 1;
+    std::vector<MgLevel> lev;
+    if (mg) lev = mg_levels(c, T_n, Ti, diag, nw.coef);  // the symmetric part of the cached Jacobian
     for (it = 0; it < newton_max_it;) {
         // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_RE(T_n) - f_vol; b = -R
         PBF_HIP(c, launch_sub(d, Ti, T_n, N, s));
@@ -1851,7 +2237,12 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
             PBF_HIP(c, launch_picard_capply(c->degree, true, pa, ge, s));
             return PBF_OK;
         };
-        // GMRES(m) from x = 0 on J(T^i) x = b, Jacobi on the right
+        if (mg) {
+            if ((st = mg_setup(c, lev, dt, s))) return st;
+            if (it == 0 && (st = mg_eigen(c, lev, dt, s))) return st;
+        }
+        // GMRES(m) from x = 0 on J(T^i) x = b, Jacobi (or the multigrid V-cycle of
+        // the symmetric part) on the right
         PBF_HIP(c, launch_fill(x, 0.0, N, s));
         PBF_HIP(c, hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         double bn = 0.0, rn = 0.0;
@@ -1865,7 +2256,11 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
             int j;
             for (j = 0; j < m && k < lin_max_it; ++j) {
                 double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N;
-                PBF_HIP(c, launch_div(z, Vj, diag, N, s));
+                if (mg) {
+                    if ((st = mg_vcycle(c, lev, Vj, z, dt, s))) return st;
+                } else {
+                    PBF_HIP(c, launch_div(z, Vj, diag, N, s));
+                }
                 if ((st = japply(z, w))) return st;
                 // classical Gram-Schmidt, twice
                 PBF_HIP(c, launch_mdot(w, V, N, j + 1, nw.partials, nw.h1, N, s));
@@ -1911,8 +2306,19 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
                 for (int l = q + 1; l < j; ++l) sum -= H[(size_t)q * m + l] * yy[l];
                 yy[q] = sum / H[(size_t)q * m + q];
             }
-            PBF_HIP(c, hipMemcpyAsync(nw.y, yy.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-            PBF_HIP(c, launch_gm_update(x, V, N, j, nw.y, diag, N, s));
+            if (mg) {  // x += M^-1 (V y): t = 0 - V (-y), z = M^-1 t
+                std::vector<double> ny(j);
+                for (int q = 0; q < j; ++q) ny[q] = -yy[q];
+                PBF_HIP(c, hipMemcpyAsync(nw.y, ny.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+                PBF_HIP(c, launch_fill(c->d_v, 0.0, N, s));
+                PBF_HIP(c, launch_maxpy(c->d_v, V, N, j, nw.y, N, s));
+                if ((st = mg_vcycle(c, lev, c->d_v, z, dt, s))) return st;
+                PBF_HIP(c, launch_axpy(x, 1.0, z, N, s));
+                PBF_HIP(c, hipStreamSynchronize(s));  // ny is read by the copy
+            } else {
+                PBF_HIP(c, hipMemcpyAsync(nw.y, yy.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+                PBF_HIP(c, launch_gm_update(x, V, N, j, nw.y, diag, N, s));
+            }
             if ((st = japply(x, w))) return st;
             PBF_HIP(c, launch_sub(r, b, w, N, s));
             if ((st = norm2(r, &rn))) return st;
@@ -2245,6 +2651,112 @@ pbf_status pbf_check_finite(pbf_ctx *c, const double *x, int64_t n, int *ok, dou
     return r[0] == 0.0 ? PBF_OK : fail(c, PBF_ENONFINITE, "%.0f non-finite values", r[0]);
 }
 
+static pbf_status prepare_remesh(pbf_ctx *c, int64_t n_leaves, const int32_t *leaves, int64_t new_top, size_t *bytes,
+                                 int64_t *new_n_dofs, int64_t *new_n_hist_qp)
+{
+    c->pending.ready = false;
+    const OctMesh &om = c->oct;
+    OctMesh nm;
+    std::string err;
+    if (!oct_build(nm, c->degree, om.maxl, om.n0, om.L, n_leaves, leaves, err, new_top))
+        return fail(c, PBF_EMESH, "%s", err.c_str());
+    nm.growing = om.growing;
+    oct_finish(nm, c->dmask, c->powder_depth);
+    const int P = c->degree, N1 = P + 1;
+    const bool grow = om.growing;
+    // new dofs: containing old leaf and reference coordinates (growing builds:
+    // dofs above the old top are activated, cell -1)
+    c->pending.cell.resize(nm.n_dofs);
+    c->pending.xi.assign(3 * nm.n_dofs, 0.0);
+    for (int64_t i = 0; i < nm.n_dofs; ++i) {
+        if (grow && nm.dof_key[3 * i + 2] > om.top * P) {
+            c->pending.cell[i] = -1;
+            continue;
+        }
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = double(nm.dof_key[3 * i + d]) / P;
+        const int32_t e = oct_locate(om, x, &c->pending.xi[3 * i]);
+        if (e < 0) return fail(c, PBF_EMESH, "new dof outside the old mesh");
+        c->pending.cell[i] = e;
+    }
+    // new history points.  Scan-following meshes: the nearest old Gauss point of
+    // the containing old leaf if that point lies in the powder layer, else the
+    // initial value.  Growing builds: points above the old top start as powder
+    // (initial value), points of a coarsened parent take the minimum over the
+    // points of its old children, the others the nearest old Gauss point of the
+    // containing old leaf.
+    auto gp = [&](int q) { return P == 1 ? Tables<1>::gp(q) : Tables<2>::gp(q); };
+    const int64_t nq = (int64_t)N1 * N1 * N1;
+    const double ztop_old = (double)om.top * om.unit[2], ztop_new = (double)nm.top * nm.unit[2];
+    c->pending.src.assign(nq * nm.n_hist_cells, -2);
+    c->pending.grp_start.assign(1, 0);
+    c->pending.grp_idx.clear();
+    for (int64_t e = 0; e < nm.n_cells; ++e) {
+        const int32_t hc = nm.cell_hist[e];
+        if (hc < 0) continue;
+        const int ln = nm.leaf[4 * e];
+        const double s = (double)(1LL << (nm.maxl - ln));
+        int32_t group = -1;
+        for (int64_t q = 0; q < nq; ++q) {
+            const int qd[3] = {int(q % N1), int((q / N1) % N1), int(q / (N1 * N1))};
+            double x[3], xi[3];
+            for (int d = 0; d < 3; ++d) x[d] = nm.leaf[4 * e + 1 + d] + gp(qd[d]) * s;
+            const double zn = nm.leaf[4 * e + 3] * nm.unit[2] + gp(qd[2]) * (s * nm.unit[2]);
+            int32_t src;
+            if (grow && x[2] > (double)om.top) {
+                src = (ztop_new - zn <= c->powder_depth) ? -1 : -2;
+            } else {
+                const int32_t eo = oct_locate(om, x, xi);
+                if (eo < 0) return fail(c, PBF_EMESH, "new point outside the old mesh");
+                if (grow && om.leaf[4 * eo] > ln) {  // coarsened parent: the old children's points
+                    if (group < 0) {
+                        const int64_t h = (int64_t)1 << (om.maxl - ln - 1);
+                        for (int k = 0; k < 8; ++k) {
+                            const int32_t f = om.leaf_map.find(
+                                ((uint64_t)(nm.leaf[4 * e + 1] + (k & 1) * h)) |
+                                ((uint64_t)(nm.leaf[4 * e + 2] + ((k >> 1) & 1) * h) << 20) |
+                                ((uint64_t)(nm.leaf[4 * e + 3] + ((k >> 2) & 1) * h) << 40) | ((uint64_t)(ln + 1) << 60));
+                            if (f < 0 || om.cell_hist[f] < 0) return fail(c, PBF_EMESH, "coarsened leaf without its children");
+                            for (int64_t qo = 0; qo < nq; ++qo)
+                                c->pending.grp_idx.push_back((int32_t)(qo * om.n_hist_cells + om.cell_hist[f]));
+                        }
+                        c->pending.grp_start.push_back((int32_t)c->pending.grp_idx.size());
+                        group = (int32_t)c->pending.grp_start.size() - 2;
+                    }
+                    src = -3 - group;
+                } else {
+                    int qo[3];
+                    for (int d = 0; d < 3; ++d) {
+                        qo[d] = 0;
+                        for (int j = 1; j <= P; ++j)
+                            if (std::fabs(xi[d] - gp(j)) < std::fabs(xi[d] - gp(qo[d]))) qo[d] = j;
+                    }
+                    const double so = (double)(1LL << (om.maxl - om.leaf[4 * eo]));
+                    const double zo = om.leaf[4 * eo + 3] * om.unit[2] + gp(qo[2]) * (so * om.unit[2]);
+                    if ((grow || ztop_old - zo <= c->powder_depth) && om.cell_hist[eo] >= 0)
+                        src = (int32_t)((qo[0] + N1 * (qo[1] + N1 * qo[2])) * om.n_hist_cells + om.cell_hist[eo]);
+                    else
+                        src = (ztop_new - zn <= c->powder_depth) ? -1 : -2;
+                }
+            }
+            c->pending.src[q * nm.n_hist_cells + hc] = src;
+        }
+    }
+    std::swap(c->oct, nm);  // size the workspace of the new mesh
+    size_t b = 0;
+    pbf_status st = pbf_workspace_bytes(c, &b);
+    std::swap(c->oct, nm);
+    if (st) return st;
+    b += align256(4 * (size_t)nm.n_dofs) + align256(24 * (size_t)nm.n_dofs) + align256(4 * c->pending.src.size()) +
+         align256(4 * c->pending.grp_start.size()) + align256(4 * c->pending.grp_idx.size());
+    if (new_n_dofs) *new_n_dofs = nm.n_dofs;
+    if (new_n_hist_qp) *new_n_hist_qp = (int64_t)c->pending.src.size();
+    c->pending.mesh = std::move(nm);
+    c->pending.ready = true;
+    *bytes = b;
+    return PBF_OK;
+}
+
 pbf_status pbf_octree_remesh_bytes(pbf_ctx *c, int64_t n_leaves, const int32_t *leaves, size_t *bytes,
                                    int64_t *new_n_dofs, int64_t *new_n_hist_qp)
 {
@@ -2252,69 +2764,18 @@ pbf_status pbf_octree_remesh_bytes(pbf_ctx *c, int64_t n_leaves, const int32_t *
     if (!c->octree) return fail(c, PBF_ESTATE, "no octree mesh");
     pbf_status st = check_bound(c);
     if (st) return st;
-    c->pending.ready = false;
-    OctMesh nm;
-    std::string err;
-    if (!oct_build(nm, c->degree, c->oct.maxl, c->oct.n0, c->oct.L, n_leaves, leaves, err))
-        return fail(c, PBF_EMESH, "%s", err.c_str());
-    oct_finish(nm, c->dmask, c->powder_depth);
-    const OctMesh &om = c->oct;
-    const int P = c->degree, N1 = P + 1;
-    // new dofs: containing old leaf and reference coordinates
-    c->pending.cell.resize(nm.n_dofs);
-    c->pending.xi.resize(3 * nm.n_dofs);
-    for (int64_t i = 0; i < nm.n_dofs; ++i) {
-        double x[3];
-        for (int d = 0; d < 3; ++d) x[d] = double(nm.dof_key[3 * i + d]) / P;
-        const int32_t e = oct_locate(om, x, &c->pending.xi[3 * i]);
-        if (e < 0) return fail(c, PBF_EMESH, "new dof outside the old mesh");
-        c->pending.cell[i] = e;
-    }
-    // new history points: nearest old Gauss point of the containing old leaf if
-    // that point lies in the powder layer, else the initial value
-    auto gp = [&](int q) { return P == 1 ? Tables<1>::gp(q) : Tables<2>::gp(q); };
-    const int64_t nq = (int64_t)N1 * N1 * N1;
-    c->pending.src.assign(nq * nm.n_hist_cells, -2);
-    for (int64_t e = 0; e < nm.n_cells; ++e) {
-        const int32_t hc = nm.cell_hist[e];
-        if (hc < 0) continue;
-        const double s = (double)(1LL << (nm.maxl - nm.leaf[4 * e]));
-        for (int64_t q = 0; q < nq; ++q) {
-            const int qd[3] = {int(q % N1), int((q / N1) % N1), int(q / (N1 * N1))};
-            double x[3], xi[3];
-            for (int d = 0; d < 3; ++d) x[d] = nm.leaf[4 * e + 1 + d] + gp(qd[d]) * s;
-            const int32_t eo = oct_locate(om, x, xi);
-            if (eo < 0) return fail(c, PBF_EMESH, "new point outside the old mesh");
-            int qo[3];
-            for (int d = 0; d < 3; ++d) {
-                qo[d] = 0;
-                for (int j = 1; j <= P; ++j)
-                    if (std::fabs(xi[d] - gp(j)) < std::fabs(xi[d] - gp(qo[d]))) qo[d] = j;
-            }
-            const double so = (double)(1LL << (om.maxl - om.leaf[4 * eo]));
-            const double zo = om.leaf[4 * eo + 3] * om.unit[2] + gp(qo[2]) * (so * om.unit[2]);
-            const double zn = nm.leaf[4 * e + 3] * nm.unit[2] + gp(qd[2]) * (s * nm.unit[2]);
-            int32_t src;
-            if (om.L[2] - zo <= c->powder_depth && om.cell_hist[eo] >= 0)
-                src = (int32_t)((qo[0] + N1 * (qo[1] + N1 * qo[2])) * om.n_hist_cells + om.cell_hist[eo]);
-            else
-                src = (nm.L[2] - zn <= c->powder_depth) ? -1 : -2;
-            c->pending.src[q * nm.n_hist_cells + hc] = src;
-        }
-    }
-    std::swap(c->oct, nm);  // size the workspace of the new mesh
-    size_t b = 0;
-    st = pbf_workspace_bytes(c, &b);
-    std::swap(c->oct, nm);
+    return prepare_remesh(c, n_leaves, leaves, c->oct.top, bytes, new_n_dofs, new_n_hist_qp);
+}
+
+pbf_status pbf_octree_grow_bytes(pbf_ctx *c, int64_t new_top, int64_t n_leaves, const int32_t *leaves, size_t *bytes,
+                                 int64_t *new_n_dofs, int64_t *new_n_hist_qp)
+{
+    if (!c || !leaves || !bytes) return fail(c, PBF_EINVAL, "NULL argument");
+    if (!c->octree || !c->oct.growing) return fail(c, PBF_ESTATE, "no growing octree (pbf_mesh_octree_growing)");
+    pbf_status st = check_bound(c);
     if (st) return st;
-    b += align256(4 * (size_t)nm.n_dofs) + align256(24 * (size_t)nm.n_dofs) +
-         align256(4 * c->pending.src.size());
-    if (new_n_dofs) *new_n_dofs = nm.n_dofs;
-    if (new_n_hist_qp) *new_n_hist_qp = (int64_t)c->pending.src.size();
-    c->pending.mesh = std::move(nm);
-    c->pending.ready = true;
-    *bytes = b;
-    return PBF_OK;
+    if (new_top < c->oct.top) return fail(c, PBF_EINVAL, "the active top cannot move down");
+    return prepare_remesh(c, n_leaves, leaves, new_top, bytes, new_n_dofs, new_n_hist_qp);
 }
 
 pbf_status pbf_octree_remesh(pbf_ctx *c, void *workspace, size_t bytes, const double *T_old, const double *rc_old,
@@ -2336,7 +2797,8 @@ pbf_status pbf_octree_remesh(pbf_ctx *c, void *workspace, size_t bytes, const do
     size_t need = 0;
     st = pbf_workspace_bytes(c, &need);
     const size_t N = (size_t)c->oct.n_dofs;
-    const size_t total = need + align256(4 * N) + align256(24 * N) + align256(4 * c->pending.src.size());
+    const size_t total = need + align256(4 * N) + align256(24 * N) + align256(4 * c->pending.src.size()) +
+                         align256(4 * c->pending.grp_start.size()) + align256(4 * c->pending.grp_idx.size());
     if (!st && bytes < total) st = fail(c, PBF_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, total);
     if (st) {  // keep the old mesh and binding
         c->pending.mesh = std::move(c->oct);
@@ -2354,17 +2816,26 @@ pbf_status pbf_octree_remesh(pbf_ctx *c, void *workspace, size_t bytes, const do
     double *d_xi = (double *)p;
     p += align256(24 * N);
     int32_t *d_src = (int32_t *)p;
+    p += align256(4 * c->pending.src.size());
+    int32_t *d_gs = (int32_t *)p;
+    p += align256(4 * c->pending.grp_start.size());
+    int32_t *d_gi = (int32_t *)p;
     PBF_HIP(c, hipMemcpyAsync(d_cell, c->pending.cell.data(), 4 * N, hipMemcpyHostToDevice, s));
     PBF_HIP(c, hipMemcpyAsync(d_xi, c->pending.xi.data(), 24 * N, hipMemcpyHostToDevice, s));
     if (!c->pending.src.empty())
         PBF_HIP(c, hipMemcpyAsync(d_src, c->pending.src.data(), 4 * c->pending.src.size(), hipMemcpyHostToDevice, s));
-    PBF_HIP(c, launch_oct_transfer(c->degree, old, T_old, d_cell, d_xi, (int64_t)N, T_new,
-                                   old_hq > 0 ? rc_old : nullptr, d_src, (int64_t)c->pending.src.size(),
+    PBF_HIP(c, hipMemcpyAsync(d_gs, c->pending.grp_start.data(), 4 * c->pending.grp_start.size(), hipMemcpyHostToDevice, s));
+    if (!c->pending.grp_idx.empty())
+        PBF_HIP(c, hipMemcpyAsync(d_gi, c->pending.grp_idx.data(), 4 * c->pending.grp_idx.size(), hipMemcpyHostToDevice, s));
+    PBF_HIP(c, launch_oct_transfer(c->degree, old, T_old, d_cell, d_xi, (int64_t)N, T_new, c->T_init,
+                                   old_hq > 0 ? rc_old : nullptr, d_src, (int64_t)c->pending.src.size(), d_gs, d_gi,
                                    rc_new, s));
     PBF_HIP(c, hipStreamSynchronize(s));
     c->pending.cell.clear();
     c->pending.xi.clear();
     c->pending.src.clear();
+    c->pending.grp_start.clear();
+    c->pending.grp_idx.clear();
     return PBF_OK;
 }
 

@@ -365,14 +365,20 @@ __global__ void k_oct_init_history(const OctDev m, double depth, double *rc)
     rc[i] = (m.Lz - z <= depth) ? 0.0 : 1.0;
 }
 
-// remesh: the old finite element field at the new dofs; history copied or reset
+// remesh: the old finite element field at the new dofs (cell < 0: a dof above
+// the old top of a growing build, which starts at T0); history copied, reset,
+// or (coarsened parents of a growing build) the minimum over a group of old points
 template <int P>
 __global__ void k_oct_transfer_T(const OctDev old, const double *T_old, const int32_t *cell, const double *xi,
-                                 long long n, double *T_new)
+                                 long long n, double *T_new, double T0)
 {
     constexpr int N = P + 1, NN = N * N * N;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    if (cell[i] < 0) {
+        T_new[i] = T0;
+        return;
+    }
     double u[NN];
     oct_gather<P>(old, T_old, cell[i], u);
     const double x = xi[3 * i], y = xi[3 * i + 1], z = xi[3 * i + 2];
@@ -384,12 +390,20 @@ __global__ void k_oct_transfer_T(const OctDev old, const double *T_old, const in
     T_new[i] = v;
 }
 
-__global__ void k_oct_transfer_hist(const double *rc_old, const int32_t *src, long long n, double *rc_new)
+__global__ void k_oct_transfer_hist(const double *rc_old, const int32_t *src, long long n, const int32_t *grp_start,
+                                    const int32_t *grp_idx, double *rc_new)
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int s = src[i];
-    rc_new[i] = s >= 0 ? rc_old[s] : (s == -1 ? 0.0 : 1.0);
+    if (s >= -2) {
+        rc_new[i] = s >= 0 ? rc_old[s] : (s == -1 ? 0.0 : 1.0);
+        return;
+    }
+    const int g = -3 - s;
+    double m = rc_old[grp_idx[grp_start[g]]];
+    for (int j = grp_start[g] + 1; j < grp_start[g + 1]; ++j) m = fmin(m, rc_old[grp_idx[j]]);
+    rc_new[i] = m;
 }
 
 inline unsigned nblocks(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -439,20 +453,21 @@ hipError_t launch_oct_init_history(const OctDev &m, int degree, double powder_de
 }
 
 hipError_t launch_oct_transfer(int degree, const OctDev &old, const double *T_old, const int32_t *cell,
-                               const double *xi, int64_t n, double *T_new, const double *rc_old,
-                               const int32_t *src, int64_t n_hist, double *rc_new, hipStream_t s)
+                               const double *xi, int64_t n, double *T_new, double T0, const double *rc_old,
+                               const int32_t *src, int64_t n_hist, const int32_t *grp_start, const int32_t *grp_idx,
+                               double *rc_new, hipStream_t s)
 {
     if (n > 0) {
         if (degree == 1)
             hipLaunchKernelGGL(k_oct_transfer_T<1>, dim3(nblocks(n, 256)), dim3(256), 0, s, old, T_old, cell, xi,
-                               (long long)n, T_new);
+                               (long long)n, T_new, T0);
         else
             hipLaunchKernelGGL(k_oct_transfer_T<2>, dim3(nblocks(n, 256)), dim3(256), 0, s, old, T_old, cell, xi,
-                               (long long)n, T_new);
+                               (long long)n, T_new, T0);
     }
     if (n_hist > 0)
         hipLaunchKernelGGL(k_oct_transfer_hist, dim3(nblocks(n_hist, 256)), dim3(256), 0, s, rc_old, src,
-                           (long long)n_hist, rc_new);
+                           (long long)n_hist, grp_start, grp_idx, rc_new);
     return hipGetLastError();
 }
 

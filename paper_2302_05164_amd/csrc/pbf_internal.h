@@ -38,8 +38,10 @@ struct Tables {
     static constexpr int N = P + 1;
     static constexpr double gp(int i)
     {
-        if (P == 1) return i == 0 ? 0.5 - 0.5 / csqrt(3.0) : 0.5 + 0.5 / csqrt(3.0);
-        return i == 0 ? 0.5 - csqrt(15.0) / 10.0 : (i == 1 ? 0.5 : 0.5 + csqrt(15.0) / 10.0);
+        // constant tables (the square roots are evaluated at compile time only)
+        constexpr double g1[2] = {0.5 - 0.5 / csqrt(3.0), 0.5 + 0.5 / csqrt(3.0)};
+        constexpr double g2[3] = {0.5 - csqrt(15.0) / 10.0, 0.5, 0.5 + csqrt(15.0) / 10.0};
+        return P == 1 ? g1[i] : g2[i];
     }
     static constexpr double gw(int i)
     {
@@ -283,7 +285,7 @@ constexpr int kRedBlocks = 1024;  // blocks of the first reduction stage
 // device scalars of the CG iteration (offsets into the scalar array)
 enum { CG_RZ0 = 8, CG_RZ1 = 9, CG_RR = 10, CG_PAP = 11, CG_BN2 = 12, CG_DMAX = 13 };
 // diagnostics: energy terms (3 values), non-finite count and max |x| (2 values)
-enum { SC_ENERGY = 16, SC_FINITE = 20 };
+enum { SC_ENERGY = 16, SC_FINITE = 20, SC_MG = 24 };
 hipError_t launch_energy(const double *Tp, const double *T, const double *f, const double *fv,
                          const double *C, double *partials, double *scal, const HaloParams &geom,
                          long long n, hipStream_t s);
@@ -301,6 +303,17 @@ hipError_t launch_cg_direction(double *p, const double *z, const double *scal, i
 hipError_t launch_picard_update(double *Ti, const double *x, double *partials, double *scal,
                                 const HaloParams &geom, long long n, hipStream_t s);
 hipError_t launch_sub(double *d, const double *a, const double *b, long long n, hipStream_t s);
+// geometric multigrid on box lattices (NXf = 2 NXc - 1 per direction)
+hipError_t launch_mg_inject(double *c, const double *f, const HaloParams &hc, int NXf, int NYf, hipStream_t s);
+hipError_t launch_mg_restrict(double *c, const double *f, const HaloParams &hc, int NXf, int NYf, int NZf,
+                              hipStream_t s);
+hipError_t launch_mg_prolong_add(double *f, const double *c, const HaloParams &hf, int NXc, int NYc, hipStream_t s);
+hipError_t launch_cheb(double *x, double *d, const double *r, const double *diag, double c1, double c2,
+                       bool from_zero, long long n, hipStream_t s);
+hipError_t launch_axpy(double *y, double a, const double *x, long long n, hipStream_t s);
+hipError_t launch_seed(double *x, long long n, hipStream_t s);
+hipError_t launch_dot_to(const double *a, const double *b, double *partials, double *out, long long n,
+                         hipStream_t s);
 // history of cells [c0, c1) of a growing box (point-major, stride n_hist_cells):
 // 0 (powder) at Gauss levels within depth of the top Lz, else 1
 hipError_t launch_layer_history(int degree, double *rc, long long stride, long long c0, long long c1,
@@ -335,6 +348,65 @@ hipError_t launch_objective(const ProbeSet &ps, const double *T, double *J, doub
 // ---------------------------------------------------------------------------
 // octree meshes with hanging nodes (octree_mesh.cpp on the host, octree.hip)
 // ---------------------------------------------------------------------------
+// Open-addressing hash map from 64-bit keys (never ~0) to int32 values, for
+// the octree's leaf and node lattices (millions of entries).
+struct FlatMap {
+    static constexpr uint64_t kEmpty = ~0ull;
+    std::vector<uint64_t> keys;
+    std::vector<int32_t> vals;
+    size_t n = 0;
+    static uint64_t mix(uint64_t k)
+    {
+        k ^= k >> 33;
+        k *= 0xff51afd7ed558ccdULL;
+        k ^= k >> 33;
+        k *= 0xc4ceb9fe1a85ec53ULL;
+        k ^= k >> 33;
+        return k;
+    }
+    void reserve(size_t cap)
+    {
+        size_t c = 16;
+        while (c < 2 * cap) c <<= 1;
+        if (c <= keys.size()) return;
+        std::vector<uint64_t> ok;
+        std::vector<int32_t> ov;
+        ok.swap(keys);
+        ov.swap(vals);
+        keys.assign(c, kEmpty);
+        vals.assign(c, -1);
+        n = 0;
+        for (size_t i = 0; i < ok.size(); ++i)
+            if (ok[i] != kEmpty) insert(ok[i], ov[i]);
+    }
+    // (value stored under k, whether it was inserted now)
+    std::pair<int32_t, bool> insert(uint64_t k, int32_t v)
+    {
+        if (2 * (n + 1) > keys.size()) reserve(keys.size() + 16);
+        const size_t mask = keys.size() - 1;
+        size_t i = mix(k) & mask;
+        while (keys[i] != kEmpty) {
+            if (keys[i] == k) return {vals[i], false};
+            i = (i + 1) & mask;
+        }
+        keys[i] = k;
+        vals[i] = v;
+        ++n;
+        return {v, true};
+    }
+    int32_t find(uint64_t k) const  // -1 if absent
+    {
+        if (keys.empty()) return -1;
+        const size_t mask = keys.size() - 1;
+        size_t i = mix(k) & mask;
+        while (keys[i] != kEmpty) {
+            if (keys[i] == k) return vals[i];
+            i = (i + 1) & mask;
+        }
+        return -1;
+    }
+};
+
 struct OctMesh {
     int P = 0, maxl = 0, n0[3] = {0, 0, 0};
     double L[3] = {0, 0, 0}, unit[3] = {0, 0, 0};  // unit: finest cell size
@@ -349,11 +421,19 @@ struct OctMesh {
     std::vector<unsigned char> dflag;               // Dirichlet flags
     std::vector<int32_t> cell_hist;                 // history cell of each leaf or -1
     std::vector<double> hist_z;                     // (z origin, z size) per history cell
-    std::unordered_map<uint64_t, int32_t> leaf_map;
+    FlatMap leaf_map;
+    // active top in finest units (the box top, or the current layer of a growing
+    // build: leaves cover z < top); growing builds keep history in every leaf
+    int64_t top = 0;
+    bool growing = false;
 };
 bool oct_build(OctMesh &m, int P, int maxl, const int n0[3], const double L[3], int64_t n_leaves,
-               const int32_t *leaves, std::string &err);
+               const int32_t *leaves, std::string &err, int64_t top = -1);
+bool oct_layer_leaves(const OctMesh &m, const std::vector<double> &rc_min, int64_t new_top, int64_t d_haz,
+                      double r_coarsen, std::vector<int32_t> &out, std::string &err);
 void oct_finish(OctMesh &m, unsigned dmask, double powder_depth);
+bool oct_path_leaves(const int n0[3], const double L[3], int maxl, double radius, const double *tracks,
+                     int n_tracks, double s_lo, double s_hi, std::vector<int32_t> &out, std::string &err);
 int32_t oct_locate(const OctMesh &m, const double x_finest[3], double xi[3]);
 
 // device view of an octree mesh
@@ -395,8 +475,9 @@ hipError_t launch_oct_init_history(const OctDev &m, int degree, double powder_de
 // remesh transfer: T_new[i] = old field at (cell[i], xi[3i..]); rc_new[i] =
 // src[i] >= 0 ? rc_old[src[i]] : (src[i] == -1 ? 0 : 1)
 hipError_t launch_oct_transfer(int degree, const OctDev &old, const double *T_old, const int32_t *cell,
-                               const double *xi, int64_t n, double *T_new, const double *rc_old,
-                               const int32_t *src, int64_t n_hist, double *rc_new, hipStream_t s);
+                               const double *xi, int64_t n, double *T_new, double T0, const double *rc_old,
+                               const int32_t *src, int64_t n_hist, const int32_t *grp_start, const int32_t *grp_idx,
+                               double *rc_new, hipStream_t s);
 
 // binomial checkpoint schedule (revolve.cpp, host only)
 bool revolve_schedule(int l, int c, std::vector<pbf_revolve_action> &acts, long long *advances);

@@ -352,6 +352,109 @@ __global__ void k_layer_history(double *rc, long long stride, long long c0, long
     rc[(long long)q * stride + c] = (Lz - z <= depth) ? 0.0 : 1.0;
 }
 
+// ---- geometric multigrid on box lattices --------------------------------------
+// A fine lattice of NXf = 2 NXc - 1 nodes per direction over the same box as
+// the coarse lattice of NXc (the Q2 and Q1 node lattices of one mesh, or the Q1
+// lattices of a mesh and its 2x coarsening).  Prolongation: trilinear
+// interpolation (a fine node at an even index is a coarse node, at an odd
+// index the average of its two coarse neighbours); restriction: its transpose.
+
+// fine index i -> coarse indices and weights (1 or 2 of them)
+__device__ __forceinline__ int mg_parents(int i, int &c0, int &c1)
+{
+    c0 = i >> 1;
+    c1 = (i + 1) >> 1;
+    return (i & 1) ? 2 : 1;
+}
+
+__global__ void k_mg_inject(double *c, const double *f, const HaloParams hc, int NXf, int NYf, long long n)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int I = int(g % hc.NX), J = int((g / hc.NX) % hc.NY), K = int(g / ((long long)hc.NX * hc.NY));
+    c[g] = f[2LL * I + (long long)NXf * (2LL * J + (long long)NYf * 2LL * K)];
+}
+
+// c = P^T f, zero on the coarse Dirichlet rows
+__global__ void k_mg_restrict(double *c, const double *f, const HaloParams hc, int NXf, int NYf, int NZf,
+                              long long n)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    if (node_dirichlet(g, hc)) {
+        c[g] = 0.0;
+        return;
+    }
+    const int I = int(g % hc.NX), J = int((g / hc.NX) % hc.NY), K = int(g / ((long long)hc.NX * hc.NY));
+    double s = 0.0;
+    for (int dk = -1; dk <= 1; ++dk) {
+        const int k = 2 * K + dk;
+        if (k < 0 || k >= NZf) continue;
+        const double wk = dk == 0 ? 1.0 : 0.5;
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int j = 2 * J + dj;
+            if (j < 0 || j >= NYf) continue;
+            const double wj = dj == 0 ? 1.0 : 0.5;
+            double row = 0.0;
+            for (int di = -1; di <= 1; ++di) {
+                const int i = 2 * I + di;
+                if (i < 0 || i >= NXf) continue;
+                row += (di == 0 ? 1.0 : 0.5) * f[i + (long long)NXf * (j + (long long)NYf * k)];
+            }
+            s += wk * wj * row;
+        }
+    }
+    c[g] = s;
+}
+
+// f += P c on the free fine rows
+__global__ void k_mg_prolong_add(double *f, const double *c, const HaloParams hf, int NXc, int NYc, long long n)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n || node_dirichlet(g, hf)) return;
+    const int i = int(g % hf.NX), j = int((g / hf.NX) % hf.NY), k = int(g / ((long long)hf.NX * hf.NY));
+    int i0, i1, j0, j1, k0, k1;
+    const int ni = mg_parents(i, i0, i1), nj = mg_parents(j, j0, j1), nk = mg_parents(k, k0, k1);
+    const double wi = ni == 2 ? 0.5 : 1.0, wj = nj == 2 ? 0.5 : 1.0, wk = nk == 2 ? 0.5 : 1.0;
+    double s = 0.0;
+    for (int b = 0; b < nk; ++b)
+        for (int a = 0; a < nj; ++a)
+            for (int e = 0; e < ni; ++e)
+                s += c[(e ? i1 : i0) + (long long)NXc * ((a ? j1 : j0) + (long long)NYc * (b ? k1 : k0))];
+    f[g] += wi * wj * wk * s;
+}
+
+// Chebyshev step of the smoother: d = c1 d + c2 r / diag, x = x + d (first step
+// of a sweep from x = 0: d = c2 r / diag, x = d)
+__global__ void k_cheb(double *x, double *d, const double *r, const double *diag, double c1, double c2, int from_zero,
+                       long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double z = r[i] / diag[i];
+    const double dn = c1 == 0.0 ? c2 * z : c1 * d[i] + c2 * z;
+    d[i] = dn;
+    x[i] = from_zero ? dn : x[i] + dn;
+}
+
+// a fixed pseudo-random vector in [-1, 1) (start of the eigenvalue estimates)
+__global__ void k_seed(double *x, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ULL + 0x632BE59BD9B4E019ULL;
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ULL;
+    h ^= h >> 29;
+    x[i] = double(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void k_axpy(double *y, double a, const double *x, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
 inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -546,6 +649,57 @@ hipError_t launch_finite(const double *x, double *partials, double *scal, long l
                        scal + SC_FINITE);
     hipLaunchKernelGGL(k_finish<true>, dim3(1), dim3(kRedThreads), 0, s, partials + 1, kRedBlocks, 2, 1,
                        scal + SC_FINITE + 1);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_mg_inject(double *c, const double *f, const HaloParams &hc, int NXf, int NYf, hipStream_t s)
+{
+    const long long n = (long long)hc.NX * hc.NY * hc.NZ;
+    hipLaunchKernelGGL(k_mg_inject, dim3(blocks_for(n, 256)), dim3(256), 0, s, c, f, hc, NXf, NYf, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict(double *c, const double *f, const HaloParams &hc, int NXf, int NYf, int NZf,
+                              hipStream_t s)
+{
+    const long long n = (long long)hc.NX * hc.NY * hc.NZ;
+    hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(n, 256)), dim3(256), 0, s, c, f, hc, NXf, NYf, NZf, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_prolong_add(double *f, const double *c, const HaloParams &hf, int NXc, int NYc, hipStream_t s)
+{
+    const long long n = (long long)hf.NX * hf.NY * hf.NZ;
+    hipLaunchKernelGGL(k_mg_prolong_add, dim3(blocks_for(n, 256)), dim3(256), 0, s, f, c, hf, NXc, NYc, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cheb(double *x, double *d, const double *r, const double *diag, double c1, double c2,
+                       bool from_zero, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cheb, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, d, r, diag, c1, c2,
+                       from_zero ? 1 : 0, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double *y, double a, const double *x, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, y, a, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(double *x, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_seed, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_to(const double *a, const double *b, double *partials, double *out, long long n,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, partials, n);
+    hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 1, 1, out);
     return hipGetLastError();
 }
 

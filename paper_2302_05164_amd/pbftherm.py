@@ -88,6 +88,7 @@ SIGNATURES = {
     "pbf_stability_lambda": [_vp, _vp, C.c_int, _dp, _vp],
     "pbf_stability_dt": [_vp, _vp, C.c_int, _dp, _dp, _vp],
     "pbf_laplace_apply": [_vp, _vp, _vp, _vp],
+    "pbf_set_implicit_preconditioner": [_vp, C.c_int, C.c_int, C.c_int],
     "pbf_implicit_step": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int,
                           C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _vp],
     "pbf_newton_work_bytes": [_vp, C.c_int, C.POINTER(C.c_size_t)],
@@ -109,6 +110,16 @@ SIGNATURES = {
     "pbf_mesh_octree": [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                         C.c_int, C.c_int64, C.POINTER(C.c_int32)],
     "pbf_octree_info": [_vp, _i64p, _i64p, C.POINTER(C.c_int)],
+    "pbf_mesh_octree_growing": [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                C.c_int, C.c_int64, C.c_int64, C.POINTER(C.c_int32)],
+    "pbf_octree_history_min": [_vp, _vp, _dp, _vp],
+    "pbf_octree_layer_leaves": [_vp, _dp, C.c_int64, C.c_int64, C.c_double, C.POINTER(C.c_int32), C.c_int64,
+                                _i64p],
+    "pbf_octree_grow_bytes": [_vp, C.c_int64, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_size_t), _i64p,
+                              _i64p],
+    "pbf_octree_path_leaves": [_vp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
+                               C.c_double, C.c_int, C.POINTER(_Track), C.c_double, C.c_double,
+                               C.POINTER(C.c_int32), C.c_int64, _i64p],
     "pbf_octree_remesh_bytes": [_vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_size_t), _i64p, _i64p],
     "pbf_octree_remesh": [_vp, _vp, C.c_size_t, _vp, _vp, _vp, _vp, _vp],
     "pbf_dof_coords": [_vp, _dp],
@@ -154,6 +165,36 @@ def _aligned(nbytes, device):
     return buf, base + (-base) % 256
 
 
+def _track_array(tracks):
+    tr = np.asarray(tracks, dtype=np.float64).reshape(-1, 8)
+    arr = (_Track * max(1, len(tr)))()
+    for i, row in enumerate(tr):
+        arr[i].x0[:] = row[0:3]
+        arr[i].x1[:] = row[3:6]
+        arr[i].speed = row[6]
+        arr[i].power = row[7]
+    return arr, len(tr)
+
+
+def octree_path_leaves(nx, ny, nz, L, max_level, radius, tracks, s_lo, s_hi):
+    """pbf_octree_path_leaves (host only): leaves (n, 4) int32 of the octree over
+    nx x ny x nz coarse cells refined to max_level within `radius` of the scan
+    path between arc lengths s_lo and s_hi, in Morton order."""
+    lib = load_library()
+    arr, nt = _track_array(tracks)
+    n = C.c_int64(0)
+    args = (None, int(nx), int(ny), int(nz), float(L[0]), float(L[1]), float(L[2]), int(max_level),
+            float(radius), nt, arr, float(s_lo), float(s_hi))
+    st = lib.pbf_octree_path_leaves(*args, None, 0, C.byref(n))
+    if st != 0:
+        raise PbfError(st, lib.pbf_last_error(None).decode())
+    out = np.empty((n.value, 4), dtype=np.int32)
+    st = lib.pbf_octree_path_leaves(*args, out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n))
+    if st != 0:
+        raise PbfError(st, lib.pbf_last_error(None).decode())
+    return out
+
+
 def revolve_schedule(n_steps, n_snaps, with_actions=True):
     """Binomial checkpoint schedule (host only): (list of (kind, step, slot),
     number of forward steps)."""
@@ -182,9 +223,10 @@ class Simulation:
     set_dirichlet, set_material, set_laser, bind(); then init_state() and the
     stepping calls.  State tensors (T, rc) belong to the caller."""
 
-    def __init__(self, degree, nx, ny, nz, L, device="cuda:0", max_level=None, leaves=None):
+    def __init__(self, degree, nx, ny, nz, L, device="cuda:0", max_level=None, leaves=None, top=None):
         """Box mesh of nx*ny*nz cells, or (leaves given) an octree over those coarse
-        cells with leaves (n, 4) = (level, ix, iy, iz)."""
+        cells with leaves (n, 4) = (level, ix, iy, iz); with `top` (finest cells)
+        a growing octree whose active part is z < top."""
         self.lib = load_library()
         self.device = torch.device(device)
         self.ctx = _vp()
@@ -193,8 +235,13 @@ class Simulation:
             self._check(self.lib.pbf_mesh_box(self.ctx, degree, nx, ny, nz, *map(float, L)))
         else:
             lv = np.ascontiguousarray(leaves, dtype=np.int32).reshape(-1, 4)
-            self._check(self.lib.pbf_mesh_octree(self.ctx, degree, nx, ny, nz, *map(float, L), int(max_level),
-                                                 len(lv), lv.ctypes.data_as(C.POINTER(C.c_int32))))
+            if top is None:
+                self._check(self.lib.pbf_mesh_octree(self.ctx, degree, nx, ny, nz, *map(float, L), int(max_level),
+                                                     len(lv), lv.ctypes.data_as(C.POINTER(C.c_int32))))
+            else:
+                self._check(self.lib.pbf_mesh_octree_growing(self.ctx, degree, nx, ny, nz, *map(float, L),
+                                                             int(max_level), int(top), len(lv),
+                                                             lv.ctypes.data_as(C.POINTER(C.c_int32))))
         self.octree = leaves is not None
         self.workspace = None
         self.n_tracks = 0
@@ -232,17 +279,10 @@ class Simulation:
         self._check(self.lib.pbf_set_material(self.ctx, C.byref(m)))
 
     def set_laser(self, kind, radius, absorptivity, h_powder, t_start, tracks):
-        tr = np.asarray(tracks, dtype=np.float64).reshape(-1, 8)
-        arr = (_Track * max(1, len(tr)))()
-        for i, row in enumerate(tr):
-            arr[i].x0[:] = row[0:3]
-            arr[i].x1[:] = row[3:6]
-            arr[i].speed = row[6]
-            arr[i].power = row[7]
-        l = _Laser(int(kind), float(radius), float(absorptivity), float(h_powder), float(t_start),
-                   len(tr), arr)
+        arr, nt = _track_array(tracks)
+        l = _Laser(int(kind), float(radius), float(absorptivity), float(h_powder), float(t_start), nt, arr)
         self._check(self.lib.pbf_set_laser(self.ctx, C.byref(l)))
-        self.n_tracks = len(tr)
+        self.n_tracks = nt
 
     def set_surface_loss(self, emissivity=0.0, T_inf=293.0, evap_on=False, T_v=3000.0, C_P=54.0e3,
                          C_T=5.0e4, C_M=1.0e-3, h_v=6.0e6, T_h0=663.0, dT_max=1000.0):
@@ -374,6 +414,13 @@ class Simulation:
             self._check(st)
         return T_out, dict(status=st, lin_iters=it.value, newton_iters=nit.value, rel_res=res.value)
 
+    def set_preconditioner(self, kind, smoothing_degree=2, coarse_degree=8):
+        """pbf_set_implicit_preconditioner: 'jacobi' or 'multigrid'; rebinds the
+        workspace (the multigrid levels take memory from it)."""
+        k = {"jacobi": 0, "multigrid": 1}[kind]
+        self._check(self.lib.pbf_set_implicit_preconditioner(self.ctx, k, int(smoothing_degree), int(coarse_degree)))
+        self.bind()
+
     def implicit_step(self, T_n, rc, t, dt, cg_rtol=1e-10, cg_max_it=10000, picard_tol=1e-8,
                       picard_max_it=30, T_out=None, check=True):
         i = self.info()
@@ -416,6 +463,44 @@ class Simulation:
                                                _ptr(rc) if old_info["n_hist_qp"] else None, _ptr(T_new),
                                                _ptr(rc_new), self._stream()))
         self.workspace = buf  # the old workspace is released here
+        return T_new, rc_new
+
+    def history_min(self, rc):
+        """pbf_octree_history_min: per-leaf minima of the device history (host)."""
+        out = np.ones(self.octree_info()["n_leaves"])
+        self._check(self.lib.pbf_octree_history_min(self.ctx, _ptr(rc) if self.info()["n_hist_qp"] else None,
+                                                    out.ctypes.data_as(_dp), self._stream()))
+        return out
+
+    def layer_leaves(self, rc_min, new_top, d_haz=4, r_coarsen=0.9):
+        """pbf_octree_layer_leaves (host): leaves (n, 4) after activating the layer
+        up to new_top (finest cells) on a growing octree; rc_min per leaf or None."""
+        n = C.c_int64(0)
+        rm = None if rc_min is None else np.ascontiguousarray(rc_min, dtype=np.float64)
+        args = (self.ctx, None if rm is None else rm.ctypes.data_as(_dp), int(new_top), int(d_haz), float(r_coarsen))
+        self._check(self.lib.pbf_octree_layer_leaves(*args, None, 0, C.byref(n)))
+        out = np.empty((n.value, 4), dtype=np.int32)
+        self._check(self.lib.pbf_octree_layer_leaves(*args, out.ctypes.data_as(C.POINTER(C.c_int32)), n.value,
+                                                     C.byref(n)))
+        return out
+
+    def grow(self, leaves, new_top, T, rc):
+        """Move a growing octree to new leaves with the active top new_top;
+        returns the transferred (T, rc) (activated dofs at the initial
+        temperature, new points as powder)."""
+        lv = np.ascontiguousarray(leaves, dtype=np.int32).reshape(-1, 4)
+        nb, nd, nh = C.c_size_t(), C.c_int64(), C.c_int64()
+        self._check(self.lib.pbf_octree_grow_bytes(self.ctx, int(new_top), len(lv),
+                                                   lv.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nb),
+                                                   C.byref(nd), C.byref(nh)))
+        buf, addr = _aligned(nb.value, self.device)
+        old_info = self.info()
+        T_new = torch.empty(nd.value, dtype=torch.float64, device=self.device)
+        rc_new = torch.empty(max(1, nh.value), dtype=torch.float64, device=self.device)
+        self._check(self.lib.pbf_octree_remesh(self.ctx, C.c_void_p(addr), nb.value, _ptr(T),
+                                               _ptr(rc) if old_info["n_hist_qp"] else None, _ptr(T_new),
+                                               _ptr(rc_new), self._stream()))
+        self.workspace = buf
         return T_new, rc_new
 
     # -- diagnostics ----------------------------------------------------------------
@@ -518,7 +603,7 @@ class Simulation:
         return a.value, b.value, n.value
 
 
-def from_problem(prob, device="cuda:0", leaves=None, active_layers=None, bind=True):
+def from_problem(prob, device="cuda:0", leaves=None, active_layers=None, bind=True, top=None):
     """Simulation set up from a problem description object with the attributes
     of pbf_workloads.Problem (argument marshalling only); an octree mesh when the
     problem (or the `leaves` argument) holds leaves; a growing box with the bottom
@@ -526,7 +611,7 @@ def from_problem(prob, device="cuda:0", leaves=None, active_layers=None, bind=Tr
     bind is False."""
     lv = leaves if leaves is not None else getattr(prob, "leaves", None)
     s = Simulation(prob.degree, prob.nx, prob.ny, prob.nz, prob.L, device=device,
-                   max_level=getattr(prob, "max_level", 0), leaves=lv)
+                   max_level=getattr(prob, "max_level", 0), leaves=lv, top=top)
     s.set_dirichlet(prob.dirichlet_mask, prob.T_D)
     s.set_material(prob.T_bp, prob.k_bp, prob.cp_bp, prob.rho, prob.T_s, prob.T_l, prob.latent,
                    prob.powder_k_factor, prob.powder_depth)

@@ -63,6 +63,8 @@ class Problem:
     max_level: int = 0
     refine_radius: float = 0.0
     refine_ahead: float = 0.0   # path length refined ahead of the beam
+    refine_trail: float = 0.0   # path length refined behind the beam (window schedules)
+    scan_start: float = 0.0     # arc length of the beam when a window schedule starts
     remesh_every: int = 0
     leaves: np.ndarray = None
     implicit_steps: int = 0
@@ -392,15 +394,40 @@ def with_leaves(p: Problem, s_hi: float, s_lo: float = 0.0) -> Problem:
 
 
 def cfg3() -> Problem:
-    """Q2 octree over a 10x10x5 mm part: coarse 20x20x10 cells refined to level 6
-    (7.8 um) within 200 um of the scanned path and 50 um ahead of the beam,
-    cfg2's law, a 10-track zigzag of 1 mm tracks at the centre of the top face;
+    """Q2 octree over a 10x10x5 mm part: coarse 20x20x10 cells (0.5 mm) refined to
+    level 6 (7.8 um) within 200 um of the window [s - 8 mm, s + 100 um] of the
+    scan path around the beam's arc length s, cfg2's law, a 10-track zigzag of
+    1 mm tracks at the centre of the top face.  The schedule starts with the
+    beam at the start of the tenth track (s = 9 mm, about 5.2M dofs) and runs
     2000 explicit steps with a remesh every 100, then 50 backward-Euler steps of
-    1 ms with the laser off."""
+    1 ms with the laser off.  The leaves are built at run time by the library
+    (the window at this size takes a minute in octree_leaves)."""
     p = _base_nonlinear("cfg3_q2_octree", 2302, 20, 20, 10, (10e-3, 10e-3, 5e-3), 2000)
-    p = p.replace(max_level=6, refine_radius=200e-6, refine_ahead=50e-6, remesh_every=100,
-                  implicit_steps=50, implicit_dt=1e-3)
-    return with_leaves(p, p.refine_ahead)
+    return p.replace(max_level=6, refine_radius=200e-6, refine_ahead=100e-6, refine_trail=8.0e-3,
+                     scan_start=9.0e-3, remesh_every=100, implicit_steps=50, implicit_dt=1e-3)
+
+
+def cfg3_reduced(max_level=2, trail=0.3e-3, start=0.45e-3) -> Problem:
+    """cfg3's schedule on a 1x0.75x0.5 mm part (coarse 4x3x2 cells of 0.25 mm)
+    refined to `max_level` within 60 um of a short path window, a zigzag of
+    0.4 mm tracks: sizes the octree oracle runs in seconds."""
+    p = _base_nonlinear("cfg3_reduced", 2302, 4, 3, 2, (1.0e-3, 0.75e-3, 0.5e-3), 40,
+                        track_length=0.4e-3, n_tracks=4, hatch=60e-6)
+    return p.replace(max_level=max_level, refine_radius=60e-6, refine_ahead=40e-6, refine_trail=trail,
+                     scan_start=start, remesh_every=10, implicit_steps=2, implicit_dt=2e-4)
+
+
+def growing_octree_build(max_level=2, n_layers=6) -> Problem:
+    """A growing build on an octree (Section 4.1): coarse cells of
+    2^max_level powder layers (h_powder = 40 um, eq. coarse_fine_relation) over
+    a 4x3 coarse-cell chamber three coarse cells tall; the part starts as one
+    coarse layer of substrate whose top 40 um are the first powder layer, and
+    every further layer is activated on top; one track per layer (a zigzag of
+    0.4 mm tracks), cfg2's law."""
+    hc = 40e-6 * (1 << max_level)
+    p = _base_nonlinear("growing_octree", 2306, 4, 3, 3, (4 * hc, 3 * hc, 3 * hc), 60,
+                        track_length=0.4e-3, n_tracks=n_layers, hatch=60e-6)
+    return p.replace(max_level=max_level, remesh_every=0)
 
 
 def small_octree(degree=2, max_level=2, seed=2302, ahead=60e-6, radius=40e-6) -> Problem:
