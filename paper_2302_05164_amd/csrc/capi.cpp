@@ -95,8 +95,13 @@ struct pbf_ctx {
     // (boxes: Q1 on the same mesh below Q2, then 2x coarser Q1 meshes)
     int precond = 0, mg_smooth = 2, mg_coarse = 8;
     std::vector<pbf_ctx *> mg;     // coarse levels (owned)
-    double *d_mg[3] = {};          // fine-level smoother vectors
+    double *d_mg[4] = {};          // fine-level smoother vectors and the V-cycle's input
     std::vector<double> mg_lmax;   // lambda_max(D^-1 A) per level (0 = fine)
+    // the V-cycle of the current step as a HIP graph (its kernels and their
+    // arguments are fixed within a step), captured on a library stream
+    hipStream_t mg_cap = nullptr;
+    hipGraphExec_t mg_exec = nullptr;
+    double *mg_exec_out = nullptr;
     // kernel timing: 4 events per timed step (cell kernel start/stop, face kernel
     // start/stop), on every `timing_every`-th explicit step
     std::vector<hipEvent_t> tev;
@@ -1137,6 +1142,14 @@ pbf_status mg_setup(pbf_ctx *c, std::vector<MgLevel> &L, double dt, hipStream_t 
     return PBF_OK;
 }
 
+// forget the captured V-cycle (new eigenvalue bounds, step or buffers)
+void mg_graph_reset(pbf_ctx *c)
+{
+    if (c->mg_exec) (void)hipGraphExecDestroy(c->mg_exec);
+    c->mg_exec = nullptr;
+    c->mg_exec_out = nullptr;
+}
+
 // lambda_max(D^-1 A) of every level by power iteration (synchronizes)
 pbf_status mg_eigen(pbf_ctx *c, std::vector<MgLevel> &L, double dt, hipStream_t s)
 {
@@ -1162,6 +1175,7 @@ pbf_status mg_eigen(pbf_ctx *c, std::vector<MgLevel> &L, double dt, hipStream_t 
         if (!(lam > 0) || !std::isfinite(lam)) return fail(c, PBF_ENONFINITE, "multigrid: no eigenvalue estimate");
         c->mg_lmax[l] = kMgSafety * lam;
     }
+    mg_graph_reset(c);
     return PBF_OK;
 }
 
@@ -1179,16 +1193,46 @@ pbf_status mg_smooth(pbf_ctx *c, const MgLevel &v, const double *b, double *x, i
         PBF_HIP(c, launch_cheb(x, v.d, b, v.diag, 0.0, 1.0 / theta, true, v.N, s));
     } else {
         if ((st = mg_apply(v, x, v.t, dt, s))) return st;
-        PBF_HIP(c, launch_sub(v.r, b, v.t, v.N, s));
-        PBF_HIP(c, launch_cheb(x, v.d, v.r, v.diag, 0.0, 1.0 / theta, false, v.N, s));
+        PBF_HIP(c, launch_cheb_res(x, v.d, b, v.t, v.diag, 0.0, 1.0 / theta, v.N, s));
     }
     for (int k = 1; k < degree; ++k) {
         if ((st = mg_apply(v, x, v.t, dt, s))) return st;
-        PBF_HIP(c, launch_sub(v.r, b, v.t, v.N, s));
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        PBF_HIP(c, launch_cheb(x, v.d, v.r, v.diag, rho_new * rho, 2.0 * rho_new / delta, false, v.N, s));
+        PBF_HIP(c, launch_cheb_res(x, v.d, b, v.t, v.diag, rho_new * rho, 2.0 * rho_new / delta, v.N, s));
         rho = rho_new;
     }
+    return PBF_OK;
+}
+
+pbf_status mg_vcycle(pbf_ctx *c, std::vector<MgLevel> &L, const double *r, double *z, double dt, hipStream_t s);
+
+// z = M^-1 r: the input is copied to a fixed buffer and the V-cycle, captured
+// once per step as a graph (one launch instead of ~100), replayed on s
+pbf_status mg_precond(pbf_ctx *c, std::vector<MgLevel> &L, const double *r, double *z, double dt, hipStream_t s)
+{
+    const long long N = L[0].N;
+    PBF_HIP(c, hipMemcpyAsync(c->d_mg[3], r, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (!c->mg_exec || c->mg_exec_out != z) {
+        mg_graph_reset(c);
+        if (!c->mg_cap) PBF_HIP(c, hipStreamCreateWithFlags(&c->mg_cap, hipStreamNonBlocking));
+        PBF_HIP(c, hipStreamBeginCapture(c->mg_cap, hipStreamCaptureModeThreadLocal));
+        pbf_status st = mg_vcycle(c, L, c->d_mg[3], z, dt, c->mg_cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->mg_cap, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, PBF_EDEVICE, "V-cycle capture: %s", hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&c->mg_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            c->mg_exec = nullptr;
+            return fail(c, PBF_EDEVICE, "V-cycle graph: %s", hipGetErrorString(ei));
+        }
+        c->mg_exec_out = z;
+    }
+    PBF_HIP(c, hipGraphLaunch(c->mg_exec, s));
     return PBF_OK;
 }
 
@@ -1203,9 +1247,8 @@ pbf_status mg_vcycle(pbf_ctx *c, std::vector<MgLevel> &L, const double *r, doubl
         MgLevel &v = L[l];
         if ((st = mg_smooth(c, v, v.b, v.x, c->mg_smooth, c->mg_lmax[l], kMgRange, true, dt, s))) return st;
         if ((st = mg_apply(v, v.x, v.t, dt, s))) return st;
-        PBF_HIP(c, launch_sub(v.r, v.b, v.t, v.N, s));
         MgLevel &w = L[l + 1];
-        PBF_HIP(c, launch_mg_restrict(w.b, v.r, w.ge, v.ge.NX, v.ge.NY, v.ge.NZ, s));
+        PBF_HIP(c, launch_mg_restrict_res(w.b, v.b, v.t, w.ge, v.ge.NX, v.ge.NY, v.ge.NZ, s));
     }
     MgLevel &cl = L[nl - 1];
     if ((st = mg_smooth(c, cl, cl.b, cl.x, c->mg_coarse, c->mg_lmax[nl - 1], kMgCoarseRange, true, dt, s)))
@@ -1303,6 +1346,8 @@ void pbf_destroy(pbf_ctx *ctx)
 {
     if (!ctx) return;
     for (pbf_ctx *l : ctx->mg) pbf_destroy(l);
+    if (ctx->mg_exec) (void)hipGraphExecDestroy(ctx->mg_exec);
+    if (ctx->mg_cap) (void)hipStreamDestroy(ctx->mg_cap);
     for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
     if (ctx->ev_read) (void)hipEventDestroy(ctx->ev_read);
     if (ctx->h_read) (void)hipHostFree(ctx->h_read);
@@ -1719,7 +1764,7 @@ pbf_status pbf_workspace_bytes(const pbf_ctx *c, size_t *bytes)
     b += align256(picard_coef_count(c) * sizeof(double));  // CG-apply coefficient cache (boxes)
     b += oct_tables(const_cast<pbf_ctx *>(c), nullptr);  // octree tables and element buffer
     if (c->precond == 1) {  // multigrid: fine smoother vectors and the coarse levels' workspaces
-        b += 3 * align256(N * sizeof(double));
+        b += 4 * align256(N * sizeof(double));
         for (pbf_ctx *l : c->mg) {
             size_t lb = 0;
             pbf_status st = pbf_workspace_bytes(l, &lb);
@@ -1783,7 +1828,7 @@ pbf_status pbf_bind_device(pbf_ctx *c, void *workspace, size_t bytes, void *stre
         if ((st = oct_upload(c, (hipStream_t)stream, true))) return st;
     }
     if (c->precond == 1) {
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             c->d_mg[k] = (double *)p;
             p += align256(N * sizeof(double));
         }
@@ -2064,7 +2109,7 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
         if (mg) {  // z = M^-1 r by a V-cycle, p = z, rz = r.z
             if ((st = mg_setup(c, lev, dt, s))) return st;
             if (it == 0 && (st = mg_eigen(c, lev, dt, s))) return st;
-            if ((st = mg_vcycle(c, lev, r, z, dt, s))) return st;
+            if ((st = mg_precond(c, lev, r, z, dt, s))) return st;
             PBF_HIP(c, hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
             PBF_HIP(c, launch_dot_to(r, z, c->d_partials, c->d_scal + CG_RZ0, N, s));
         }
@@ -2094,7 +2139,7 @@ pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, doubl
             PBF_HIP(c, hipEventRecord(c->ev_read, s));
             const int rz_new = rz_old == CG_RZ0 ? CG_RZ1 : CG_RZ0;
             if (mg) {  // z = M^-1 r, rz = r.z
-                if ((st = mg_vcycle(c, lev, r, z, dt, s))) return st;
+                if ((st = mg_precond(c, lev, r, z, dt, s))) return st;
                 PBF_HIP(c, launch_dot_to(r, z, c->d_partials, c->d_scal + rz_new, N, s));
             }
             PBF_HIP(c, launch_cg_direction(p, z, c->d_scal, rz_old, rz_new, N, s));
@@ -2257,7 +2302,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
             for (j = 0; j < m && k < lin_max_it; ++j) {
                 double *Vj = V + (size_t)j * N, *Vn = V + (size_t)(j + 1) * N;
                 if (mg) {
-                    if ((st = mg_vcycle(c, lev, Vj, z, dt, s))) return st;
+                    if ((st = mg_precond(c, lev, Vj, z, dt, s))) return st;
                 } else {
                     PBF_HIP(c, launch_div(z, Vj, diag, N, s));
                 }
@@ -2312,7 +2357,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
                 PBF_HIP(c, hipMemcpyAsync(nw.y, ny.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
                 PBF_HIP(c, launch_fill(c->d_v, 0.0, N, s));
                 PBF_HIP(c, launch_maxpy(c->d_v, V, N, j, nw.y, N, s));
-                if ((st = mg_vcycle(c, lev, c->d_v, z, dt, s))) return st;
+                if ((st = mg_precond(c, lev, c->d_v, z, dt, s))) return st;
                 PBF_HIP(c, launch_axpy(x, 1.0, z, N, s));
                 PBF_HIP(c, hipStreamSynchronize(s));  // ny is read by the copy
             } else {

@@ -311,6 +311,10 @@ hipError_t launch_mg_prolong_add(double *f, const double *c, const HaloParams &h
 hipError_t launch_cheb(double *x, double *d, const double *r, const double *diag, double c1, double c2,
                        bool from_zero, long long n, hipStream_t s);
 hipError_t launch_axpy(double *y, double a, const double *x, long long n, hipStream_t s);
+hipError_t launch_cheb_res(double *x, double *d, const double *b, const double *t, const double *diag, double c1,
+                           double c2, long long n, hipStream_t s);
+hipError_t launch_mg_restrict_res(double *c, const double *b, const double *t, const HaloParams &hc, int NXf, int NYf,
+                                  int NZf, hipStream_t s);
 hipError_t launch_seed(double *x, long long n, hipStream_t s);
 hipError_t launch_dot_to(const double *a, const double *b, double *partials, double *out, long long n,
                          hipStream_t s);

@@ -449,6 +449,51 @@ __global__ void k_seed(double *x, long long n)
     x[i] = double(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+// Chebyshev step after an apply t = A x: d = c1 d + c2 (b - t) / diag, x += d
+__global__ void k_cheb_res(double *x, double *d, const double *b, const double *t, const double *diag, double c1,
+                           double c2, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double z = (b[i] - t[i]) / diag[i];
+    const double dn = c1 == 0.0 ? c2 * z : c1 * d[i] + c2 * z;
+    d[i] = dn;
+    x[i] += dn;
+}
+
+// c = P^T (b - t), zero on the coarse Dirichlet rows
+__global__ void k_mg_restrict_res(double *c, const double *b, const double *t, const HaloParams hc, int NXf, int NYf,
+                                  int NZf, long long n)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    if (node_dirichlet(g, hc)) {
+        c[g] = 0.0;
+        return;
+    }
+    const int I = int(g % hc.NX), J = int((g / hc.NX) % hc.NY), K = int(g / ((long long)hc.NX * hc.NY));
+    double s = 0.0;
+    for (int dk = -1; dk <= 1; ++dk) {
+        const int k = 2 * K + dk;
+        if (k < 0 || k >= NZf) continue;
+        const double wk = dk == 0 ? 1.0 : 0.5;
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int j = 2 * J + dj;
+            if (j < 0 || j >= NYf) continue;
+            const double wj = dj == 0 ? 1.0 : 0.5;
+            double row = 0.0;
+            for (int di = -1; di <= 1; ++di) {
+                const int i = 2 * I + di;
+                if (i < 0 || i >= NXf) continue;
+                const long long f = i + (long long)NXf * (j + (long long)NYf * k);
+                row += (di == 0 ? 1.0 : 0.5) * (b[f] - t[f]);
+            }
+            s += wk * wj * row;
+        }
+    }
+    c[g] = s;
+}
+
 __global__ void k_axpy(double *y, double a, const double *x, long long n)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -680,6 +725,21 @@ hipError_t launch_cheb(double *x, double *d, const double *r, const double *diag
 {
     hipLaunchKernelGGL(k_cheb, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, d, r, diag, c1, c2,
                        from_zero ? 1 : 0, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cheb_res(double *x, double *d, const double *b, const double *t, const double *diag, double c1,
+                           double c2, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cheb_res, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, d, b, t, diag, c1, c2, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict_res(double *c, const double *b, const double *t, const HaloParams &hc, int NXf, int NYf,
+                                  int NZf, hipStream_t s)
+{
+    const long long n = (long long)hc.NX * hc.NY * hc.NZ;
+    hipLaunchKernelGGL(k_mg_restrict_res, dim3(blocks_for(n, 256)), dim3(256), 0, s, c, b, t, hc, NXf, NYf, NZf, n);
     return hipGetLastError();
 }
 

@@ -248,9 +248,12 @@ class Simulation:
         self.n_probes = 0
 
     def __del__(self):
-        if getattr(self, "ctx", None) and self.ctx.value:
-            self.lib.pbf_destroy(self.ctx)
-            self.ctx = _vp()
+        try:
+            if getattr(self, "ctx", None) and self.ctx.value:
+                self.lib.pbf_destroy(self.ctx)
+                self.ctx = _vp()
+        except TypeError:  # interpreter shutdown: ctypes already torn down
+            pass
 
     def _check(self, st, use_ctx=True):
         if st != 0:
