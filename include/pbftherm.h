@@ -364,6 +364,14 @@ pbf_status pbf_stability_dt(pbf_ctx *ctx, const double *v0, int iters, double *d
  * PBF_ESTATE before mesh and material, PBF_EMESH on octrees and growing boxes,
  * PBF_EINVAL for degrees outside [1, 8] (smoothing) and [1, 64] (coarse). */
 pbf_status pbf_set_implicit_preconditioner(pbf_ctx *ctx, int kind, int smoothing_degree, int coarse_degree);
+/* Forcing terms of pbf_implicit_step_newton's linear solves.  kind 0 (the
+ * default): every Newton system is solved to the relative residual lin_rtol.
+ * kind 1: inexact Newton with the Eisenstat-Walker forcing term (choice 2):
+ * eta_0 = 0.1, eta_k = 0.9 (|R(T^k)| / |R(T^k-1)|)^2, safeguarded by 0.9
+ * eta_{k-1}^2 when that exceeds 0.1, at most 0.1 and at least lin_rtol; early
+ * systems are solved loosely, the last ones to lin_rtol.  The Newton stopping
+ * rule (max |dT| <= newton_tol) is unchanged. */
+pbf_status pbf_set_newton_forcing(pbf_ctx *ctx, int kind);
 
 /* ---- implicit scheme (Section 3.2, eqs. backward_euler_nonlinear, Newton_1, Newton_2)
  * One backward-Euler step from T_n (time t) to T_out (time t + dt), solving

@@ -94,6 +94,7 @@ struct pbf_ctx {
     // implicit-step preconditioner: 0 Jacobi, 1 geometric multigrid V-cycle
     // (boxes: Q1 on the same mesh below Q2, then 2x coarser Q1 meshes)
     int precond = 0, mg_smooth = 2, mg_coarse = 8;
+    int newton_forcing = 0;        // 0: every Newton system to lin_rtol; 1: Eisenstat-Walker forcing
     std::vector<pbf_ctx *> mg;     // coarse levels (owned)
     double *d_mg[4] = {};          // fine-level smoother vectors and the V-cycle's input
     std::vector<double> mg_lmax;   // lambda_max(D^-1 A) per level (0 = fine)
@@ -2057,6 +2058,14 @@ pbf_status pbf_set_implicit_preconditioner(pbf_ctx *c, int kind, int smoothing_d
     return PBF_OK;
 }
 
+pbf_status pbf_set_newton_forcing(pbf_ctx *c, int kind)
+{
+    if (!c) return fail(nullptr, PBF_EINVAL, "ctx is NULL");
+    if (kind != 0 && kind != 1) return fail(c, PBF_EINVAL, "kind must be 0 (fixed) or 1 (Eisenstat-Walker)");
+    c->newton_forcing = kind;
+    return PBF_OK;
+}
+
 pbf_status pbf_implicit_step(pbf_ctx *c, const double *T_n, double *T_out, double *rc, double t,
                              double dt, double cg_rtol, int cg_max_it, double picard_tol,
                              int picard_max_it, int *cg_iters_total, int *picard_iters,
@@ -2264,6 +2273,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
     const bool mg = c->precond == 1;
     std::vector<MgLevel> lev;
     if (mg) lev = mg_levels(c, T_n, Ti, diag, nw.coef);  // the symmetric part of the cached Jacobian
+    double bn_prev = 0.0, eta_prev = 0.1;
     for (it = 0; it < newton_max_it;) {
         // residual R(T^i) = C(T_n)(T^i - T_n)/dt + K(T^i) T^i - f_RE(T_n) - f_vol; b = -R
         PBF_HIP(c, launch_sub(d, Ti, T_n, N, s));
@@ -2293,8 +2303,25 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
         double bn = 0.0, rn = 0.0;
         if ((st = norm2(b, &bn))) return st;
         rn = bn;
+        // forcing term of this Newton system: lin_rtol, or (Eisenstat-Walker, choice 2)
+        // eta = 0.9 (|R_k| / |R_k-1|)^2 safeguarded by 0.9 eta_k-1^2 when that exceeds
+        // 0.1, capped at 0.1 and floored at lin_rtol
+        double eta = lin_rtol;
+        if (c->newton_forcing == 1) {
+            if (it == 0) eta = 0.1;
+            else {
+                const double ratio = bn_prev > 0 ? bn / bn_prev : 1.0;
+                eta = 0.9 * ratio * ratio;
+                const double guard = 0.9 * eta_prev * eta_prev;
+                if (guard > 0.1) eta = std::max(eta, guard);
+                eta = std::min(eta, 0.1);
+            }
+            eta = std::max(eta, lin_rtol);
+        }
+        bn_prev = bn;
+        eta_prev = eta;
         int k = 0;
-        while (bn > 0 && rn > lin_rtol * bn && k < lin_max_it) {
+        while (bn > 0 && rn > eta * bn && k < lin_max_it) {
             PBF_HIP(c, launch_div_scalar(V, r, rn, N, s));
             std::fill(g.begin(), g.end(), 0.0);
             g[0] = rn;
@@ -2341,7 +2368,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
                 g[j + 1] = -sn[j] * g[j];
                 g[j] = cs[j] * g[j];
                 for (int q = 0; q <= j; ++q) H[(size_t)q * m + j] = hc[q];
-                if (std::fabs(g[j + 1]) <= lin_rtol * bn || hn == 0.0) {
+                if (std::fabs(g[j + 1]) <= eta * bn || hn == 0.0) {
                     ++j;
                     break;
                 }
@@ -2370,7 +2397,7 @@ pbf_status pbf_implicit_step_newton(pbf_ctx *c, const double *T_n, double *T_out
         }
         total += k;
         last_rel = bn > 0 ? rn / bn : 0.0;
-        if (bn > 0 && rn > lin_rtol * bn) lin_fail = true;
+        if (bn > 0 && rn > eta * bn) lin_fail = true;
         PBF_HIP(c, launch_picard_update(Ti, x, c->d_partials, c->d_scal, ge, N, s));
         double dmax = 0.0;
         PBF_HIP(c, hipMemcpyAsync(&dmax, c->d_scal + CG_DMAX, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -89,6 +89,7 @@ SIGNATURES = {
     "pbf_stability_dt": [_vp, _vp, C.c_int, _dp, _dp, _vp],
     "pbf_laplace_apply": [_vp, _vp, _vp, _vp],
     "pbf_set_implicit_preconditioner": [_vp, C.c_int, C.c_int, C.c_int],
+    "pbf_set_newton_forcing": [_vp, C.c_int],
     "pbf_implicit_step": [_vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int,
                           C.c_double, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _vp],
     "pbf_newton_work_bytes": [_vp, C.c_int, C.POINTER(C.c_size_t)],
@@ -423,6 +424,10 @@ class Simulation:
         k = {"jacobi": 0, "multigrid": 1}[kind]
         self._check(self.lib.pbf_set_implicit_preconditioner(self.ctx, k, int(smoothing_degree), int(coarse_degree)))
         self.bind()
+
+    def set_newton_forcing(self, kind):
+        """pbf_set_newton_forcing: 'fixed' or 'eisenstat-walker'."""
+        self._check(self.lib.pbf_set_newton_forcing(self.ctx, {"fixed": 0, "eisenstat-walker": 1}[kind]))
 
     def implicit_step(self, T_n, rc, t, dt, cg_rtol=1e-10, cg_max_it=10000, picard_tol=1e-8,
                       picard_max_it=30, T_out=None, check=True):

@@ -50,6 +50,10 @@ def test_host_validation_errors():
         assert L.pbf_stability_dt(ctx, None, 10, None, None, None) == -1  # no output
         assert L.pbf_laplace_apply(ctx, None, None, None) == -7
         assert L.pbf_set_dirichlet(ctx, 64, 293.0) == -1
+        assert L.pbf_set_newton_forcing(ctx, 7) == -1
+        assert b"Eisenstat" in L.pbf_last_error(ctx)
+        assert L.pbf_set_newton_forcing(ctx, 1) == 0 and L.pbf_set_newton_forcing(ctx, 0) == 0
+        assert L.pbf_set_newton_forcing(None, 0) == -1
         # unsorted breakpoints
         import numpy as np
         T = np.array([300.0, 200.0])

@@ -22,9 +22,10 @@ def _hot(prob, steps=60):
     return T, rc, steps * dt_ex
 
 
-def _gpu(prob, T, rc, t, dt, newton=False, kind="multigrid", **kw):
+def _gpu(prob, T, rc, t, dt, newton=False, kind="multigrid", forcing="fixed", **kw):
     sim = sim_for(prob)
     sim.set_preconditioner(kind)
+    sim.set_newton_forcing(forcing)
     info = sim.info()
     hist = full_to_history(prob, rc, info["n_hist_layers"])
     rd = torch.tensor(hist if hist.size else np.zeros(1), device="cuda")
@@ -77,6 +78,27 @@ def test_multigrid_newton_gmres_vs_oracle(degree, dims):
     assert mx <= 1e-10 and l2 <= 1e-10
     assert abs(gi["newton_iters"] - oi["newton_iters"]) <= 1
     assert gi["lin_iters"] * 2 <= gj["lin_iters"]
+
+
+@pytest.mark.parametrize("degree,dims", [(2, (16, 16, 8)), (2, (20, 18, 10))])
+def test_eisenstat_walker_newton_same_root(degree, dims):
+    """Inexact Newton (loose early linear solves, Eisenstat-Walker forcing) converges
+    to the same root as the oracle's Newton with every system solved to lin_rtol,
+    in fewer Krylov iterations than the fixed forcing."""
+    need_gpu()
+    nx, ny, nz = dims
+    prob = W.small_nonlinear(nx=nx, ny=ny, nz=nz, steps=0, track_length=0.5 * nx * 31.25e-6).replace(degree=degree)
+    T, rc, t = _hot(prob)
+    cool = prob.replace(laser_kind=W.LASER_OFF)
+    kw = dict(lin_rtol=1e-12, restart=30, lin_max_it=20000, newton_tol=1e-9, newton_max_it=40)
+    To, oi = oracle.Oracle(cool).implicit_step_newton(T, rc.copy(), t, 2e-4, **kw)
+    assert oi["status"] == 0
+    Tg, gi, _ = _gpu(cool, T, rc, t, 2e-4, newton=True, forcing="eisenstat-walker", **kw)
+    Tf, gf, _ = _gpu(cool, T, rc, t, 2e-4, newton=True, **kw)
+    mx, l2 = rel_errors(Tg, To)
+    print(f"Q{degree} {dims} newton EW: {gi} fixed {gf} oracle {oi} max rel {mx:.2e} rel-L2 {l2:.2e}")
+    assert mx <= 1e-10 and l2 <= 1e-10
+    assert gi["lin_iters"] < gf["lin_iters"]
 
 
 def test_multigrid_refused_where_unsupported():
