@@ -292,7 +292,8 @@ def implicit_timing(sim, T, rc, t, dt=1e-4):
     solved by Picard iterations with CG and by Newton's method with restarted
     GMRES(30) (relative residual 1e-10 per linear system, 1e-8 K on the
     update), each with the Jacobi preconditioner and with the geometric
-    multigrid V-cycle; wall time on the library's stream, iteration counts."""
+    multigrid V-cycle, and Newton with multigrid and Eisenstat-Walker forcing
+    (inexact Newton); wall time on the library's stream, iteration counts."""
     import torch
 
     def timed(fn):
@@ -320,13 +321,23 @@ def implicit_timing(sim, T, rc, t, dt=1e-4):
         res[f"newton_gmres_{kind}"] = {"ms": ms, "outer": inw["newton_iters"], "krylov": inw["lin_iters"],
                                        "ms_per_krylov": ms / max(1, inw["lin_iters"]), "work_bytes": work["bytes"]}
         roots[kind] = (Tp, Tn)
+        if kind == "multigrid":
+            sim.set_newton_forcing("eisenstat-walker")
+            r3 = rc.clone()
+            ms, (Te, ie) = timed(lambda: sim.implicit_step_newton(T, r3, t, dt, lin_rtol=1e-10, restart=30,
+                                                                   newton_tol=1e-8, newton_max_it=60, work=work))
+            sim.set_newton_forcing("fixed")
+            res["newton_gmres_multigrid_ew"] = {"ms": ms, "outer": ie["newton_iters"], "krylov": ie["lin_iters"],
+                                                "ms_per_krylov": ms / max(1, ie["lin_iters"])}
+            roots["ew"] = Te
         del work
     sim.set_preconditioner("jacobi")
     res["max_abs_diff_K"] = {
         "picard_vs_newton": float((roots["jacobi"][0] - roots["jacobi"][1]).abs().max().item()),
         "multigrid_vs_jacobi_picard": float((roots["multigrid"][0] - roots["jacobi"][0]).abs().max().item()),
-        "multigrid_vs_jacobi_newton": float((roots["multigrid"][1] - roots["jacobi"][1]).abs().max().item())}
-    j, m = res["picard_cg_jacobi"], res["newton_gmres_multigrid"]
+        "multigrid_vs_jacobi_newton": float((roots["multigrid"][1] - roots["jacobi"][1]).abs().max().item()),
+        "multigrid_ew_vs_jacobi_newton": float((roots["ew"] - roots["jacobi"][1]).abs().max().item())}
+    j, m = res["picard_cg_jacobi"], res["newton_gmres_multigrid_ew"]
     res["best_over_jacobi_picard"] = {"krylov": j["krylov"] / max(1, m["krylov"]), "time": j["ms"] / m["ms"]}
     return res
 

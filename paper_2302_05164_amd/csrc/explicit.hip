@@ -538,7 +538,7 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
         const double C = node_capacity(L, T, gi, gj, gk, P, NX, NY, NZ, q.hx, q.hy, q.hz);
         if constexpr (MODE == 0) {
             const bool dir = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ);
-            const double inc = q.dt * f / C;
+            const double inc = (q.dt * f) * rcp_nr(C);
             const bool later = (li == 0 && fx) || (lj == 0 && fy) || (az == 0 && first && gk > 0);
             const double val = dir ? ((face && later) ? 0.0 : q.T_D) : ((face && later) ? inc : T + inc);
             if (face) slots[t] = val;
