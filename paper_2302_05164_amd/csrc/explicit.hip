@@ -282,37 +282,37 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
     }
 }
 
-// Lane mapping of node-plane loads: the P*kTX + 1 nodes of a row are loaded by
-// P*kTX consecutive lanes (one coalesced row segment each) plus one lane for
-// the row's last node; the rows of `np` consecutive planes (BY rows each) are
-// dealt out kTPB / (P*kTX) rows per pass.  Element e of a lane is row
-// (tid / W) + RPP*e at column tid % W for e < NPASS, and the last node of row
-// tid for e == NPASS.  Offsets are 32-bit, relative to the planes' first node
-// (i0, j0, k); the caller checks that a column's planes fit in 32 bits.
+// Lane mapping of node-plane loads and their LDS stores.  Regular elements:
+// element e of a lane is plane e / P^2, row tid / W + RPP * (e % P^2) (RPP =
+// kTPB / W rows per pass; the P^2 passes of a plane cover its rows 0 .. P*kTY-1
+// exactly) at column tid % W, so that plane and row offset are compile-time
+// constants per element and the lane's own part is fixed.  Extra elements: the
+// last row (row P*kTY, columns 0 .. W-1) and the last column (column W, rows
+// 0 .. P*kTY) of every plane, dealt out over the lanes.  Offsets are 32-bit,
+// relative to the planes' first node (i0, j0, k); the caller checks that a
+// column's planes fit in 32 bits.
 template <int P, int kTY, int NP>
 struct PlaneRows {
     static constexpr int W = P * kTX, BX = W + 1, BY = P * kTY + 1, kTPB = kTX * kTY;
-    static constexpr int RPP = kTPB / W, NROWS = NP * BY, NPASS = (NROWS + RPP - 1) / RPP;
-    static constexpr int NE = NPASS + 1;  // elements per lane
-    // row and column of element e of lane tid (row < 0: no element)
-    __device__ static __forceinline__ void at(int tid, int e, int &row, int &li)
+    static constexpr int RPP = kTPB / W, PPP = P * P;
+    static constexpr int NREG = NP * PPP;
+    static constexpr int NEXTRA = (NP * (W + BY) + kTPB - 1) / kTPB;
+    static_assert(RPP * PPP == BY - 1, "the regular passes cover all rows but the last");
+    // extra element x of lane tid: plane lp, row lj, column li (false: none)
+    __device__ static __forceinline__ bool extra(int tid, int x, int &lp, int &lj, int &li)
     {
-        if (e < NPASS) {
-            row = tid / W + RPP * e;
-            li = tid % W;
-            if (row >= NROWS) row = -1;
-        } else {
-            row = tid < NROWS ? tid : -1;
-            li = W;
+        const int idx = tid + kTPB * x;
+        if (idx < NP * W) {
+            lp = idx / W;
+            lj = BY - 1;
+            li = idx % W;
+            return true;
         }
-    }
-    // plane and row within the plane of a row index (row >= 0)
-    __device__ static __forceinline__ void split(int row, int &lp, int &lj)
-    {
-        lp = 0;
-#pragma unroll
-        for (int k = 1; k < NP; ++k) lp += row >= k * BY ? 1 : 0;
-        lj = row - lp * BY;
+        const int k = idx - NP * W;
+        lp = k / BY;
+        lj = k - lp * BY;
+        li = W;
+        return k < NP * BY;
     }
 };
 
@@ -491,66 +491,85 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
     }
 
     // ---------------- perimeter nodes ----------------
+    // One side of the column per wave (x = 0, x = P*kTX, y = 0, y = P*kTY; the
+    // y sides without the corners), so that each wave runs one straight-line
+    // variant; a side's (position, plane) items are dealt out over the lanes.
+    // Along a side, a node at index a lies in the cell below it, (a-1)/P, unless
+    // a = 0, and in the cell above it, a/P, when a is a multiple of P; the two
+    // are added in that order (cells by y, then x).
     const double *pc_prev = sPC + ((cz & 1) ^ 1) * NPER;
     double *pc_cur = sPC + (cz & 1) * NPER;
     const FaceMap fm = face_map_of(q);
-    for (int it = tid; it < NPER * N; it += kTPB) {
-        const int az = it / NPER, pos = it - az * NPER;
-        int li, lj;
-        if (pos < BY) { li = 0; lj = pos; }
-        else if (pos < 2 * BY) { li = P * kTX; lj = pos - BY; }
-        else if (pos < 2 * BY + BX - 2) { lj = 0; li = pos - 2 * BY + 1; }
-        else { lj = P * kTY; li = pos - 2 * BY - (BX - 2) + 1; }
-        const int gi = i0 + li, gj = j0 + lj, gk = k0 + az;
-        if (gi >= NX || gj >= NY) continue;
-        double f = (az == 0 && !first) ? pc_prev[pos] : 0.0;
-        // containing cells of the column: x cells cxa..cxb, y cells cya..cyb
-        const int cxa = li % P == 0 ? max(li / P - 1, 0) : li / P, cxb = min(li / P, kTX - 1);
-        const int cya = lj % P == 0 ? max(lj / P - 1, 0) : lj / P, cyb = min(lj / P, kTY - 1);
-        for (int cyl = cya; cyl <= cyb; ++cyl) {
-            if (kTY * ty + cyl >= q.ny) break;
-            for (int cxl = cxa; cxl <= cxb; ++cxl) {
-                if (kTX * tx + cxl >= q.nx) break;
-                const int ax = li - P * cxl, ay = lj - P * cyl, t = cxl + kTX * cyl;
-                double v;
-                if (ax == 0) v = sS[(az * N + ay) * kTPB + t];
-                else if (ay == 0) v = sS[(N * N + az * P + ax - 1) * kTPB + t];
-                else if (ax == P && cxl == kTX - 1) v = sE[(az * P + ay - 1) * kTY + cyl];
-                else v = sE[P * N * kTY + (az * P + ax - 1) * kTX + cxl];
-                f += v;
+    constexpr int NWAVE = kTPB / 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid) >> 6, lane = tid & 63;
+    sfor<0, 4>([&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        if (S % NWAVE != wave) return;  // uniform
+        constexpr bool XS = S < 2;       // nodes along y at fixed x
+        constexpr int NPOS = XS ? BY : BX - 2;
+        constexpr int POS0 = S == 0 ? 0 : (S == 1 ? BY : (S == 2 ? 2 * BY : 2 * BY + BX - 2));
+        // contribution of cell c along the side, at index a (0..P) along the side
+        auto part = [&](int az, int c, int a) -> double {
+            if constexpr (S == 0) return sS[(az * N + a) * kTPB + kTX * c];
+            else if constexpr (S == 1)
+                return a == 0 ? sS[(N * N + az * P + P - 1) * kTPB + kTX - 1 + kTX * c]
+                              : sE[(az * P + a - 1) * kTY + c];
+            else if constexpr (S == 2)
+                return a == 0 ? sS[(az * N) * kTPB + c] : sS[(N * N + az * P + a - 1) * kTPB + c];
+            else
+                return a == 0 ? sS[(az * N + P) * kTPB + kTX * (kTY - 1) + c]
+                              : sE[P * N * kTY + (az * P + a - 1) * kTX + c];
+        };
+        for (int it = lane; it < NPOS * N; it += 64) {
+            const int az = it / NPOS, pp = it - az * NPOS;
+            const int li = S == 0 ? 0 : (S == 1 ? P * kTX : pp + 1);
+            const int lj = S == 2 ? 0 : (S == 3 ? P * kTY : pp);
+            const int gi = i0 + li, gj = j0 + lj, gk = k0 + az;
+            if (gi >= NX || gj >= NY) continue;
+            const int pos = POS0 + pp;
+            const int al = XS ? lj : li;  // index along the side
+            double f = (az == 0 && !first) ? pc_prev[pos] : 0.0;
+            if (al >= 1) {  // the cell below exists whenever the node does
+                const int c = (al - 1) / P;
+                f += part(az, c, al - P * c);
+            }
+            if (al % P == 0) {
+                const int c = al / P;
+                const bool ok = XS ? (c < kTY && kTY * ty + c < q.ny) : (kTX * tx + c < q.nx);
+                if (ok) f += part(az, c, 0);
+            }
+            if (az == P && !last) {
+                pc_cur[pos] = f;
+                continue;
+            }
+            const bool fx = is_face(gi, P * kTX, NX), fy = is_face(gj, P * kTY, NY);
+            const bool fz = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1);
+            const bool face = fx || fy || fz;
+            const long long g = (long long)gi + (long long)NX * gj + (long long)NX * NY * gk;
+            const long long t = face_slot(gi, gj, gk, az == 0 ? seg - 1 : seg, P * kTX, P * kTY, NX, NY, NZ, fm);
+            if constexpr (MODE == 2) {
+                if (face) slots[t] = f;
+                else q.fout[g] = f;
+                continue;
+            }
+            const double T = sT[slot_r[az] + lj * BX + li];
+            const double C = node_capacity(L, T, gi, gj, gk, P, NX, NY, NZ, q.hx, q.hy, q.hz);
+            if constexpr (MODE == 0) {
+                const bool dir = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ);
+                const double inc = (q.dt * f) * rcp_nr(C);
+                const bool later = (li == 0 && fx) || (lj == 0 && fy) || (az == 0 && first && gk > 0);
+                const double val = dir ? ((face && later) ? 0.0 : q.T_D) : ((face && later) ? inc : T + inc);
+                if (face) slots[t] = val;
+                else q.Tout[g] = val;
+            } else {
+                if (face) slots[t] = f;
+                else {
+                    q.fout[g] = f;
+                    q.Cout[g] = C;
+                }
             }
         }
-        if (az == P && !last) {
-            pc_cur[pos] = f;
-            continue;
-        }
-        const bool fx = is_face(gi, P * kTX, NX), fy = is_face(gj, P * kTY, NY);
-        const bool fz = (az == 0 && first && gk > 0) || (az == P && last && gk < NZ - 1);
-        const bool face = fx || fy || fz;
-        const long long g = (long long)gi + (long long)NX * gj + (long long)NX * NY * gk;
-        const long long t = face_slot(gi, gj, gk, az == 0 ? seg - 1 : seg, P * kTX, P * kTY, NX, NY, NZ, fm);
-        if constexpr (MODE == 2) {
-            if (face) slots[t] = f;
-            else q.fout[g] = f;
-            continue;
-        }
-        const double T = sT[slot_r[az] + lj * BX + li];
-        const double C = node_capacity(L, T, gi, gj, gk, P, NX, NY, NZ, q.hx, q.hy, q.hz);
-        if constexpr (MODE == 0) {
-            const bool dir = on_dirichlet(dmask, gi, gj, gk, NX, NY, NZ);
-            const double inc = (q.dt * f) * rcp_nr(C);
-            const bool later = (li == 0 && fx) || (lj == 0 && fy) || (az == 0 && first && gk > 0);
-            const double val = dir ? ((face && later) ? 0.0 : q.T_D) : ((face && later) ? inc : T + inc);
-            if (face) slots[t] = val;
-            else q.Tout[g] = val;
-        } else {
-            if (face) slots[t] = f;
-            else {
-                q.fout[g] = f;
-                q.Cout[g] = C;
-            }
-        }
-    }
+    });
 }
 
 // MODE 0: explicit step (fused update into Tout); MODE 1: assemble f and C~;
@@ -611,24 +630,34 @@ k_cells(const CellParams<R> p)
         using PR = PlaneRows<P, kTY, N>;
         const double *src = p.Tin + ((long long)i0 + (long long)p.NX * j0 + NXY * (P * z0));
         const int nxl = p.NX - i0, nyl = p.NY - j0;
-        double val[PR::NE];
+        const int rl = threadIdx.x / PR::W, cl = threadIdx.x % PR::W;
+        const unsigned goff = unsigned(rl) * unsigned(p.NX) + unsigned(cl);
+        double val[PR::NREG], vx[PR::NEXTRA];
 #pragma unroll
-        for (int e = 0; e < PR::NE; ++e) {
-            int row, li;
-            PR::at(threadIdx.x, e, row, li);
-            int lp, lj;
-            PR::split(row, lp, lj);
+        for (int e = 0; e < PR::NREG; ++e) {
+            const int lp = e / PR::PPP, dr = PR::RPP * (e % PR::PPP);
             val[e] = 0.0;
-            if (row >= 0 && li < nxl && lj < nyl)
-                val[e] = src[unsigned(lp) * unsigned(NXY) + unsigned(lj) * unsigned(p.NX) + unsigned(li)];
+            if (cl < nxl && rl + dr < nyl)
+                val[e] = src[goff + unsigned(lp) * unsigned(NXY) + unsigned(dr) * unsigned(p.NX)];
         }
 #pragma unroll
-        for (int e = 0; e < PR::NE; ++e) {
-            int row, li;
-            PR::at(threadIdx.x, e, row, li);
-            int lp, lj;
-            PR::split(row, lp, lj);
-            if (row >= 0) sT[((P * z0 + lp) % N) * PLANE + lj * BX + li] = val[e];
+        for (int x = 0; x < PR::NEXTRA; ++x) {
+            int lp, lj, li;
+            const bool ok = PR::extra(threadIdx.x, x, lp, lj, li);
+            vx[x] = 0.0;
+            if (ok && li < nxl && lj < nyl)
+                vx[x] = src[unsigned(lp) * unsigned(NXY) + unsigned(lj) * unsigned(p.NX) + unsigned(li)];
+        }
+        const int loff = rl * BX + cl;
+#pragma unroll
+        for (int e = 0; e < PR::NREG; ++e) {
+            const int lp = e / PR::PPP, dr = PR::RPP * (e % PR::PPP);
+            sT[((P * z0 + lp) % N) * PLANE + loff + dr * BX] = val[e];
+        }
+#pragma unroll
+        for (int x = 0; x < PR::NEXTRA; ++x) {
+            int lp, lj, li;
+            if (PR::extra(threadIdx.x, x, lp, lj, li)) sT[((P * z0 + lp) % N) * PLANE + lj * BX + li] = vx[x];
         }
     }
     __syncthreads();
@@ -684,19 +713,26 @@ k_cells(const CellParams<R> p)
         // 2. loads of the next layer's new planes (global planes k0+N .. k0+N+P-1)
         using PR = PlaneRows<P, kTY, P>;
         const bool more = cz + 1 < z1;
-        double pf[PR::NE];
+        const int rl = tid / PR::W, cl = tid % PR::W;
+        double pf[PR::NREG], pfx[PR::NEXTRA];
         if (more) {
             const double *src = q.Tin + ((long long)i0 + (long long)q.NX * j0 + NXY * (k0 + N));
             const int nxl = q.NX - i0, nyl = q.NY - j0;
+            const unsigned goff = unsigned(rl) * unsigned(q.NX) + unsigned(cl);
 #pragma unroll
-            for (int e = 0; e < PR::NE; ++e) {
-                int row, li;
-                PR::at(tid, e, row, li);
-                int lp, lj;
-                PR::split(row, lp, lj);
+            for (int e = 0; e < PR::NREG; ++e) {
+                const int lp = e / PR::PPP, dr = PR::RPP * (e % PR::PPP);
                 pf[e] = 0.0;
-                if (row >= 0 && li < nxl && lj < nyl)
-                    pf[e] = src[unsigned(lp) * unsigned(NXY) + unsigned(lj) * unsigned(q.NX) + unsigned(li)];
+                if (cl < nxl && rl + dr < nyl)
+                    pf[e] = src[goff + unsigned(lp) * unsigned(NXY) + unsigned(dr) * unsigned(q.NX)];
+            }
+#pragma unroll
+            for (int x = 0; x < PR::NEXTRA; ++x) {
+                int lp, lj, li;
+                const bool ok = PR::extra(tid, x, lp, lj, li);
+                pfx[x] = 0.0;
+                if (ok && li < nxl && lj < nyl)
+                    pfx[x] = src[unsigned(lp) * unsigned(NXY) + unsigned(lj) * unsigned(q.NX) + unsigned(li)];
             }
         }
         // 3. node completion: interior nodes per lane, perimeter spread over the lanes
@@ -705,14 +741,20 @@ k_cells(const CellParams<R> p)
         __syncthreads();
         // 4. the new planes replace planes k0 .. k0+P-1 (slots r0 .. r0+P-1 mod N)
         if (more) {
+            const int loff = rl * BX + cl;
 #pragma unroll
-            for (int e = 0; e < PR::NE; ++e) {
-                int row, li;
-                PR::at(tid, e, row, li);
-                int lp, lj;
-                PR::split(row, lp, lj);
+            for (int e = 0; e < PR::NREG; ++e) {
+                const int lp = e / PR::PPP, dr = PR::RPP * (e % PR::PPP);
                 const int sl = r0 + lp < N ? r0 + lp : r0 + lp - N;
-                if (row >= 0) sT[sl * PLANE + lj * BX + li] = pf[e];
+                sT[sl * PLANE + loff + dr * BX] = pf[e];
+            }
+#pragma unroll
+            for (int x = 0; x < PR::NEXTRA; ++x) {
+                int lp, lj, li;
+                if (PR::extra(tid, x, lp, lj, li)) {
+                    const int sl = r0 + lp < N ? r0 + lp : r0 + lp - N;
+                    sT[sl * PLANE + lj * BX + li] = pfx[x];
+                }
             }
             __syncthreads();
         }
