@@ -454,6 +454,9 @@ CellParams<R> cell_params(const pbf_ctx *c, const Law<R> *law, bool history)
     p.ih2x = R(1.0 / (p.hx * p.hx));
     p.ih2y = R(1.0 / (p.hy * p.hy));
     p.ih2z = R(1.0 / (p.hz * p.hz));
+    p.ihx = 1.0 / p.hx;
+    p.ihy = 1.0 / p.hy;
+    p.ihz = 1.0 / p.hz;
     p.T_D = c->T_D;
     p.Tref = std::is_same<R, double>::value ? 0.0 : c->Tref;
     p.dmask = c->dmask;
@@ -601,6 +604,7 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const dou
         pd.Cout = C;
         pd.hist = rc;
         pd.dt = dt;
+        pd.dtr = dt / (linear ? c->h_lin64.rho : c->h_law64.rho);
         pd.hist_write = hist_write ? 1 : 0;
         if (!linear && law != LAW_SURFACE) set_beam(c, pd, t);
         pd.re = surface_params(c, law);
@@ -612,6 +616,7 @@ pbf_status operator_pass(pbf_ctx *c, int mode, int precision, int law, const dou
         pf.Cout = C;
         pf.hist = rc;
         pf.dt = dt;
+        pf.dtr = dt / c->h_law64.rho;
         pf.hist_write = hist_write ? 1 : 0;
         set_beam(c, pf, t);
         pf.re = surface_params(c, law);

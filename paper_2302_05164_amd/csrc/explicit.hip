@@ -369,8 +369,7 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
     const int NX = q.NX, NY = q.NY, NZ = q.NZ;
     const int i0 = P * kTX * tx, j0 = P * kTY * ty, k0 = P * cz;
     const unsigned dmask = q.dmask;
-    const double dtr = q.dt / L.rho;
-    const double ihx = 1.0 / q.hx, ihy = 1.0 / q.hy, ihz = 1.0 / q.hz;  // uniform
+    const double dtr = q.dtr, ihx = q.ihx, ihy = q.ihy, ihz = q.ihz;  // dt / rho, 1/h (uniform)
     int slot_r[N];  // node plane az of the layer (rotating slots)
 #pragma unroll
     for (int az = 0; az < N; ++az) slot_r[az] = (r0 + az < N ? r0 + az : r0 + az - N) * PLANE;
@@ -396,6 +395,16 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
         }
         const double c0 = L.c0, Ts = L.Ts, Tl = L.Tl, lat = L.lat;
         // base of the layer's nodes (uniform) and the lane's 32-bit offset
+        // dt / rho times the inverse lumped masses in x and y of the lane's nodes
+        double sxy[P * P];
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int ay = 1; ay < N; ++ay)
+#pragma unroll
+                for (int ax = 1; ax < N; ++ax)
+                    sxy[(ay - 1) * P + ax - 1] = dtr * inv_mass_1d<P>(P == 2 && ax == 1, ax == P && bx, ihx) *
+                                                 inv_mass_1d<P>(P == 2 && ay == 1, ay == P && by, ihy);
+        }
         double *const out = MODE == 0 ? q.Tout : q.fout;
         const long long base = (long long)i0 + (long long)NX * j0 + (long long)NX * NY * k0;
         const unsigned NXY = unsigned(NX) * unsigned(NY);
@@ -465,9 +474,7 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
                     const double T = sTl[slot_r[az] + ay * BX + ax];
                     const double c = cpl[(ay - 1) * P + ax - 1];
                     if constexpr (MODE == 0) {
-                        const double ixm = inv_mass_1d<P>(P == 2 && ax == 1, ax == P && bx, ihx);
-                        const double iym = inv_mass_1d<P>(P == 2 && ay == 1, ay == P && by, ihy);
-                        const double inc = f * (dtr * ixm * iym * iz) * rcp_nr(c);
+                        const double inc = f * (sxy[(ay - 1) * P + ax - 1] * iz) * rcp_nr(c);
                         if (zface) {
                             const double val = dir ? (zlater ? 0.0 : q.T_D) : (zlater ? inc : T + inc);
                             slots[q.fm.GX + q.fm.GY + ((long long)zf * NY + j0 + P * ly + ay) * NX + i0 + P * lx + ax] = val;
@@ -491,12 +498,15 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
     }
 
     // ---------------- perimeter nodes ----------------
-    // One side of the column per wave (x = 0, x = P*kTX, y = 0, y = P*kTY; the
-    // y sides without the corners), so that each wave runs one straight-line
-    // variant; a side's (position, plane) items are dealt out over the lanes.
+    // One side of the column per wave, each side with one corner: x = 0
+    // (y index 0 .. P*kTY-1), x = P*kTX (y index 1 .. P*kTY), y = 0 (x index
+    // 1 .. P*kTX), y = P*kTY (x index 0 .. P*kTX-1), so that each wave runs one
+    // straight-line variant over as many positions as it has lanes (Q2, 16x16
+    // cells: 32 positions x 2 planes, plus the top plane on half the lanes).
     // Along a side, a node at index a lies in the cell below it, (a-1)/P, unless
-    // a = 0, and in the cell above it, a/P, when a is a multiple of P; the two
-    // are added in that order (cells by y, then x).
+    // a = 0, and in the cell above it, a/P, when a is a multiple of P and that
+    // cell belongs to the column; the two are added in that order (cells by y,
+    // then x).
     const double *pc_prev = sPC + ((cz & 1) ^ 1) * NPER;
     double *pc_cur = sPC + (cz & 1) * NPER;
     const FaceMap fm = face_map_of(q);
@@ -506,8 +516,8 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
         constexpr int S = decltype(sc)::value;
         if (S % NWAVE != wave) return;  // uniform
         constexpr bool XS = S < 2;       // nodes along y at fixed x
-        constexpr int NPOS = XS ? BY : BX - 2;
-        constexpr int POS0 = S == 0 ? 0 : (S == 1 ? BY : (S == 2 ? 2 * BY : 2 * BY + BX - 2));
+        constexpr int NPOS = XS ? P * kTY : P * kTX;
+        constexpr int POS0 = S == 0 ? 0 : (S == 1 ? P * kTY : (S == 2 ? 2 * P * kTY : 2 * P * kTY + P * kTX));
         // contribution of cell c along the side, at index a (0..P) along the side
         auto part = [&](int az, int c, int a) -> double {
             if constexpr (S == 0) return sS[(az * N + a) * kTPB + kTX * c];
@@ -522,8 +532,8 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
         };
         for (int it = lane; it < NPOS * N; it += 64) {
             const int az = it / NPOS, pp = it - az * NPOS;
-            const int li = S == 0 ? 0 : (S == 1 ? P * kTX : pp + 1);
-            const int lj = S == 2 ? 0 : (S == 3 ? P * kTY : pp);
+            const int li = S == 0 ? 0 : (S == 1 ? P * kTX : (S == 2 ? pp + 1 : pp));
+            const int lj = S == 0 ? pp : (S == 1 ? pp + 1 : (S == 2 ? 0 : P * kTY));
             const int gi = i0 + li, gj = j0 + lj, gk = k0 + az;
             if (gi >= NX || gj >= NY) continue;
             const int pos = POS0 + pp;
@@ -535,7 +545,7 @@ __device__ __forceinline__ void complete_layer(Q &q, const R *fe, const double *
             }
             if (al % P == 0) {
                 const int c = al / P;
-                const bool ok = XS ? (c < kTY && kTY * ty + c < q.ny) : (kTX * tx + c < q.nx);
+                const bool ok = XS ? (c < kTY && kTY * ty + c < q.ny) : (c < kTX && kTX * tx + c < q.nx);
                 if (ok) f += part(az, c, 0);
             }
             if (az == P && !last) {

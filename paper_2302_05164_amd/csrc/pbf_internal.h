@@ -140,6 +140,7 @@ struct CellParams {
     double hx, hy, hz, Lz;
     R detJ, ih2x, ih2y, ih2z;  // h^-2 per direction
     double dt, T_D, Tref;
+    double ihx, ihy, ihz, dtr;  // 1/h per direction; dt / rho of the nodal law (explicit mode)
     unsigned dmask;
     int laser_on, laser_kind, src_cz0;
     double xb, yb, src_amp, two_over_R2, h_powder;
