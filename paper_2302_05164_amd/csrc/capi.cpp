@@ -454,6 +454,7 @@ CellParams<R> cell_params(const pbf_ctx *c, const Law<R> *law, bool history)
     p.ih2x = R(1.0 / (p.hx * p.hx));
     p.ih2y = R(1.0 / (p.hy * p.hy));
     p.ih2z = R(1.0 / (p.hz * p.hz));
+    p.iso = p.ih2x == p.ih2y && p.ih2y == p.ih2z;
     p.ihx = 1.0 / p.hx;
     p.ihy = 1.0 / p.hy;
     p.ihz = 1.0 / p.hz;

@@ -46,7 +46,7 @@ constexpr double kSourceCut = 56.0;
 // collocation-space integrand w.  FAST: at most one hinge of the law active, no
 // source and no history update in the wave (uniform branch-free straight-line
 // code); FHIST: the FAST cell reads its (unchanged) consolidated fraction.
-template <int P, typename R, bool FAST, bool FHIST = false, typename PP, typename L>
+template <int P, typename R, bool FAST, bool FHIST = false, bool ISO = false, typename PP, typename L>
 __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int nhinge, bool melt,
                                             bool has_hist, long long hc, bool src_cell, int cx, int cy,
                                             int cz)
@@ -57,6 +57,7 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
     const R b0 = law.b[0];
     const R dk0 = nhinge > 0 ? R(law.dk[0]) : R(0);
     const R detJ = p.detJ, ih2x = p.ih2x, ih2y = p.ih2y, ih2z = p.ih2z;
+    const R ndih = ISO ? -(detJ * ih2x) : R(0);
     // General cells: the hinge sums of all points first, one hinge at a time
     // (each coefficient is read once per cell; every point still adds its
     // hinges in increasing order), and the Gaussian source once per (x, y)
@@ -129,9 +130,20 @@ __device__ __forceinline__ void flux_points(PP &p, L &law, const R *v, R *w, int
             }
         }
         constexpr double wq = TB::gw(qx) * TB::gw(qy) * TB::gw(qz);
-        const R kW = k * (R(wq) * detJ);
-        // flux -k W J^{-1} J^{-T} grad T, collocation transpose
-        const R Fx = -kW * ih2x * gx, Fy = -kW * ih2y * gy, Fz = -kW * ih2z * gz;
+        // flux -k W J^{-1} J^{-T} grad T, collocation transpose (ISO: equal
+        // spacing in x, y and z, one common factor -W detJ / h^2 per point)
+        R Fx, Fy, Fz;
+        if constexpr (ISO) {
+            const R kWi = k * (R(wq) * ndih);
+            Fx = kWi * gx;
+            Fy = kWi * gy;
+            Fz = kWi * gz;
+        } else {
+            const R kW = k * (R(wq) * detJ);
+            Fx = -kW * ih2x * gx;
+            Fy = -kW * ih2y * gy;
+            Fz = -kW * ih2z * gz;
+        }
         sfor<0, N>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
             constexpr double dx = TB::D(qx, r), dy = TB::D(qy, r), dz = TB::D(qz, r);
@@ -244,7 +256,10 @@ __device__ __forceinline__ void cell_operator(PP &p, const Law<R> *lawp, const R
         if (has_hist)
             flux_points<P, R, true, true>(p, law, v, w, nhinge, false, true, hc, false, cx, cy, cz);
         else
-            flux_points<P, R, true>(p, law, v, w, nhinge, false, false, 0, false, cx, cy, cz);
+            if (p.iso)
+                flux_points<P, R, true, false, true>(p, law, v, w, nhinge, false, false, 0, false, cx, cy, cz);
+            else
+                flux_points<P, R, true>(p, law, v, w, nhinge, false, false, 0, false, cx, cy, cz);
     } else
         flux_points<P, R, false>(p, law, v, w, nhinge, melt, has_hist, hc, src_cell, cx, cy, cz);
 

@@ -139,6 +139,7 @@ struct CellParams {
     int hist_write;  // 0: the updated consolidated fraction is used but not stored
     double hx, hy, hz, Lz;
     R detJ, ih2x, ih2y, ih2z;  // h^-2 per direction
+    int iso;                   // ih2x == ih2y == ih2z
     double dt, T_D, Tref;
     double ihx, ihy, ihz, dtr;  // 1/h per direction; dt / rho of the nodal law (explicit mode)
     unsigned dmask;
