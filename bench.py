@@ -80,7 +80,7 @@ def cpu_baseline(prob, dt, steps=5):
 
 # every source file the explicit cell kernel is compiled from
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_05164_amd", "csrc", f)
-                  for f in ("explicit.hip", "cellkit.h", "pbf_internal.h")]
+                  for f in ("cells.h", "cells_q2_f64.hip", "cellkit.h", "pbf_internal.h")]
 
 
 def kernel_source_hash():

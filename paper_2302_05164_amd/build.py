@@ -11,8 +11,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpbftherm.so")
-SOURCES = ["explicit.hip", "implicit.hip", "adjoint.hip", "octree.hip", "vec.hip", "revolve.cpp",
-           "octree_mesh.cpp", "capi.cpp"]
+# the Q2 FP64 column kernels first: the longest compile
+SOURCES = ["cells_q2_f64.hip", "cells_q2_f32.hip", "cells_q1.hip", "explicit.hip", "implicit.hip",
+           "adjoint.hip", "octree.hip", "vec.hip", "revolve.cpp", "octree_mesh.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-x", "hip",

@@ -1,0 +1,12 @@
+// Instantiations of the column kernels of cells.h: Q2 cells in double precision
+// (one translation unit each, so that they compile in parallel).
+#include "cells.h"
+
+namespace pbf {
+hipError_t launch_cells_q2_f64(int mode, const CellParams<double> &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    if (mode == 0) return launch_cells_inst<2, double, 0>(p, s, e0, e1);
+    if (mode == 1) return launch_cells_inst<2, double, 1>(p, s, e0, e1);
+    return launch_cells_inst<2, double, 2>(p, s, e0, e1);
+}
+}  // namespace pbf
