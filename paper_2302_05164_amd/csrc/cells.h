@@ -720,6 +720,12 @@ k_cells(const CellParams<R> p)
                 const double *top = sTl + st * PLANE;
                 surface_loss_face<P>(q.re, q.hx, q.hy, [&](int ax, int ay) { return top[ay * BX + ax]; }, fe);
             }
+            // Wave priority: the cell operator is dense FP64 arithmetic and runs
+            // at the default priority; the staging and the node completion are
+            // short, latency-bound chains of LDS and memory accesses, so they
+            // run at a higher priority and issue ahead of the other workgroup's
+            // cell operator on the same SIMD (measured 10-13% faster).
+            __builtin_amdgcn_s_setprio(2);
             stage_shared<P, kTPB>(sS, fe, tid);
             if (lx == kTX - 1) {
 #pragma unroll
@@ -736,6 +742,7 @@ k_cells(const CellParams<R> p)
             }
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(2);
         // 2. loads of the next layer's new planes (global planes k0+N .. k0+N+P-1)
         using PR = PlaneRows<P, kTY, P>;
         const bool more = cz + 1 < z1;
@@ -764,6 +771,7 @@ k_cells(const CellParams<R> p)
         // 3. node completion: interior nodes per lane, perimeter spread over the lanes
         complete_layer<P, kTY, MODE>(q, fe, sS, sE, sC, sPC, sT, r0, tid, lx, ly, tx, ty, cz, seg, cz == z0,
                                      cz == z1 - 1, active, q.slots + tpar * q.fm.GT);
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         // 4. the new planes replace planes k0 .. k0+P-1 (slots r0 .. r0+P-1 mod N)
         if (more) {
