@@ -389,9 +389,14 @@ k_picard_capply(const PicardParams p)
                 });
             }
             integrate3<TagSt<P>, TagSt<P>, TagSt<P>, N>(m, fe);
+            // staging and node completion at a raised wave priority (short,
+            // latency-bound LDS and memory chains; they issue ahead of the
+            // other workgroup's cell arithmetic on the same SIMD)
+            __builtin_amdgcn_s_setprio(2);
             stage_shared<P, kTPB>(sS, fe, tid);
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(2);
         if (active) {
             owner_nodes<P, kTY>(fe, sS, sC, tid, lx, ly, cx, cy, q.nx, q.ny, k0, seg, cz == z0, cz == z1 - 1,
                                 q.NX, q.NY, q.NZ, q.slots + tpar * q.fm.GT, face_map_of(q), NXY,
@@ -399,6 +404,7 @@ k_picard_capply(const PicardParams p)
                 q.yout[g] = on_dirichlet(q.dmask, gi, gj, gk, q.NX, q.NY, q.NZ) ? 0.0 : f;
             });
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
 }
