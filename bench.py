@@ -445,7 +445,7 @@ def main():
         sq_summary(args.sq_summary[:-1], args.sq_summary[-1], workload=args.workload)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only (the library has no multi-GPU path); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
