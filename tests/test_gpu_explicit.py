@@ -58,6 +58,23 @@ def test_q2_nonlinear_run(dims):
     assert np.abs(rg - ro).max() <= 1e-9
 
 
+@pytest.mark.parametrize("degree", [1, 2])
+def test_anisotropic_spacing_run(degree):
+    """Unequal cell sizes in x, y and z (the cell kernel then forms the three
+    flux factors separately instead of one common factor per point)."""
+    need_gpu()
+    nx, ny, nz = 21, 17, 9
+    base = W.small_nonlinear(nx=nx, ny=ny, nz=nz, steps=100, track_length=0.8 * nx * 31.25e-6)
+    prob = base.replace(degree=degree, L=(nx * 31.25e-6, ny * 26.0e-6, nz * 37.5e-6))
+    dt = oracle_dt(prob)
+    Tg, rg, To, ro, info = _run_pair(prob, prob.steps, dt)
+    mx, l2 = rel_errors(Tg, To)
+    print(f"Q{degree} anisotropic: dt={dt:.3e} max rel {mx:.2e} rel-L2 {l2:.2e} Tmax {To.max():.0f}")
+    assert To.max() > prob.T0 + 100.0
+    assert mx <= TOL64 and l2 <= TOL64
+    assert np.abs(rg - ro).max() <= 1e-9
+
+
 def test_q2_run_reaches_melting_and_history():
     """The small case must exercise every branch of the law: melting, latent heat,
     powder consolidation, several breakpoints."""
