@@ -959,7 +959,9 @@ size_t oct_tables(pbf_ctx *c, char *base)
     d.cell_hist = (const int32_t *)take((size_t)m.n_cells * 4);
     d.nstart = (const int32_t *)take(m.nstart.size() * 4);
     d.nslot = (const int32_t *)take(m.nslot.size() * 4);
-    d.nw = (const double *)take(m.nw.size() * 8);
+    d.nw = m.nw_f32 ? nullptr : (const double *)take(m.nw.size() * 8);
+    d.nwf = m.nw_f32 ? (const float *)take(m.nwf.size() * 4) : nullptr;
+    d.nw_f32 = m.nw_f32 ? 1 : 0;
     d.mass = (const double *)take(m.mass.size() * 8);
     d.dflag = (const unsigned char *)take((size_t)m.n_dofs);
     d.hist_z = (const double *)take(std::max<size_t>(m.hist_z.size(), 2) * 8);
@@ -999,7 +1001,8 @@ pbf_status oct_upload(pbf_ctx *c, hipStream_t s, bool all)
     PBF_HIP(c, put(d.cell_hist, m.cell_hist.data(), m.cell_hist.size() * 4));
     PBF_HIP(c, put(d.nstart, m.nstart.data(), m.nstart.size() * 4));
     PBF_HIP(c, put(d.nslot, m.nslot.data(), m.nslot.size() * 4));
-    PBF_HIP(c, put(d.nw, m.nw.data(), m.nw.size() * 8));
+    if (m.nw_f32) PBF_HIP(c, put(d.nwf, m.nwf.data(), m.nwf.size() * 4));
+    else PBF_HIP(c, put(d.nw, m.nw.data(), m.nw.size() * 8));
     PBF_HIP(c, put(d.mass, m.mass.data(), m.mass.size() * 8));
     PBF_HIP(c, put(d.dflag, m.dflag.data(), m.dflag.size()));
     PBF_HIP(c, put(d.hist_z, m.hist_z.data(), m.hist_z.size() * 8));

@@ -317,22 +317,27 @@ __global__ void __launch_bounds__(256) k_oct_nodes(const OctNodeParams p)
     const bool dir = p.m.dflag[i] != 0;
     const double T = MODE <= 1 ? p.Tin[i] : 0.0;
     const int e1 = p.m.nstart[i + 1];
-    int e = p.m.nstart[i];
-    double f = 0.0;
-    for (; e + 4 <= e1; e += 4) {
-        double w[4], v[4];
+    // weights in FP32 when the mesh's weights are exact there (uniform), else FP64
+    auto gather = [&](auto wts) -> double {
+        int e = p.m.nstart[i];
+        double f = 0.0;
+        for (; e + 4 <= e1; e += 4) {
+            double w[4], v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            w[j] = p.m.nw[e + j];
-            v[j] = p.m.E[p.m.nslot[e + j]];
+            for (int j = 0; j < 4; ++j) {
+                w[j] = double(wts[e + j]);
+                v[j] = p.m.E[p.m.nslot[e + j]];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) f = __builtin_fma(MODE == 3 ? w[j] * w[j] : w[j], v[j], f);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) f = __builtin_fma(MODE == 3 ? w[j] * w[j] : w[j], v[j], f);
-    }
-    for (; e < e1; ++e) {
-        const double w = p.m.nw[e];
-        f = __builtin_fma(MODE == 3 ? w * w : w, p.m.E[p.m.nslot[e]], f);
-    }
+        for (; e < e1; ++e) {
+            const double w = double(wts[e]);
+            f = __builtin_fma(MODE == 3 ? w * w : w, p.m.E[p.m.nslot[e]], f);
+        }
+        return f;
+    };
+    const double f = p.m.nw_f32 ? gather(p.m.nwf) : gather(p.m.nw);
     if constexpr (MODE <= 1) {
         ConstLaw<double> &L = const_law(p.nlaw);
         const double C = L.rho * law_c(L, T) * p.m.mass[i];

@@ -410,6 +410,12 @@ bool oct_build(OctMesh &m, int P, int maxl, const int n0[3], const double L[3], 
                           m1[P - 1][a / (N1 * N1)] * s * m.unit[2];
         m.mass[d] += w * me;
     });
+    // the weights (constraint products of Lagrange values at dyadic points) are
+    // normally exact in FP32: then the node pass reads them in half the bytes
+    m.nw_f32 = true;
+    for (double w : m.nw) m.nw_f32 = m.nw_f32 && (double)(float)w == w;
+    m.nwf.clear();
+    if (m.nw_f32) m.nwf.assign(m.nw.begin(), m.nw.end());
     // dof coordinates and lattice keys
     m.dof_key.resize(3 * m.n_dofs);
     m.coords.resize(3 * m.n_dofs);

@@ -423,6 +423,8 @@ struct OctMesh {
     std::vector<double> hw;
     std::vector<int32_t> nstart, nslot;             // per dof: slots a * n_cells + cell
     std::vector<double> nw, mass, coords;
+    std::vector<float> nwf;                         // nw in FP32 when every weight is exact there
+    bool nw_f32 = false;
     std::vector<int64_t> dof_key;                   // lattice coordinates (step unit / P)
     std::vector<unsigned char> dflag;               // Dirichlet flags
     std::vector<int32_t> cell_hist;                 // history cell of each leaf or -1
@@ -446,9 +448,10 @@ int32_t oct_locate(const OctMesh &m, const double x_finest[3], double xi[3]);
 struct OctDev {
     const int32_t *cidx, *hstart, *hdof, *leaf, *cell_hist, *nstart, *nslot;
     const double *hw, *nw, *mass, *hist_z;
+    const float *nwf;  // the scatter weights in FP32 (nw_f32), else nw
     const unsigned char *dflag;
     double *E;  // NN x n_cells element vectors
-    int n_cells, n_dofs, n_hist_cells, maxl, top_iz;
+    int n_cells, n_dofs, n_hist_cells, maxl, top_iz, nw_f32;
     double ux, uy, uz, Lz;
 };
 // parameters of the octree cell passes
